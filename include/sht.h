@@ -1,0 +1,130 @@
+/*
+ * sht.h -- C ABI of the MI355X spin spherical-harmonic transform library.
+ *
+ * Implements the fast spin SHT of McEwen, "Fast, exact (but unstable) spin
+ * spherical harmonic transforms" (arXiv:0807.4494): separation of variables
+ * into a 2-D Fourier transform on the torus (Section 3.2, Eq. (sht_inv_fast))
+ * and an O(L^3) contraction with Wigner functions at pi/2 (Eq. (fourier_coeff)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * L        band-limit: degrees 0 <= l < L.  N = 2L - 1 samples per torus axis.
+ *          (The paper writes the largest degree as its band-limit, with
+ *          N = 2 L_paper + 1; L here is L_paper + 1.)  2 <= L <= SHT_L_MAX.
+ * spin     integer s with |s| < L.  Coefficients with l < |s| do not exist
+ *          (Section 2.3): they are ignored on input and written as 0.
+ * batch    number of maps per call, 1 <= batch <= SHT_BATCH_MAX.
+ * sampling SHT_SAMPLING_MW: the equiangular nodes of Eq. (nodes_theta) and
+ *          Eq. (nodes_phi), theta_t = pi (2t+1)/N for t = 0..L-1 (the ring
+ *          theta = pi is kept) and phi_p = pi (2p+1)/N for p = 0..N-1.
+ * precision
+ *          SHT_FP64   all arithmetic in FP64 (FP64 MFMA contraction).
+ *          SHT_FP32   Wigner recursion in FP64, contraction on FP32 MFMA with
+ *                     FP32 accumulation, FFT stages in FP32.
+ *          SHT_BF16X3 Wigner recursion in FP64, contraction as three BF16
+ *                     MFMA products (hi*hi + hi*lo + lo*hi) with FP32
+ *                     accumulation, FFT stages in FP32.
+ *
+ * Memory layouts (device memory, row-major, complex = interleaved re, im):
+ *   flm  [batch][L*L]        coefficient f_lm at index l*l + l + m.
+ *   map  [batch][L][N]       sample f(theta_t, phi_p) at [t][p].
+ *   Element type: complex double for SHT_FP64, complex float otherwise.
+ *   Pointers must be 16-byte aligned (SHT_ERR_ALIGNMENT otherwise).
+ *
+ * Ownership: the caller owns flm, map and workspace and keeps them alive
+ * until the stream reaches the call.  The library owns its plan cache (Wigner
+ * seed tables, chirp tables, FFT kernels; device memory per (device, L,
+ * precision) and per (device, L, spin)) until sht_release_all().
+ *
+ * Semantics: every transform call only enqueues work on `stream` (a
+ * hipStream_t; NULL = the legacy default stream) and returns.  The first call
+ * for a new (L, spin, precision) builds its plan, which allocates device
+ * memory and enqueues the plan kernels on the same stream.  Results are
+ * deterministic for a given (L, spin, batch, precision).  Calls may be made
+ * from several host threads; the plan cache is internally locked.
+ *
+ * Errors: 0 on success, a negative SHT_ERR_* code otherwise.  All argument
+ * checks run before any HIP call; a failed check enqueues nothing.  No C++
+ * exception crosses this interface.  sht_status_string() gives the text.
+ */
+#ifndef SHT_H
+#define SHT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHT_VERSION 10000          /* 1.0.0 */
+#define SHT_L_MAX 2048
+#define SHT_BATCH_MAX 64
+
+enum sht_status {
+    SHT_OK = 0,
+    SHT_ERR_INVALID_ARG = -1,   /* L, spin, batch out of range, NULL pointer */
+    SHT_ERR_UNSUPPORTED = -2,   /* unknown sampling or precision */
+    SHT_ERR_WORKSPACE = -3,     /* ws_bytes < sht_workspace_bytes(...) */
+    SHT_ERR_ALIGNMENT = -4,     /* flm, map or workspace not 16-byte aligned */
+    SHT_ERR_OOM = -5,           /* plan allocation failed */
+    SHT_ERR_HIP = -6            /* a HIP call or kernel launch failed */
+};
+
+enum sht_sampling { SHT_SAMPLING_MW = 0 };
+
+enum sht_precision { SHT_FP64 = 0, SHT_FP32 = 1, SHT_BF16X3 = 2 };
+
+/*
+ * Inverse transform, Eq. (ssht_inv): f(theta_t, phi_p) = sum_{l,m} f_lm sY_lm,
+ * with sY_lm = (-1)^s sqrt((2l+1)/4pi) d^l_{m,-s}(theta) e^{i m phi}
+ * (Eq. (ssh_wigner)), computed as the contraction Eq. (fourier_coeff) followed
+ * by the torus sum Eq. (sht_inv_fast) on the sampling nodes (Section 3.4.3).
+ *   flm        in:  [batch][L*L] complex
+ *   map        out: [batch][L][2L-1] complex
+ *   workspace  scratch of at least sht_workspace_bytes(...) bytes (device)
+ *   stream     hipStream_t to enqueue on
+ */
+int sht_inverse(int L, int spin, int batch, int sampling, int precision,
+                const void *flm, void *map, void *workspace, size_t ws_bytes,
+                void *stream);
+
+/*
+ * Forward transform, Eq. (ssht_fwd): f_lm = integral of f sY*_lm over the
+ * sphere.  Computed exactly for band-limited maps: phi DFT, per-order parity
+ * extension in theta (Section 3.2), theta DFT (Eq. (fourier_series)), the
+ * exact sin(theta) quadrature on the torus, and the contraction with the
+ * Wigner functions of the conjugated Eq. (shf_exp).
+ *   map        in:  [batch][L][2L-1] complex
+ *   flm        out: [batch][L*L] complex (entries with l < |spin| are 0)
+ */
+int sht_forward(int L, int spin, int batch, int sampling, int precision,
+                const void *map, void *flm, void *workspace, size_t ws_bytes,
+                void *stream);
+
+/* Workspace bytes needed by sht_inverse / sht_forward with these arguments
+ * (the same size serves both directions).  0 if the arguments are invalid. */
+size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precision);
+
+/* Build (or find) the plan for (L, spin, precision) on the current device,
+ * enqueueing its kernels on `stream`.  Optional: transforms build plans on
+ * first use.  Returns SHT_OK or an error code. */
+int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream);
+
+/* Free every cached plan on every device.  The caller must make sure no
+ * enqueued transform still uses them (e.g. synchronise first). */
+int sht_release_all(void);
+
+/* Static text for a status code (never NULL). */
+const char *sht_status_string(int status);
+
+/* SHT_VERSION of the built library. */
+int sht_version(void);
+
+/* Text of the last HIP error seen by the library in this thread ("" if none). */
+const char *sht_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHT_H */

@@ -1,0 +1,11 @@
+"""MI355X-native fast spin spherical-harmonic transform (McEwen, arXiv:0807.4494).
+
+The transform runs in hand-written HIP kernels for gfx950 behind the C ABI of
+``include/sht.h`` (``libsht.so``); this package is its thin Python binding.
+"""
+
+from .sht import (PRECISIONS, forward, inverse, io_dtype, plan_warmup, release_all, version,
+                  workspace_bytes)
+
+__all__ = ["PRECISIONS", "forward", "inverse", "io_dtype", "plan_warmup", "release_all", "version",
+           "workspace_bytes"]

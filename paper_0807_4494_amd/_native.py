@@ -1,0 +1,75 @@
+"""ctypes binding of libsht.so (the C ABI in include/sht.h).
+
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  Loading fails loudly if the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsht.so")
+
+SHT_OK = 0
+SHT_ERR_INVALID_ARG = -1
+SHT_ERR_UNSUPPORTED = -2
+SHT_ERR_WORKSPACE = -3
+SHT_ERR_ALIGNMENT = -4
+SHT_ERR_OOM = -5
+SHT_ERR_HIP = -6
+
+SHT_SAMPLING_MW = 0
+SHT_FP64, SHT_FP32, SHT_BF16X3 = 0, 1, 2
+
+#: every symbol include/sht.h declares
+EXPORTS = ("sht_inverse", "sht_forward", "sht_workspace_bytes", "sht_plan_warmup",
+           "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error")
+
+_lib = None
+
+
+class ShtError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        lib = load()
+        msg = lib.sht_status_string(code).decode()
+        if code == SHT_ERR_HIP:
+            msg += ": " + lib.sht_last_hip_error().decode()
+        super().__init__(f"{where} failed ({code}): {msg}")
+
+
+def load() -> ctypes.CDLL:
+    """Load libsht.so from the package directory (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_0807_4494_amd.build.build() "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    for name in ("sht_inverse", "sht_forward"):
+        f = getattr(lib, name)
+        f.argtypes = [i, i, i, i, i, vp, vp, vp, sz, vp]
+        f.restype = i
+    lib.sht_workspace_bytes.argtypes = [i, i, i, i, i]
+    lib.sht_workspace_bytes.restype = sz
+    lib.sht_plan_warmup.argtypes = [i, i, i, i, vp]
+    lib.sht_plan_warmup.restype = i
+    lib.sht_release_all.argtypes = []
+    lib.sht_release_all.restype = i
+    lib.sht_status_string.argtypes = [i]
+    lib.sht_status_string.restype = ctypes.c_char_p
+    lib.sht_version.argtypes = []
+    lib.sht_version.restype = i
+    lib.sht_last_hip_error.argtypes = []
+    lib.sht_last_hip_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(code: int, where: str) -> None:
+    if code != SHT_OK:
+        raise ShtError(code, where)

@@ -1,0 +1,287 @@
+// C ABI of libsht (declared in include/sht.h): argument checks, the plan
+// cache and the launch sequences of the inverse and forward transforms.
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "sht_internal.h"
+
+using namespace sht;
+
+namespace {
+
+thread_local char g_last_hip_error[256] = "";
+
+int hip_fail(hipError_t e, const char *where) {
+    std::snprintf(g_last_hip_error, sizeof(g_last_hip_error), "%s: %s", where, hipGetErrorString(e));
+    return SHT_ERR_HIP;
+}
+
+#define SHT_HIP(call, where)                          \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+struct DeviceState {
+    EdgeTable E;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceState> g_devices;
+std::map<std::tuple<int, int>, Plan *> g_plans;              // (device, L)
+std::map<std::tuple<int, int, int>, SpinPlan *> g_spin;      // (device, L, spin)
+
+int fft_size(int L) {
+    int need = 4 * L - 3;
+    if (need < 8) need = 8;
+    return next_pow2(need);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t elem_bytes(int precision) { return precision == SHT_FP64 ? 8 : 4; }
+
+// Workspace: two regions. A holds the layout panels / phi-stage output, B the
+// contraction input or output; see the launch sequences below.
+void regions(int L, int batch, int precision, size_t &ra, size_t &rb) {
+    const size_t T = elem_bytes(precision);
+    const size_t C = 4 * (size_t)batch, N = 2 * (size_t)L - 1;
+    const size_t panel = (size_t)L * C * L * T;
+    const size_t grid = (size_t)batch * L * N * 2 * T;
+    ra = align256(panel > grid ? panel : grid);
+    rb = align256(panel);
+}
+
+int check_args(int L, int spin, int batch, int sampling, int precision) {
+    if (sampling != SHT_SAMPLING_MW) return SHT_ERR_UNSUPPORTED;
+    if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_ERR_UNSUPPORTED;
+    if (precision == SHT_BF16X3) return SHT_ERR_UNSUPPORTED;
+    if (L < 1 || L > SHT_L_MAX) return SHT_ERR_INVALID_ARG;
+    if (spin <= -L || spin >= L) return SHT_ERR_INVALID_ARG;
+    if (batch < 1 || batch > SHT_BATCH_MAX) return SHT_ERR_INVALID_ARG;
+    return SHT_OK;
+}
+
+int get_device_state(int dev, hipStream_t st, DeviceState **out) {
+    auto it = g_devices.find(dev);
+    if (it != g_devices.end()) { *out = &it->second; return SHT_OK; }
+    DeviceState ds;
+    ds.E.lmax = SHT_L_MAX;
+    const size_t n = (size_t)SHT_L_MAX * (SHT_L_MAX + 1) / 2;
+    if (hipMalloc(&ds.E.mant, n * sizeof(double)) != hipSuccess) return SHT_ERR_OOM;
+    if (hipMalloc(&ds.E.expo, n * sizeof(int)) != hipSuccess) { (void)hipFree(ds.E.mant); return SHT_ERR_OOM; }
+    SHT_HIP(launch_edge_table(ds.E, st), "edge table");
+    SHT_HIP(hipStreamSynchronize(st), "edge table sync");
+    auto res = g_devices.emplace(dev, ds);
+    *out = &res.first->second;
+    return SHT_OK;
+}
+
+template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
+    using C = typename CT<T>::type;
+    ft.L = L;
+    ft.N = 2 * L - 1;
+    ft.M = fft_size(L);
+    ft.logM = ilog2(ft.M);
+    const size_t n = (size_t)ft.M / 2 + 2 * (size_t)ft.N + 4 * (size_t)ft.M;
+    C *base = nullptr;
+    if (hipMalloc(&base, n * sizeof(C)) != hipSuccess) return SHT_ERR_OOM;
+    ft.tw = base;
+    ft.e2n = ft.tw + ft.M / 2;
+    ft.h_it = ft.e2n + 2 * ft.N;
+    ft.h_ip = ft.h_it + ft.M;
+    ft.h_fd = ft.h_ip + ft.M;
+    ft.h_fk = ft.h_fd + ft.M;
+    return SHT_OK;
+}
+
+int get_plan(int dev, int L, hipStream_t st, Plan **out) {
+    auto key = std::make_tuple(dev, L);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) { *out = it->second; return SHT_OK; }
+    Plan *p = new Plan();
+    p->device = dev;
+    p->L = L;
+    int rc = alloc_fft(p->f64, L);
+    if (rc == SHT_OK) rc = alloc_fft(p->f32, L);
+    if (rc != SHT_OK) { delete p; return rc; }
+    SHT_HIP(launch_fft_tables<double>(p->f64, nullptr, st), "fft tables f64");
+    SHT_HIP(launch_fft_tables<float>(p->f32, &p->f64, st), "fft tables f32");
+    SHT_HIP(hipStreamSynchronize(st), "plan sync");
+    g_plans[key] = p;
+    *out = p;
+    return SHT_OK;
+}
+
+int get_spin_plan(int dev, int L, int spin, const DeviceState *ds, hipStream_t st, SpinPlan **out) {
+    auto key = std::make_tuple(dev, L, spin);
+    auto it = g_spin.find(key);
+    if (it != g_spin.end()) { *out = it->second; return SHT_OK; }
+    SpinPlan *sp = new SpinPlan();
+    sp->device = dev;
+    sp->L = L;
+    sp->spin = spin;
+    if (hipMalloc(&sp->ss, (size_t)L * L * sizeof(SpinState)) != hipSuccess) { delete sp; return SHT_ERR_OOM; }
+    SHT_HIP(launch_spin_states(ds->E, *sp, st), "spin states");
+    SHT_HIP(hipStreamSynchronize(st), "spin plan sync");
+    g_spin[key] = sp;
+    *out = sp;
+    return SHT_OK;
+}
+
+int prepare(int L, int spin, hipStream_t st, DeviceState **ds, Plan **plan, SpinPlan **sp) {
+    int dev = 0;
+    SHT_HIP(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_mu);
+    int rc = get_device_state(dev, st, ds);
+    if (rc != SHT_OK) return rc;
+    rc = get_plan(dev, L, st, plan);
+    if (rc != SHT_OK) return rc;
+    return get_spin_plan(dev, L, spin, *ds, st, sp);
+}
+
+bool misaligned(const void *p, size_t a) { return ((uintptr_t)p) % a != 0; }
+
+int check_buffers(int L, int batch, int precision, const void *in, const void *out, const void *ws,
+                  size_t ws_bytes) {
+    if (!in || !out || !ws) return SHT_ERR_INVALID_ARG;
+    const size_t ca = 2 * elem_bytes(precision);
+    if (misaligned(in, ca) || misaligned(out, ca) || misaligned(ws, 256)) return SHT_ERR_ALIGNMENT;
+    size_t ra, rb;
+    regions(L, batch, precision, ra, rb);
+    if (ws_bytes < ra + rb) return SHT_ERR_WORKSPACE;
+    return SHT_OK;
+}
+
+template <typename T>
+int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const DeviceState *ds, const SpinPlan *sp,
+                const void *flm, void *map, void *ws, hipStream_t st) {
+    size_t ra, rb;
+    regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
+    unsigned char *w = (unsigned char *)ws;
+    T *P = (T *)w;            // region A: layout panels, later the theta-stage output
+    T *R = (T *)(w + ra);     // region B: contraction output
+    SHT_HIP(launch_layout_in<T>(L, spin, batch, flm, P, st), "layout_in");
+    SHT_HIP(launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, sp->ss, st), "contract inverse");
+    SHT_HIP(launch_theta_inv<T>(ft, spin, batch, R, (void *)P, st), "theta inverse");
+    SHT_HIP(launch_phi_inv<T>(ft, batch, (const void *)P, map, st), "phi inverse");
+    return SHT_OK;
+}
+
+template <typename T>
+int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const DeviceState *ds, const SpinPlan *sp,
+                const void *map, void *flm, void *ws, hipStream_t st) {
+    size_t ra, rb;
+    regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
+    unsigned char *w = (unsigned char *)ws;
+    void *Q = (void *)w;      // region A: phi-stage output, later the contraction output
+    T *X = (T *)(w + ra);     // region B: weighted theta coefficients
+    SHT_HIP(launch_phi_fwd<T>(ft, batch, map, Q, st), "phi forward");
+    SHT_HIP(launch_theta_fwd<T>(ft, spin, batch, Q, X, st), "theta forward");
+    T *R = (T *)w;
+    SHT_HIP(launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, sp->ss, st), "contract forward");
+    SHT_HIP(launch_layout_out<T>(L, spin, batch, R, flm, st), "layout_out");
+    return SHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precision) {
+    if (check_args(L, spin, batch, sampling, precision) != SHT_OK) return 0;
+    size_t ra, rb;
+    regions(L, batch, precision, ra, rb);
+    return ra + rb;
+}
+
+int sht_inverse(int L, int spin, int batch, int sampling, int precision, const void *flm, void *map,
+                void *workspace, size_t ws_bytes, void *stream) {
+    int rc = check_args(L, spin, batch, sampling, precision);
+    if (rc != SHT_OK) return rc;
+    rc = check_buffers(L, batch, precision, flm, map, workspace, ws_bytes);
+    if (rc != SHT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    if (rc != SHT_OK) return rc;
+    if (precision == SHT_FP64) return run_inverse<double>(L, spin, batch, plan->f64, ds, sp, flm, map, workspace, st);
+    return run_inverse<float>(L, spin, batch, plan->f32, ds, sp, flm, map, workspace, st);
+}
+
+int sht_forward(int L, int spin, int batch, int sampling, int precision, const void *map, void *flm,
+                void *workspace, size_t ws_bytes, void *stream) {
+    int rc = check_args(L, spin, batch, sampling, precision);
+    if (rc != SHT_OK) return rc;
+    rc = check_buffers(L, batch, precision, map, flm, workspace, ws_bytes);
+    if (rc != SHT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    if (rc != SHT_OK) return rc;
+    if (precision == SHT_FP64) return run_forward<double>(L, spin, batch, plan->f64, ds, sp, map, flm, workspace, st);
+    return run_forward<float>(L, spin, batch, plan->f32, ds, sp, map, flm, workspace, st);
+}
+
+int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) {
+    int rc = check_args(L, spin, 1, sampling, precision);
+    if (rc != SHT_OK) return rc;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    return prepare(L, spin, (hipStream_t)stream, &ds, &plan, &sp);
+}
+
+int sht_release_all(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    int rc = SHT_OK;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+    for (auto &kv : g_spin) {
+        (void)hipSetDevice(kv.second->device);
+        if (hipFree(kv.second->ss) != hipSuccess) rc = SHT_ERR_HIP;
+        delete kv.second;
+    }
+    g_spin.clear();
+    for (auto &kv : g_plans) {
+        (void)hipSetDevice(kv.second->device);
+        if (hipFree(kv.second->f64.tw) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->f32.tw) != hipSuccess) rc = SHT_ERR_HIP;
+        delete kv.second;
+    }
+    g_plans.clear();
+    for (auto &kv : g_devices) {
+        (void)hipSetDevice(kv.first);
+        if (hipFree(kv.second.E.mant) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second.E.expo) != hipSuccess) rc = SHT_ERR_HIP;
+    }
+    g_devices.clear();
+    (void)hipSetDevice(cur);
+    return rc;
+}
+
+const char *sht_status_string(int status) {
+    switch (status) {
+        case SHT_OK: return "ok";
+        case SHT_ERR_INVALID_ARG: return "invalid argument (L, spin, batch or a NULL pointer)";
+        case SHT_ERR_UNSUPPORTED: return "unsupported sampling or precision";
+        case SHT_ERR_WORKSPACE: return "workspace smaller than sht_workspace_bytes()";
+        case SHT_ERR_ALIGNMENT: return "misaligned buffer";
+        case SHT_ERR_OOM: return "device allocation for a plan failed";
+        case SHT_ERR_HIP: return "HIP error (see sht_last_hip_error)";
+        default: return "unknown status";
+    }
+}
+
+int sht_version(void) { return SHT_VERSION; }
+
+const char *sht_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"

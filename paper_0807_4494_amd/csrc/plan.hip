@@ -1,0 +1,177 @@
+// Plan kernels: Wigner edge seeds, spin-chain states, torus FFT tables.
+//
+// Everything here runs once per (device), (device, L, precision) or
+// (device, L, spin) and is cached by the host library.
+#include "chain.h"
+
+namespace sht {
+
+// ----------------------------------------------------------- edge table ---
+// E(l, k) = 2^-l sqrt(C(2l, l+k)) for 0 <= k <= l.  Its square is built as a
+// product of factors below one,
+//   4^-l C(2l, l)       = prod_{j=1..l} (2j-1)/(2j),
+//   C(2l,l+k+1)/C(2l,l+k) = (l-k)/(l+k+1),
+// with the binary exponent carried separately (E(l,l) = 2^-l underflows
+// double precision for l > 1074).  One thread per degree l.
+__global__ void k_edge_table(double *mant, int *expo, int lmax) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= lmax) return;
+    double m = 1.0;
+    int e = 0;
+    for (int j = 1; j <= l; ++j) {
+        m *= (double)(2 * j - 1) / (double)(2 * j);
+        if (m < 0x1p-500) { m *= 0x1p500; e -= 500; }
+    }
+    const long long base = (long long)l * (l + 1) / 2;
+    for (int k = 0; k <= l; ++k) {
+        // sqrt(m 2^e) as mantissa in [1, 2) and exponent
+        double mm = m;
+        int ee = e;
+        if (ee & 1) { mm *= 2.0; ee -= 1; }
+        double r = sqrt(mm);
+        int e2;
+        double fr = frexp(r, &e2);  // r = fr 2^e2, fr in [0.5, 1)
+        mant[base + k] = fr * 2.0;
+        expo[base + k] = ee / 2 + e2 - 1;
+        if (k < l) {
+            m *= (double)(l - k) / (double)(l + k + 1);
+            if (m < 0x1p-500) { m *= 0x1p500; e -= 500; }
+        }
+    }
+}
+
+hipError_t launch_edge_table(EdgeTable &E, hipStream_t st) {
+    const int threads = 64;
+    hipLaunchKernelGGL(k_edge_table, dim3((E.lmax + threads - 1) / threads), dim3(threads), 0, st,
+                       E.mant, E.expo, E.lmax);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- spin states -----
+// For each m' in [0, L): the chain d^l_{m', sigma}(pi/2), sigma = -s, run in l
+// from its edge l0 = max(m', |sigma|), storing (d^l, d^{l-1}, scale) at every l.
+// The inverse contraction resumes these chains at the first degree of its tile.
+__global__ void k_spin_states(EdgeTable E, SpinState *ss, int L, int sigma) {
+    const int mp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mp >= L) return;
+    const int asg = sigma < 0 ? -sigma : sigma;
+    const int l0 = mp > asg ? mp : asg;
+    Chain c;
+    c.zero();
+    double q = 0.0;  // sqrt(l^2 - m'^2) at the current l
+    for (int l = 0; l < L; ++l) {
+        if (l == l0) c.inject(edge_seed(E, mp, sigma));
+        SpinState st;
+        st.d = c.d;
+        st.dp = c.dp;
+        st.k = c.k;
+        st.pad = 0;
+        ss[(size_t)l * L + mp] = st;
+        // transition l -> l+1
+        const double X = (double)(l + 1) * (l + 1) - (double)mp * mp;
+        const double r = rsqrt(X > 1.0 ? X : 1.0);
+        const double ap = (double)mp * r, bp = q * r;
+        q = X > 0.0 ? X * r : 0.0;
+        double am, bm;
+        lrec_factor_full(l, sigma, am, bm);
+        const double dn = -(ap * am * c.d + bp * bm * c.dp);
+        if (l >= l0) c.push(dn);
+    }
+}
+
+hipError_t launch_spin_states(const EdgeTable &E, SpinPlan &sp, hipStream_t st) {
+    const int threads = 64;
+    hipLaunchKernelGGL(k_spin_states, dim3((sp.L + threads - 1) / threads), dim3(threads), 0, st,
+                       E, sp.ss, sp.L, -sp.spin);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- FFT tables ------
+// Angles are pi * (integer) / N or 2 pi * (integer) / M with the integer
+// reduced exactly first, then evaluated with sincospi in double precision.
+__global__ void k_fill_tw(cplx64 *tw, int M) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M / 2) return;
+    double s, c;
+    sincospi(-2.0 * (double)k / (double)M, &s, &c);
+    tw[k] = cplx64{c, s};
+}
+
+__global__ void k_fill_e2n(cplx64 *e, int N) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * N) return;
+    double s, c;
+    sincospi((double)k / (double)N, &s, &c);
+    e[k] = cplx64{c, s};
+}
+
+// Chirp-z kernel sequence c_j for j in [-(nin-1), kout-1], stored at j mod M.
+//   type 0: e^{-i pi j^2 / N}      (inverse stages)
+//   type 1: e^{+i pi j^2 / N}      (forward DFT stages)
+//   type 2: K(j + h), h = L-1      (forward sin-theta quadrature, real)
+//           K(p) = 2/(1-p^2) for even p, 0 for odd p
+__global__ void k_fill_kernel_seq(cplx64 *c, int M, int N, int L, int nin, int kout, int type) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    // j such that j mod M == i, within the range
+    long long j;
+    if (i < kout) j = i;
+    else if (i >= M - (nin - 1)) j = (long long)i - M;
+    else { c[i] = cplx64{0.0, 0.0}; return; }
+    if (type == 2) {
+        const long long p = j + (L - 1);
+        const double v = (p & 1) ? 0.0 : 2.0 / (1.0 - (double)p * (double)p);
+        c[i] = cplx64{v, 0.0};
+        return;
+    }
+    const long long twoN = 2LL * N;
+    long long r = (j * j) % twoN;
+    double s, cc;
+    sincospi((double)r / (double)N, &s, &cc);
+    c[i] = cplx64{cc, type == 0 ? -s : s};
+}
+
+template <typename T> __global__ void k_convert_table(typename CT<T>::type *dst, const cplx64 *src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i].x = (T)src[i].x;
+    dst[i].y = (T)src[i].y;
+}
+
+template <>
+hipError_t launch_fft_tables<double>(FftTables<double> &ft, FftTables<double> *, hipStream_t st) {
+    const int M = ft.M, N = ft.N, L = ft.L;
+    const int th = 256;
+    hipLaunchKernelGGL(k_fill_tw, dim3((M / 2 + th - 1) / th), dim3(th), 0, st, ft.tw, M);
+    hipLaunchKernelGGL(k_fill_e2n, dim3((2 * N + th - 1) / th), dim3(th), 0, st, ft.e2n, N);
+    hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_it, M, N, L, N, L, 0);
+    hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_ip, M, N, L, N, N, 0);
+    hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fd, M, N, L, N, N, 1);
+    hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fk, M, N, L, N, L, 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // spectra: forward DIF in place, scaled by 1/M (the inverse transform's normalisation)
+    const double inv = 1.0 / (double)M;
+    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_it, 1, inv, st)) != hipSuccess) return e;
+    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_ip, 1, inv, st)) != hipSuccess) return e;
+    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_fd, 1, inv, st)) != hipSuccess) return e;
+    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_fk, 1, inv, st)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template <>
+hipError_t launch_fft_tables<float>(FftTables<float> &ft, FftTables<double> *src, hipStream_t st) {
+    const int th = 256;
+    auto conv = [&](cplx32 *d, const cplx64 *s, int n) {
+        hipLaunchKernelGGL(k_convert_table<float>, dim3((n + th - 1) / th), dim3(th), 0, st, d, s, n);
+    };
+    conv(ft.tw, src->tw, ft.M / 2);
+    conv(ft.e2n, src->e2n, 2 * ft.N);
+    conv(ft.h_it, src->h_it, ft.M);
+    conv(ft.h_ip, src->h_ip, ft.M);
+    conv(ft.h_fd, src->h_fd, ft.M);
+    conv(ft.h_fk, src->h_fk, ft.M);
+    return hipGetLastError();
+}
+
+}  // namespace sht

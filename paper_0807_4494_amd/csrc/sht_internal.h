@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP translation units of libsht.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sht.h"
+
+namespace sht {
+
+// ---------------------------------------------------------------- numbers ---
+struct cplx64 { double x, y; };
+struct cplx32 { float x, y; };
+
+template <typename T> struct CT;
+template <> struct CT<double> { using type = cplx64; };
+template <> struct CT<float> { using type = cplx32; };
+
+template <typename C> __host__ __device__ inline C cmul(C a, C b) {
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __host__ __device__ inline C cmulc(C a, C b) {  // a * conj(b)
+    return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename C> __host__ __device__ inline C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __host__ __device__ inline C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+
+// Extended-range scale for Wigner chains: a chain value is stored as
+// d * 2^(-512 k); k = 0 means plain.  Seeds as small as 2^-2048 occur.
+constexpr double kBig = 0x1p512;
+constexpr double kSmall = 0x1p-512;
+
+__host__ __device__ inline int parity(long long x) { return (int)(x & 1); }
+__host__ __device__ inline double sgn_pow(long long x) { return parity(x) ? -1.0 : 1.0; }
+
+// ---------------------------------------------------------------- plans -----
+// Edge table: E[l][k] = 2^-l sqrt(C(2l, l+k)), 0 <= k <= l < SHT_L_MAX, as a
+// mantissa in [1, 2) and a binary exponent, at index l(l+1)/2 + k.
+struct EdgeTable {
+    double *mant = nullptr;
+    int *expo = nullptr;
+    int lmax = 0;
+};
+
+// State of the spin chain d^l_{m', -s}(pi/2) over l, per (l, m'):
+// d = value at l, dp = value at l-1, both scaled by 2^(512 k).
+struct SpinState {
+    double d, dp;
+    int k, pad;
+};
+
+// Per-(L, precision) tables for the torus FFT stages.
+template <typename T> struct FftTables {
+    using C = typename CT<T>::type;
+    int L = 0, N = 0, M = 0, logM = 0;
+    C *tw = nullptr;      // e^{-2 pi i k / M}, k < M/2
+    C *e2n = nullptr;     // e^{i pi k / N}, k < 2N
+    C *h_it = nullptr;    // spectra (bit-reversed, 1/M folded in) of the chirp-z kernels
+    C *h_ip = nullptr;
+    C *h_fd = nullptr;
+    C *h_fk = nullptr;
+};
+
+struct Plan {
+    int device = 0, L = 0, prec = 0;
+    FftTables<double> f64;
+    FftTables<float> f32;
+};
+
+struct SpinPlan {
+    int device = 0, L = 0, spin = 0;
+    SpinState *ss = nullptr;  // [L][L]
+};
+
+// -------------------------------------------------------- kernel launches ---
+// plan.hip
+hipError_t launch_edge_table(EdgeTable &E, hipStream_t st);
+hipError_t launch_spin_states(const EdgeTable &E, SpinPlan &sp, hipStream_t st);
+template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
+
+// layout.hip
+template <typename T>
+hipError_t launch_layout_in(int L, int s, int B, const void *flm, T *P, hipStream_t st);
+template <typename T>
+hipError_t launch_layout_out(int L, int s, int B, const T *R, void *flm, hipStream_t st);
+
+// fft.hip: row transforms
+template <typename T>
+hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, const T *R, void *G, hipStream_t st);
+template <typename T>
+hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, hipStream_t st);
+template <typename T>
+hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st);
+template <typename T>
+hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q, T *X, hipStream_t st);
+// forward DIF transform of one sequence per block, in place (plan building)
+template <typename T>
+hipError_t launch_fft_dif_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows,
+                                  double scale, hipStream_t st);
+
+// contract.hip
+enum ContractMode { kInverse = 0, kForward = 1 };
+template <typename T>
+hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
+                           const SpinState *ss, hipStream_t st);
+hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y,
+                                  const EdgeTable &E, const SpinState *ss, hipStream_t st);
+
+// ------------------------------------------------------------- helpers -----
+inline int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
+inline int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+}  // namespace sht

@@ -1,0 +1,108 @@
+"""Python entry points of the spin SHT (same names as the C ABI).
+
+``inverse(flm, L, spin, precision)`` and ``forward(fmap, L, spin, precision)``
+take and return CUDA/HIP torch tensors; torch provides device memory and the
+current stream only.
+
+Layouts (see include/sht.h): ``flm`` is complex ``[batch, L*L]`` (index
+l*l + l + m) and maps are complex ``[batch, L, 2L-1]`` on the sampling of
+Eq. (nodes_theta)/(nodes_phi).  A 1-D ``flm`` / 2-D map is treated as batch 1
+and returned unbatched.  complex128 for ``"fp64"``, complex64 otherwise.
+"""
+
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import _native as N
+
+PRECISIONS = {"fp64": N.SHT_FP64, "fp32": N.SHT_FP32, "bf16x3": N.SHT_BF16X3}
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, int):
+        return precision
+    try:
+        return PRECISIONS[precision]
+    except KeyError:
+        raise ValueError(f"precision must be one of {list(PRECISIONS)}") from None
+
+
+def io_dtype(precision) -> torch.dtype:
+    return torch.complex128 if _prec(precision) == N.SHT_FP64 else torch.complex64
+
+
+def _stream_handle(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def workspace_bytes(L: int, spin: int, batch: int, precision="fp64") -> int:
+    return int(N.load().sht_workspace_bytes(L, spin, batch, N.SHT_SAMPLING_MW, _prec(precision)))
+
+
+def _workspace(L, spin, batch, p, device, workspace):
+    need = N.load().sht_workspace_bytes(L, spin, batch, N.SHT_SAMPLING_MW, p)
+    if need == 0:
+        # invalid arguments: let the library report the precise error
+        return None, 0
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=device)
+    return workspace, workspace.numel() * workspace.element_size()
+
+
+def inverse(flm: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Optional[torch.Tensor] = None,
+            workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Inverse spin SHT: f_lm -> samples f(theta_t, phi_p)."""
+    p = _prec(precision)
+    single = flm.dim() == 1
+    f = flm.reshape(1, -1) if single else flm
+    if f.shape[-1] != L * L:
+        raise ValueError(f"flm has {f.shape[-1]} coefficients per map, expected L*L = {L * L}")
+    if not f.is_cuda:
+        raise ValueError("flm must be a GPU tensor")
+    f = f.to(io_dtype(p)).contiguous()
+    B = f.shape[0]
+    if out is None:
+        out = torch.empty((B, L, 2 * L - 1), dtype=io_dtype(p), device=f.device)
+    ws, nbytes = _workspace(L, spin, B, p, f.device, workspace)
+    rc = N.load().sht_inverse(L, spin, B, N.SHT_SAMPLING_MW, p, f.data_ptr(), out.data_ptr(),
+                              ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(f.device))
+    N.check(rc, "sht_inverse")
+    return out[0] if single else out
+
+
+def forward(fmap: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Optional[torch.Tensor] = None,
+            workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Forward spin SHT: samples f(theta_t, phi_p) -> f_lm."""
+    p = _prec(precision)
+    single = fmap.dim() == 2
+    g = fmap.reshape(1, *fmap.shape) if single else fmap
+    if tuple(g.shape[-2:]) != (L, 2 * L - 1):
+        raise ValueError(f"map shape {tuple(g.shape[-2:])}, expected ({L}, {2 * L - 1})")
+    if not g.is_cuda:
+        raise ValueError("map must be a GPU tensor")
+    g = g.to(io_dtype(p)).contiguous()
+    B = g.shape[0]
+    if out is None:
+        out = torch.empty((B, L * L), dtype=io_dtype(p), device=g.device)
+    ws, nbytes = _workspace(L, spin, B, p, g.device, workspace)
+    rc = N.load().sht_forward(L, spin, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
+                              ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(g.device))
+    N.check(rc, "sht_forward")
+    return out[0] if single else out
+
+
+def plan_warmup(L: int, spin: int = 0, precision="fp64", device=None) -> None:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    N.check(N.load().sht_plan_warmup(L, spin, N.SHT_SAMPLING_MW, _prec(precision), _stream_handle(dev)),
+            "sht_plan_warmup")
+
+
+def release_all() -> None:
+    N.check(N.load().sht_release_all(), "sht_release_all")
+
+
+def version() -> int:
+    return int(N.load().sht_version())

@@ -1,0 +1,81 @@
+"""CPU tests of the C ABI: the library loads, exports every symbol the header
+declares, and rejects bad arguments before touching HIP (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sht.h")
+
+
+def _lib():
+    from paper_0807_4494_amd import _native as N
+    try:
+        return N, N.load()
+    except ImportError as e:
+        pytest.fail(f"libsht.so must be built before the tests: {e}")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(sht_[a-z_0-9]+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = header_functions()
+    for must in ("sht_inverse", "sht_forward", "sht_workspace_bytes", "sht_plan_warmup",
+                 "sht_release_all", "sht_status_string", "sht_version"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    N, lib = _lib()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert set(header_functions()) == set(N.EXPORTS)
+
+
+def test_version_and_status_strings():
+    N, lib = _lib()
+    assert lib.sht_version() == 10000
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert lib.sht_status_string(code)
+
+
+def test_argument_checks_run_before_any_hip_call():
+    N, lib = _lib()
+    fake = ctypes.c_void_p(1 << 20)     # never dereferenced: checks fail first
+    big = 1 << 40
+    call = lambda *a: lib.sht_inverse(*a)
+    # sampling / precision
+    assert call(8, 0, 1, 1, 0, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
+    assert call(8, 0, 1, 0, 7, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
+    # L, spin, batch
+    assert call(0, 0, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(4097, 0, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 8, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, -8, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 0, 0, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    # NULL pointers, alignment, workspace size
+    assert call(8, 0, 1, 0, 0, None, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 0, 1, 0, 0, ctypes.c_void_p((1 << 20) + 8), fake, fake, big, None) == N.SHT_ERR_ALIGNMENT
+    assert call(8, 0, 1, 0, 0, fake, fake, ctypes.c_void_p((1 << 20) + 16), big, None) == N.SHT_ERR_ALIGNMENT
+    need = lib.sht_workspace_bytes(8, 0, 1, 0, 0)
+    assert call(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
+    assert lib.sht_forward(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
+
+
+def test_workspace_size_formula():
+    N, lib = _lib()
+    for L, B, p in [(32, 1, 0), (1024, 16, 1), (2048, 4, 1), (255, 3, 0)]:
+        T = 8 if p == 0 else 4
+        C, Nn = 4 * B, 2 * L - 1
+        al = lambda x: (x + 255) // 256 * 256
+        ra = al(max(L * C * L * T, B * L * Nn * 2 * T))
+        rb = al(L * C * L * T)
+        assert lib.sht_workspace_bytes(L, 0, B, 0, p) == ra + rb
+    assert lib.sht_workspace_bytes(8, 9, 1, 0, 0) == 0
+    assert lib.sht_workspace_bytes(8, 0, 1, 3, 0) == 0
