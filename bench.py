@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the spin SHT on one MI355X.
+
+Workload (default): L = 1024, spins {0, +2, -2}, 16 maps per spin, complex
+Gaussian coefficients with C_l = 1/(l+1)^2 (sht_synth workload
+"L1024_s0pm2_b16").  One step = inverse then forward transform of every map of
+every spin (48 maps), inputs resident in HBM.  A "transform" is one map taken
+through inverse and forward, so value = 48 / step time.
+
+Prints one JSON line (rank 0):
+  metric, value (transforms/s), ms_per_step, dtype, config,
+  roofline   the dominant kernel's achieved rate from HIP events recorded
+             around every stage (library stage tracing, same stream) against
+             its roofline; algorithmic flops / bytes per launch as documented
+             in the design doc,
+  cpu_baseline  the CPU oracle timed on a bounded sample (one map through
+             inverse + forward) on this host,
+  fp64_path  the all-FP64 GPU path on the same workload, for comparison,
+  stages_ms  per-step time of every stage.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp32_mfma_TFs": 157.3,
+    "fp64_mfma_TFs": 78.6,
+    "bf16_mfma_TFs": 2500.0,
+}
+
+
+def contraction_flops(L: int, s: int, B: int) -> float:
+    """Algorithmic flops of one contraction launch (one direction, B maps):
+    4 sum_{l=|s|}^{L-1} (2l+1)(l+1) per map -- real multiply-adds x 2 over the
+    non-zero triangle m' <= l, |m| <= l, m' >= 0 folded (the Delta product is
+    shared by the Re/Im columns and by +-m)."""
+    a = abs(s)
+    return 4.0 * B * sum((2 * l + 1) * (l + 1) for l in range(a, L))
+
+
+def stage_bytes(stage: str, L: int, B: int, cbytes: int) -> float:
+    """Algorithmic HBM bytes of one launch of a stage (B maps, cbytes per complex)."""
+    N = 2 * L - 1
+    if stage in ("theta_inv", "phi_inv", "phi_fwd", "theta_fwd"):
+        return 2.0 * N * L * B * cbytes           # read one N x L grid, write one
+    if stage in ("layout_in", "layout_out"):
+        return 2.0 * L * L * B * cbytes           # read L^2, write L^2 (folded +-m panels)
+    if stage in ("contract_inv", "contract_fwd"):
+        # read the folded panel (L^2 complex per map), write N x L per map
+        return (L * L + N * L) * B * cbytes
+    raise KeyError(stage)
+
+
+def run_steps(sht, torch, wl, prec, flm, steps, warmup, trace):
+    L, B = wl.L, wl.batch
+    dev = flm[wl.spins[0]].device
+    dt = sht.io_dtype(prec)
+    maps = {s: torch.empty((B, L, 2 * L - 1), dtype=dt, device=dev) for s in wl.spins}
+    back = {s: torch.empty((B, L * L), dtype=dt, device=dev) for s in wl.spins}
+    ws = torch.empty(max(sht.workspace_bytes(L, s, B, prec) for s in wl.spins), dtype=torch.uint8, device=dev)
+
+    def step():
+        for s in wl.spins:
+            sht.inverse(flm[s], L, s, prec, out=maps[s], workspace=ws)
+            sht.forward(maps[s], L, s, prec, out=back[s], workspace=ws)
+
+    for s in wl.spins:
+        sht.plan_warmup(L, s, prec)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if trace:
+        sht.trace_enable(True)
+        sht.trace_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = None
+    if trace:
+        stages = sht.trace_read()
+        sht.trace_enable(False)
+    return (t1 - t0) / steps * 1e3, stages, back
+
+
+def cpu_baseline(wl, seconds_hint: float = 30.0) -> dict:
+    """The oracle (never tuned) on one map of the workload: inverse + forward."""
+    import numpy as np
+    import oracle
+
+    s = wl.spins[-1]
+    flm = wl.flm(s)[:1]
+    t0 = time.perf_counter()
+    fmap = oracle.inverse_batch(flm, wl.L, s)
+    back = oracle.forward_batch(fmap, wl.L, s)
+    dt = time.perf_counter() - t0
+    err = oracle.rel_l2(flm, back)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    cores = os.cpu_count() or 1
+    if omp and omp.isdigit():
+        cores = min(cores, int(omp))
+    return {"value": 1.0 / dt, "unit": "transforms/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 map, L={wl.L}, spin {s}, inverse + forward (numpy FP64 + C Risbo); "
+                      f"{dt:.1f} s; oracle round trip rel_l2 {err:.1e}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--workload", default="L1024_s0pm2_b16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design note, not an implementation", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_0807_4494_amd as sht
+    import sht_synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    wl = {w.name: w for w in sht_synth.WORKLOADS}[args.workload]
+    dev = torch.device("cuda", 0)
+    prec = args.precision
+    host_flm = {s: wl.flm(s) for s in wl.spins}
+    flm = {s: torch.from_numpy(host_flm[s]).to(dev, sht.io_dtype(prec)) for s in wl.spins}
+
+    ms, stages, back = run_steps(sht, torch, wl, prec, flm, args.steps, args.warmup, trace=True)
+    per_step = len(wl.spins) * wl.batch
+    value = per_step / (ms / 1e3)
+
+    # round-trip error of the measured path (inverse then forward returns f_lm)
+    rt = max(float(torch.linalg.vector_norm(back[s] - flm[s]) / torch.linalg.vector_norm(flm[s]))
+             for s in wl.spins)
+
+    L, B = wl.L, wl.batch
+    cbytes = 16 if prec == "fp64" else 8
+    stages_ms = {k: v[0] / args.steps for k, v in stages.items()}
+    counts = {k: v[1] for k, v in stages.items()}
+    dominant = max(stages_ms, key=lambda k: stages_ms[k])
+    if dominant.startswith("contract"):
+        launches = [(st_, s) for s in wl.spins for st_ in ("contract_inv", "contract_fwd")]
+        flops = sum(contraction_flops(L, s, B) for _, s in launches) * args.steps
+        t = (stages["contract_inv"][0] + stages["contract_fwd"][0]) / 1e3
+        achieved = flops / t / 1e12
+        peak = PEAK["fp64_mfma_TFs"] if prec == "fp64" else PEAK["fp32_mfma_TFs"]
+        roof = {"bound": "mfma", "kernel": "k_contract (inverse + forward launches)",
+                "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "launches": counts["contract_inv"] + counts["contract_fwd"],
+                "avg_launch_ms": round(t * 1e3 / (counts["contract_inv"] + counts["contract_fwd"]), 4)}
+    else:
+        by = stage_bytes(dominant, L, B, cbytes) * counts[dominant]
+        t = stages[dominant][0] / 1e3
+        achieved = by / t / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK["hbm_GBs"],
+                "unit": "GB/s", "frac": round(achieved / PEAK["hbm_GBs"], 4), "traffic": None,
+                "launches": counts[dominant], "avg_launch_ms": round(stages[dominant][0] / counts[dominant], 4)}
+
+    # every stage against its own roofline
+    stage_roof = {}
+    for k, tot in stages.items():
+        if tot[1] == 0:
+            continue
+        avg_s = tot[0] / tot[1] / 1e3
+        if k.startswith("contract"):
+            f = sum(contraction_flops(L, s, B) for s in wl.spins) / len(wl.spins)
+            pk = PEAK["fp64_mfma_TFs"] if prec == "fp64" else PEAK["fp32_mfma_TFs"]
+            stage_roof[k] = {"ms": round(avg_s * 1e3, 4), "TFLOP/s": round(f / avg_s / 1e12, 2),
+                             "frac": round(f / avg_s / 1e12 / pk, 4)}
+        else:
+            b = stage_bytes(k, L, B, cbytes)
+            stage_roof[k] = {"ms": round(avg_s * 1e3, 4), "GB/s": round(b / avg_s / 1e9, 1),
+                             "frac": round(b / avg_s / 1e9 / PEAK["hbm_GBs"], 4)}
+
+    out = {
+        "metric": "spin SHT fwd+inv transforms/sec at L=1024 batch 16",
+        "value": round(value, 2),
+        "unit": "transforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[prec],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "L": L, "batch": B, "spins": list(wl.spins),
+                   "spectrum": "C_l = 1/(l+1)^2", "precision": prec,
+                   "maps_per_step": per_step, "wigner_recursion": "f64"},
+        "roofline": roof,
+        "round_trip_rel_l2": rt,
+        "stages": stage_roof,
+    }
+    if not args.no_fp64 and prec != "fp64":
+        flm64 = {s: torch.from_numpy(host_flm[s]).to(dev, torch.complex128) for s in wl.spins}
+        n64 = max(2, min(args.steps, 5))
+        ms64, st64, back64 = run_steps(sht, torch, wl, "fp64", flm64, n64, 1, trace=False)
+        rt64 = max(float(torch.linalg.vector_norm(back64[s] - flm64[s]) / torch.linalg.vector_norm(flm64[s]))
+                   for s in wl.spins)
+        out["fp64_path"] = {"value": round(per_step / (ms64 / 1e3), 2), "ms_per_step": round(ms64, 4),
+                            "steps": n64, "round_trip_rel_l2": rt64}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

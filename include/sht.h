@@ -123,6 +123,28 @@ int sht_version(void);
 /* Text of the last HIP error seen by the library in this thread ("" if none). */
 const char *sht_last_hip_error(void);
 
+/*
+ * Stage tracing (a profiling aid, off by default).  While enabled, every
+ * transform records a pair of HIP events on its own stream around each of its
+ * stages.  sht_trace_read() waits for the recorded events, adds each stage's
+ * elapsed milliseconds into ms[stage] and its launch count into count[stage]
+ * for stage < nstages (SHT_STAGE_COUNT covers them all), and forgets them.
+ * Stages: SHT_STAGE_* below.  Not thread-safe against concurrent transforms.
+ */
+enum sht_stage {
+    SHT_STAGE_LAYOUT_IN = 0,   /* inverse: coefficients -> order-major panels */
+    SHT_STAGE_CONTRACT_INV,    /* inverse: Wigner chains + MFMA contraction */
+    SHT_STAGE_THETA_INV,       /* inverse: theta torus sum */
+    SHT_STAGE_PHI_INV,         /* inverse: phi torus sum */
+    SHT_STAGE_PHI_FWD,         /* forward: phi DFT */
+    SHT_STAGE_THETA_FWD,       /* forward: extension, theta DFT, quadrature */
+    SHT_STAGE_CONTRACT_FWD,    /* forward: Wigner chains + MFMA contraction */
+    SHT_STAGE_LAYOUT_OUT,      /* forward: panels -> coefficients */
+    SHT_STAGE_COUNT
+};
+int sht_trace_enable(int on);
+int sht_trace_read(double *ms, int *count, int nstages);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,12 @@ SHT_FP64, SHT_FP32, SHT_BF16X3 = 0, 1, 2
 
 #: every symbol include/sht.h declares
 EXPORTS = ("sht_inverse", "sht_forward", "sht_workspace_bytes", "sht_plan_warmup",
-           "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error")
+           "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error",
+           "sht_trace_enable", "sht_trace_read")
+
+#: stage ids of sht_trace_read (enum sht_stage)
+STAGES = ("layout_in", "contract_inv", "theta_inv", "phi_inv", "phi_fwd", "theta_fwd",
+          "contract_fwd", "layout_out")
 
 _lib = None
 
@@ -66,6 +71,10 @@ def load() -> ctypes.CDLL:
     lib.sht_version.restype = i
     lib.sht_last_hip_error.argtypes = []
     lib.sht_last_hip_error.restype = ctypes.c_char_p
+    lib.sht_trace_enable.argtypes = [i]
+    lib.sht_trace_enable.restype = i
+    lib.sht_trace_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), i]
+    lib.sht_trace_read.restype = i
     _lib = lib
     return lib
 

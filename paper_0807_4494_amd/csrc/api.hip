@@ -5,6 +5,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "sht_internal.h"
 
@@ -33,6 +34,48 @@ std::mutex g_mu;
 std::map<int, DeviceState> g_devices;
 std::map<std::tuple<int, int>, Plan *> g_plans;              // (device, L)
 std::map<std::tuple<int, int, int>, SpinPlan *> g_spin;      // (device, L, spin)
+
+// ---- stage tracing ----
+struct TraceRec {
+    int stage;
+    hipEvent_t a, b;
+};
+bool g_trace_on = false;
+std::mutex g_trace_mu;
+std::vector<TraceRec> g_trace_pending;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pool_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs `launch` (returns hipError_t), bracketed by events when tracing is on.
+template <typename F> hipError_t traced(int stage, hipStream_t st, F launch) {
+    if (!g_trace_on) return launch();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_trace_mu);
+        a = pool_event();
+        b = pool_event();
+    }
+    if (!a || !b) return launch();
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    g_trace_pending.push_back(TraceRec{stage, a, b});
+    return hipSuccess;
+}
 
 int fft_size(int L) {
     int need = 4 * L - 3;
@@ -164,10 +207,16 @@ int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const Device
     unsigned char *w = (unsigned char *)ws;
     T *P = (T *)w;            // region A: layout panels, later the theta-stage output
     T *R = (T *)(w + ra);     // region B: contraction output
-    SHT_HIP(launch_layout_in<T>(L, spin, batch, flm, P, st), "layout_in");
-    SHT_HIP(launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, sp->ss, st), "contract inverse");
-    SHT_HIP(launch_theta_inv<T>(ft, spin, batch, R, (void *)P, st), "theta inverse");
-    SHT_HIP(launch_phi_inv<T>(ft, batch, (const void *)P, map, st), "phi inverse");
+    SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st, [&] { return launch_layout_in<T>(L, spin, batch, flm, P, st); }),
+            "layout_in");
+    SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
+                   [&] { return launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, sp->ss, st); }),
+            "contract inverse");
+    SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
+                   [&] { return launch_theta_inv<T>(ft, spin, batch, R, (void *)P, st); }),
+            "theta inverse");
+    SHT_HIP(traced(SHT_STAGE_PHI_INV, st, [&] { return launch_phi_inv<T>(ft, batch, (const void *)P, map, st); }),
+            "phi inverse");
     return SHT_OK;
 }
 
@@ -179,11 +228,16 @@ int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const Device
     unsigned char *w = (unsigned char *)ws;
     void *Q = (void *)w;      // region A: phi-stage output, later the contraction output
     T *X = (T *)(w + ra);     // region B: weighted theta coefficients
-    SHT_HIP(launch_phi_fwd<T>(ft, batch, map, Q, st), "phi forward");
-    SHT_HIP(launch_theta_fwd<T>(ft, spin, batch, Q, X, st), "theta forward");
+    SHT_HIP(traced(SHT_STAGE_PHI_FWD, st, [&] { return launch_phi_fwd<T>(ft, batch, map, Q, st); }),
+            "phi forward");
+    SHT_HIP(traced(SHT_STAGE_THETA_FWD, st, [&] { return launch_theta_fwd<T>(ft, spin, batch, Q, X, st); }),
+            "theta forward");
     T *R = (T *)w;
-    SHT_HIP(launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, sp->ss, st), "contract forward");
-    SHT_HIP(launch_layout_out<T>(L, spin, batch, R, flm, st), "layout_out");
+    SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
+                   [&] { return launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, sp->ss, st); }),
+            "contract forward");
+    SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st, [&] { return launch_layout_out<T>(L, spin, batch, R, flm, st); }),
+            "layout_out");
     return SHT_OK;
 }
 
@@ -283,5 +337,35 @@ const char *sht_status_string(int status) {
 int sht_version(void) { return SHT_VERSION; }
 
 const char *sht_last_hip_error(void) { return g_last_hip_error; }
+
+int sht_trace_enable(int on) {
+    g_trace_on = on != 0;
+    return SHT_OK;
+}
+
+int sht_trace_read(double *ms, int *count, int nstages) {
+    if ((!ms || !count) && nstages > 0) return SHT_ERR_INVALID_ARG;
+    std::vector<TraceRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_trace_mu);
+        recs.swap(g_trace_pending);
+    }
+    int rc = SHT_OK;
+    for (const TraceRec &r : recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+            rc = hip_fail(hipGetLastError(), "trace read");
+        } else if (r.stage < nstages) {
+            ms[r.stage] += (double)t;
+            count[r.stage] += 1;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    for (const TraceRec &r : recs) {
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    return rc;
+}
 
 }  // extern "C"

@@ -106,3 +106,18 @@ def release_all() -> None:
 
 def version() -> int:
     return int(N.load().sht_version())
+
+
+def trace_enable(on: bool = True) -> None:
+    """Record HIP events around every stage of subsequent transforms."""
+    N.check(N.load().sht_trace_enable(1 if on else 0), "sht_trace_enable")
+
+
+def trace_read() -> dict:
+    """Per-stage {name: (total_ms, launches)} since the last read (waits for the events)."""
+    import ctypes
+    n = len(N.STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    N.check(N.load().sht_trace_read(ms, cnt, n), "sht_trace_read")
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(N.STAGES)}
