@@ -129,11 +129,11 @@ template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
     ft.N = 2 * L - 1;
     ft.M = fft_size(L);
     ft.logM = ilog2(ft.M);
-    const size_t n = (size_t)ft.M / 2 + 2 * (size_t)ft.N + 4 * (size_t)ft.M;
+    const size_t n = (size_t)ft.M + 2 * (size_t)ft.N + 4 * (size_t)ft.M;
     C *base = nullptr;
     if (hipMalloc(&base, n * sizeof(C)) != hipSuccess) return SHT_ERR_OOM;
     ft.tw = base;
-    ft.e2n = ft.tw + ft.M / 2;
+    ft.e2n = ft.tw + ft.M;
     ft.h_it = ft.e2n + 2 * ft.N;
     ft.h_ip = ft.h_it + ft.M;
     ft.h_fd = ft.h_ip + ft.M;
@@ -151,6 +151,12 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     int rc = alloc_fft(p->f64, L);
     if (rc == SHT_OK) rc = alloc_fft(p->f32, L);
     if (rc != SHT_OK) { delete p; return rc; }
+    if (hipMalloc(&p->rec.ri, (size_t)L * L * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->rec.rf, (size_t)L * L * sizeof(double)) != hipSuccess) {
+        delete p;
+        return SHT_ERR_OOM;
+    }
+    SHT_HIP(launch_rec_tables(L, p->rec, st), "recursion tables");
     SHT_HIP(launch_fft_tables<double>(p->f64, nullptr, st), "fft tables f64");
     SHT_HIP(launch_fft_tables<float>(p->f32, &p->f64, st), "fft tables f32");
     SHT_HIP(hipStreamSynchronize(st), "plan sync");
@@ -200,8 +206,8 @@ int check_buffers(int L, int batch, int precision, const void *in, const void *o
 }
 
 template <typename T>
-int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const DeviceState *ds, const SpinPlan *sp,
-                const void *flm, void *map, void *ws, hipStream_t st) {
+int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const RecTables &rec, const DeviceState *ds,
+                const SpinPlan *sp, const void *flm, void *map, void *ws, hipStream_t st) {
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
@@ -210,7 +216,7 @@ int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const Device
     SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st, [&] { return launch_layout_in<T>(L, spin, batch, flm, P, st); }),
             "layout_in");
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
-                   [&] { return launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, sp->ss, st); }),
+                   [&] { return launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, sp->ss, rec, st); }),
             "contract inverse");
     SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
                    [&] { return launch_theta_inv<T>(ft, spin, batch, R, (void *)P, st); }),
@@ -221,8 +227,8 @@ int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const Device
 }
 
 template <typename T>
-int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const DeviceState *ds, const SpinPlan *sp,
-                const void *map, void *flm, void *ws, hipStream_t st) {
+int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const RecTables &rec, const DeviceState *ds,
+                const SpinPlan *sp, const void *map, void *flm, void *ws, hipStream_t st) {
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
@@ -234,7 +240,7 @@ int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const Device
             "theta forward");
     T *R = (T *)w;
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
-                   [&] { return launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, sp->ss, st); }),
+                   [&] { return launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, sp->ss, rec, st); }),
             "contract forward");
     SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st, [&] { return launch_layout_out<T>(L, spin, batch, R, flm, st); }),
             "layout_out");
@@ -264,8 +270,9 @@ int sht_inverse(int L, int spin, int batch, int sampling, int precision, const v
     SpinPlan *sp;
     rc = prepare(L, spin, st, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
-    if (precision == SHT_FP64) return run_inverse<double>(L, spin, batch, plan->f64, ds, sp, flm, map, workspace, st);
-    return run_inverse<float>(L, spin, batch, plan->f32, ds, sp, flm, map, workspace, st);
+    if (precision == SHT_FP64)
+        return run_inverse<double>(L, spin, batch, plan->f64, plan->rec, ds, sp, flm, map, workspace, st);
+    return run_inverse<float>(L, spin, batch, plan->f32, plan->rec, ds, sp, flm, map, workspace, st);
 }
 
 int sht_forward(int L, int spin, int batch, int sampling, int precision, const void *map, void *flm,
@@ -280,8 +287,9 @@ int sht_forward(int L, int spin, int batch, int sampling, int precision, const v
     SpinPlan *sp;
     rc = prepare(L, spin, st, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
-    if (precision == SHT_FP64) return run_forward<double>(L, spin, batch, plan->f64, ds, sp, map, flm, workspace, st);
-    return run_forward<float>(L, spin, batch, plan->f32, ds, sp, map, flm, workspace, st);
+    if (precision == SHT_FP64)
+        return run_forward<double>(L, spin, batch, plan->f64, plan->rec, ds, sp, map, flm, workspace, st);
+    return run_forward<float>(L, spin, batch, plan->f32, plan->rec, ds, sp, map, flm, workspace, st);
 }
 
 int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) {
@@ -308,6 +316,8 @@ int sht_release_all(void) {
         (void)hipSetDevice(kv.second->device);
         if (hipFree(kv.second->f64.tw) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->f32.tw) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.ri) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.rf) != hipSuccess) rc = SHT_ERR_HIP;
         delete kv.second;
     }
     g_plans.clear();

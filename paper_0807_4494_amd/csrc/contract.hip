@@ -10,12 +10,13 @@
 //
 // M is never stored.  Each workgroup owns GM consecutive orders, a tile of TJ
 // output indices j (m' for the inverse, l for the forward) and up to CTILE
-// columns; every thread owns the Wigner chains of one j:
+// columns.  Its producer waves own the Wigner chains of the tile's j:
 //   inverse: chains in l (the GEMM's K axis) for (m', m) and (m', -s);
-//   forward: chains in m' (the K axis) for (l, m) and (l, -s).
-// The chains run in FP64 (chain.h), emit one K-slab of M into LDS per step
-// of TK, and the slab is multiplied on the matrix cores:
-//   out[c][j] += sum_k X^T[c][k] M[k][j]   (v_mfma 16x16x4, f32 or f64).
+//   forward: chains in m' (the K axis) for (l, m) and (l, -s),
+// run them in FP64 (chain.h) and emit one K-slab of M at a time into LDS;
+// its consumer waves multiply the previous slab on the matrix cores
+//   out[c][j] += sum_k X^T[c][k] M[k][j]   (v_mfma 16x16x4, f32 or f64)
+// while the producers fill the next one (double-buffered LDS).
 #include "chain.h"
 
 namespace sht {
@@ -44,13 +45,17 @@ template <> struct Mfma<double> {
     }
 };
 
+// Tile shapes.  A workgroup is 8 waves: waves 0-3 consume (MFMA), waves 4-7
+// produce (FP64 Wigner chains).  TJ output indices j per workgroup, WJ per
+// consumer wave; GM orders m; TK rows of K per slab.
 template <typename T> struct Tile;
-template <> struct Tile<float> { static constexpr int TJ = 256, WJ = 64; };
-template <> struct Tile<double> { static constexpr int TJ = 128, WJ = 32; };
+template <> struct Tile<float> { static constexpr int TJ = 128, WJ = 32; };
+template <> struct Tile<double> { static constexpr int TJ = 64, WJ = 16; };
 
-constexpr int GM = 2;   // orders per workgroup
-constexpr int TK = 16;  // K slab
-constexpr int NT = 256; // threads
+constexpr int GM = 4;    // orders per workgroup
+constexpr int TK = 16;   // K slab
+constexpr int NT = 512;  // threads: 256 consumers + 256 producers
+constexpr int NC = 256;  // consumer threads
 
 template <typename T> struct Args {
     int L, s, B, C;       // C = 4B columns
@@ -59,37 +64,236 @@ template <typename T> struct Args {
     T *Y;                 // [L][C][L]
     EdgeTable E;
     const SpinState *ss;  // [L][L], inverse only
+    const double *ri;     // [L][L] 1/sqrt((l+1)^2 - j^2)
+    const double *rf;     // [L][L] 1/sqrt((l+k)(l-k+1)) at [k][l]
 };
 
 template <typename T, int MODE, int CTILE>
 __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
     constexpr int TJ = Tile<T>::TJ, WJ = Tile<T>::WJ;
-    constexpr int NSUB = NT / TJ;   // threads sharing one j
-    constexpr int NCH = GM / NSUB;  // main chains per thread
+    constexpr int NPJ = NC / TJ;    // producer threads sharing one j
+    constexpr int NCH = GM / NPJ;   // main chains per producer thread
     constexpr int NCI = CTILE / 16, NJI = WJ / 16;
+    constexpr int XPT = GM * CTILE * TK / NC;  // X slab elements per consumer thread
     using acc_t = typename Mfma<T>::acc;
 
-    __shared__ T Mt[GM][TK][TJ];
-    __shared__ T Xt[GM][TK][CTILE];
-    __shared__ double fam[GM + 1][TK], fbm[GM + 1][TK], fcl[TK];
+    __shared__ T Mt[2][GM][TK][TJ];
+    __shared__ T Xt[2][GM][TK][CTILE];
+    __shared__ double fam[2][GM + 1][TK], fbm[2][GM + 1][TK], fcl[2][TK];
 
     const int L = a.L, s = a.s, Cn = a.C;
     const int sigma = -s, asg = s < 0 ? -s : s;
-    int bid = blockIdx.x;
-    const int cb = bid % a.ncb;
-    bid /= a.ncb;
-    const int jt = bid % a.njt;
-    const int mg = bid / a.njt;
+    // Hardware workgroup b runs on XCD b mod 8.  Order group mg goes to XCD
+    // mg mod 8 with all its j tiles and column blocks (they stream the same X
+    // panel through that XCD's L2); each XCD takes its groups in ascending
+    // order, which for the inverse is heaviest first.
+    const int tiles = a.njt * a.ncb;
+    const int xcd = (int)(blockIdx.x % 8), slot = (int)(blockIdx.x / 8);
+    const int mg = (slot / tiles) * 8 + xcd;
+    if (mg * GM >= a.L) return;
+    const int cb = (slot % tiles) % a.ncb;
+    const int jt = (slot % tiles) / a.ncb;
     const int m0 = mg * GM, j0 = jt * TJ, c0 = cb * CTILE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int jl = tid % TJ, sub = tid / TJ;
-    const int j = j0 + jl;
-    const bool jvalid = j < L;
+    const bool producer = tid >= NC;
 
     if (MODE == kForward) {
         // outputs l < max(m0, |s|) are never read
         const int need = m0 > asg ? m0 : asg;
         if (j0 + TJ - 1 < need) return;
+    }
+
+    // ---- K schedule (shared by both roles) ----
+    int kfirst, nchunks;
+    if (MODE == kInverse) {
+        const int l_lo = m0 > j0 ? m0 : j0;
+        kfirst = (l_lo / TK) * TK;
+        nchunks = (L - kfirst + TK - 1) / TK;
+    } else {
+        int top = j0 + TJ - 1;
+        if (top > L - 1) top = L - 1;
+        kfirst = ((top + TK) / TK) * TK - 1;  // chunk-aligned top, >= top
+        nchunks = (kfirst + 1) / TK;
+    }
+    auto kbase_of = [&](int chunk) {
+        return MODE == kInverse ? kfirst + chunk * TK : kfirst - (chunk + 1) * TK + 1;
+    };
+
+    // ---- producer state ----
+    const int ptid = tid - NC;
+    const int jl = producer ? ptid % TJ : 0, sub = producer ? ptid / TJ : 0;
+    const int j = j0 + jl;
+    const bool jvalid = producer && j < L;
+    Chain ch[NCH], sc;
+    int mch[NCH];
+    bool vch[NCH];
+    Seed seed[NCH], sseed;  // chain seeds, loaded once before the K loop
+    double q = 0.0, gprev = 0.0, clj = 0.0;
+    int l0s = 0;
+
+    // inverse: l-recursion factors of the workgroup's orders and of sigma for one slab
+    auto fill_factors = [&](int chunk, int buf) {
+        if (MODE == kInverse && producer && ptid < (GM + 1) * TK && chunk < nchunks) {
+            const int gi = ptid / TK, kk = ptid % TK;
+            const int l = kbase_of(chunk) + kk;
+            const int idx = gi < GM ? m0 + gi : sigma;
+            double am, bm;
+            lrec_factor_full(l, idx, am, bm);
+            fam[buf][gi][kk] = am;
+            fbm[buf][gi][kk] = bm;
+            if (gi == 0) fcl[buf][kk] = sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846));
+        }
+    };
+
+    if (producer) {
+#pragma unroll
+        for (int g = 0; g < NCH; ++g) {
+            mch[g] = m0 + sub * NCH + g;
+            ch[g].zero();
+        }
+        sc.zero();
+        if (MODE == kInverse) {
+#pragma unroll
+            for (int g = 0; g < NCH; ++g) vch[g] = jvalid && mch[g] < L;
+            l0s = j > asg ? j : asg;
+#pragma unroll
+            for (int g = 0; g < NCH; ++g) seed[g] = vch[g] ? edge_seed(a.E, j, mch[g]) : Seed{0.0, 0};
+            sseed = jvalid ? edge_seed(a.E, j, sigma) : Seed{0.0, 0};
+            if (jvalid && l0s < kfirst) {
+                const SpinState st = a.ss[(size_t)kfirst * L + j];
+                sc.d = st.d;
+                sc.dp = st.dp;
+                sc.k = st.k;
+                sc.es = emit_scale(st.k);
+            }
+            const double Y = (double)kfirst * kfirst - (double)j * j;
+            q = Y > 0.0 ? sqrt(Y) : 0.0;
+        } else {
+#pragma unroll
+            for (int g = 0; g < NCH; ++g) vch[g] = jvalid && mch[g] < L && j >= mch[g];
+            clj = sqrt((2.0 * j + 1.0) / (4.0 * 3.14159265358979323846));
+#pragma unroll
+            for (int g = 0; g < NCH; ++g) seed[g] = vch[g] ? edge_seed(a.E, j, mch[g]) : Seed{0.0, 0};
+            sseed = (jvalid && j >= asg) ? edge_seed(a.E, j, sigma) : Seed{0.0, 0};
+        }
+    }
+
+    // producers: emit slab `chunk` of M into Mt[buf]
+    auto generate = [&](int chunk, int buf) {
+        const int kbase = kbase_of(chunk);
+        // this slab's reciprocal square roots for the thread's j, loaded up front
+        double rr[TK];
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            const int k = kbase + kk;
+            const bool ok = jvalid && k >= 0 && k < L;
+            rr[kk] = ok ? (MODE == kInverse ? a.ri[(size_t)k * L + j] : a.rf[(size_t)k * L + j]) : 0.0;
+        }
+        if (MODE == kInverse) {
+#pragma unroll 4
+            for (int kk = 0; kk < TK; ++kk) {
+                const int l = kbase + kk;
+                if (l == l0s && jvalid) sc.inject(sseed);
+#pragma unroll
+                for (int g = 0; g < NCH; ++g) {
+                    const int l0 = j > mch[g] ? j : mch[g];
+                    if (vch[g] && l == l0) ch[g].inject(seed[g]);
+                }
+                const double W = (l < L) ? fcl[buf][kk] * sc.value() : 0.0;
+#pragma unroll
+                for (int g = 0; g < NCH; ++g)
+                    Mt[buf][sub * NCH + g][kk][jl] = (T)(vch[g] ? ch[g].value() * W : 0.0);
+                // step l -> l+1
+                const double Xl = (double)(l + 1) * (l + 1) - (double)j * j;
+                const double r = rr[kk];
+                const double ap = (double)j * r, bp = q * r;
+                q = Xl * r;
+                {
+                    const double dn = -(ap * fam[buf][GM][kk] * sc.d + bp * fbm[buf][GM][kk] * sc.dp);
+                    if (l >= l0s) sc.push(dn);
+                }
+#pragma unroll
+                for (int g = 0; g < NCH; ++g) {
+                    const int gi = sub * NCH + g;
+                    const double dn = -(ap * fam[buf][gi][kk] * ch[g].d + bp * fbm[buf][gi][kk] * ch[g].dp);
+                    const int l0 = j > mch[g] ? j : mch[g];
+                    if (l >= l0) ch[g].push(dn);
+                }
+            }
+        } else {
+#pragma unroll 4
+            for (int kk = TK - 1; kk >= 0; --kk) {
+                const int k = kbase + kk;  // m'
+                if (k == j && jvalid) {
+                    if (j >= asg) sc.inject(sseed);
+#pragma unroll
+                    for (int g = 0; g < NCH; ++g)
+                        if (vch[g]) ch[g].inject(seed[g]);
+                    gprev = 0.0;
+                }
+                const bool live = k >= 0 && k <= j && jvalid;
+                const double W = live ? clj * sc.value() : 0.0;
+#pragma unroll
+                for (int g = 0; g < NCH; ++g)
+                    Mt[buf][sub * NCH + g][kk][jl] = (T)(vch[g] ? ch[g].value() * W : 0.0);
+                // step m' -> m'-1
+                const double Xk = (double)(j + k) * (double)(j - k + 1);
+                const double y = rr[kk];
+                const double gcur = Xk * y;
+                if (live) {
+                    sc.push((2.0 * sigma * sc.d - gprev * sc.dp) * y);
+#pragma unroll
+                    for (int g = 0; g < NCH; ++g)
+                        ch[g].push((2.0 * mch[g] * ch[g].d - gprev * ch[g].dp) * y);
+                }
+                gprev = gcur;
+            }
+        }
+    };
+
+    // consumers: X slab for `chunk` into registers, then into Xt[buf]
+    T xr[XPT];
+    auto load_x = [&](int chunk) {
+        const int kbase = kbase_of(chunk);
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int e = tid + i * NC;           // over [GM][CTILE][TK]
+            const int g = e / (CTILE * TK), rem = e % (CTILE * TK);
+            const int c = rem / TK, kk = rem % TK;
+            const int m = m0 + g, k = kbase + kk;
+            bool ok = m < L && (c0 + c) < Cn && k >= 0 && k < L;
+            if (MODE == kInverse) ok = ok && k >= m;
+            xr[i] = ok ? a.X[((size_t)m * Cn + c0 + c) * L + k] : T(0);
+        }
+    };
+    auto store_x = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int e = tid + i * NC;
+            const int g = e / (CTILE * TK), rem = e % (CTILE * TK);
+            const int c = rem / TK, kk = rem % TK;
+            Xt[buf][g][kk][c] = xr[i];
+        }
+    };
+
+    // ---- pipeline: producers run one slab ahead of the consumers.  Each role
+    // has its own loop (disjoint register live ranges); both execute the same
+    // number of workgroup barriers, and every wave takes one role as a whole.
+    if (producer) {
+        fill_factors(0, 0);
+        __syncthreads();
+        generate(0, 0);
+        fill_factors(1, 1);
+        __syncthreads();
+        for (int chunk = 1; chunk <= nchunks; ++chunk) {
+            const int cur = chunk & 1, prev = cur ^ 1;
+            if (chunk < nchunks) {
+                generate(chunk, cur);
+                fill_factors(chunk + 1, prev);
+            }
+            __syncthreads();
+        }
+        return;
     }
 
     acc_t acc[GM][NCI][NJI];
@@ -100,140 +304,9 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
 #pragma unroll
             for (int ji = 0; ji < NJI; ++ji) acc[g][ci][ji] = acc_t{0, 0, 0, 0};
 
-    Chain ch[NCH], sc;
-    int mch[NCH];
-    bool vch[NCH];
-#pragma unroll
-    for (int g = 0; g < NCH; ++g) {
-        mch[g] = m0 + sub * NCH + g;
-        ch[g].zero();
-    }
-    sc.zero();
-
-    // K range and per-thread chain bookkeeping
-    int kfirst, klast;  // inclusive, in iteration order
-    double q = 0.0;     // inverse: sqrt(l^2 - m'^2) at the current l
-    double gprev = 0.0; // forward: sqrt((l+m'+1)(l-m')) for the previous m'
-    double clj = 0.0;   // forward: sqrt((2l+1)/4pi)
-    int l0s = 0;
-    if (MODE == kInverse) {
-        const int l_lo = m0 > j0 ? m0 : j0;
-        kfirst = (l_lo / TK) * TK;
-        klast = L - 1;
-#pragma unroll
-        for (int g = 0; g < NCH; ++g) vch[g] = jvalid && mch[g] < L;
-        l0s = j > asg ? j : asg;
-        if (jvalid && l0s < kfirst) {
-            const SpinState st = a.ss[(size_t)kfirst * L + j];
-            sc.d = st.d;
-            sc.dp = st.dp;
-            sc.k = st.k;
-            sc.es = emit_scale(st.k);
-        }
-        const double Y = (double)kfirst * kfirst - (double)j * j;
-        q = Y > 0.0 ? sqrt(Y) : 0.0;
-    } else {
-        int top = j0 + TJ - 1;
-        if (top > L - 1) top = L - 1;
-        kfirst = ((top + TK) / TK) * TK - 1;  // chunk-aligned top, >= top
-        klast = 0;
-#pragma unroll
-        for (int g = 0; g < NCH; ++g) vch[g] = jvalid && mch[g] < L && j >= mch[g];
-        clj = sqrt((2.0 * j + 1.0) / (4.0 * 3.14159265358979323846));
-    }
-
-    const int nchunks = MODE == kInverse ? (L - kfirst + TK - 1) / TK : (kfirst + 1) / TK;
-    for (int chunk = 0; chunk < nchunks; ++chunk) {
-        // K rows kk = 0..TK-1 of this slab correspond to k = kbase + kk
-        const int kbase = MODE == kInverse ? kfirst + chunk * TK : kfirst - (chunk + 1) * TK + 1;
-
-        if (MODE == kInverse && tid < (GM + 1) * TK) {
-            const int gi = tid / TK, kk = tid % TK;
-            const int l = kbase + kk;
-            const int idx = gi < GM ? m0 + gi : sigma;
-            double am, bm;
-            lrec_factor_full(l, idx, am, bm);
-            fam[gi][kk] = am;
-            fbm[gi][kk] = bm;
-            if (gi == 0) fcl[kk] = sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846));
-        }
-        // X slab: Xt[g][kk][c] = X[m0+g][c0+c][kbase+kk]
-#pragma unroll
-        for (int g = 0; g < GM; ++g) {
-            const int m = m0 + g;
-            for (int e = tid; e < CTILE * TK; e += NT) {
-                const int c = e / TK, kk = e % TK;
-                const int k = kbase + kk;
-                bool ok = m < L && (c0 + c) < Cn && k >= 0 && k < L;
-                if (MODE == kInverse) ok = ok && k >= m;
-                Xt[g][kk][c] = ok ? a.X[((size_t)m * Cn + c0 + c) * L + k] : T(0);
-            }
-        }
-        __syncthreads();
-
-        // ---- generate the M slab ----
-        if (MODE == kInverse) {
-            for (int kk = 0; kk < TK; ++kk) {
-                const int l = kbase + kk;
-                if (l == l0s && jvalid) sc.inject(edge_seed(a.E, j, sigma));
-#pragma unroll
-                for (int g = 0; g < NCH; ++g) {
-                    const int l0 = j > mch[g] ? j : mch[g];
-                    if (vch[g] && l == l0) ch[g].inject(edge_seed(a.E, j, mch[g]));
-                }
-                const double W = (l < L) ? fcl[kk] * sc.value() : 0.0;
-#pragma unroll
-                for (int g = 0; g < NCH; ++g)
-                    Mt[sub * NCH + g][kk][jl] = (T)(vch[g] ? ch[g].value() * W : 0.0);
-                // step l -> l+1
-                const double Xl = (double)(l + 1) * (l + 1) - (double)j * j;
-                const double r = rsqrt(Xl > 1.0 ? Xl : 1.0);
-                const double ap = (double)j * r, bp = q * r;
-                q = Xl > 0.0 ? Xl * r : 0.0;
-                {
-                    const double dn = -(ap * fam[GM][kk] * sc.d + bp * fbm[GM][kk] * sc.dp);
-                    if (l >= l0s) sc.push(dn);
-                }
-#pragma unroll
-                for (int g = 0; g < NCH; ++g) {
-                    const int gi = sub * NCH + g;
-                    const double dn = -(ap * fam[gi][kk] * ch[g].d + bp * fbm[gi][kk] * ch[g].dp);
-                    const int l0 = j > mch[g] ? j : mch[g];
-                    if (l >= l0) ch[g].push(dn);
-                }
-            }
-        } else {
-            for (int kk = TK - 1; kk >= 0; --kk) {
-                const int k = kbase + kk;  // m'
-                if (k == j && jvalid) {
-                    if (j >= asg) sc.inject(edge_seed(a.E, j, sigma));
-#pragma unroll
-                    for (int g = 0; g < NCH; ++g)
-                        if (vch[g]) ch[g].inject(edge_seed(a.E, j, mch[g]));
-                    gprev = 0.0;
-                }
-                const bool live = k >= 0 && k <= j && jvalid;
-                const double W = live ? clj * sc.value() : 0.0;
-#pragma unroll
-                for (int g = 0; g < NCH; ++g)
-                    Mt[sub * NCH + g][kk][jl] = (T)(vch[g] ? ch[g].value() * W : 0.0);
-                // step m' -> m'-1
-                const double Xk = (double)(j + k) * (double)(j - k + 1);
-                const double y = rsqrt(Xk > 1.0 ? Xk : 1.0);
-                const double gcur = Xk > 0.0 ? Xk * y : 0.0;
-                if (live) {
-                    sc.push((2.0 * sigma * sc.d - gprev * sc.dp) * y);
-#pragma unroll
-                    for (int g = 0; g < NCH; ++g)
-                        ch[g].push((2.0 * mch[g] * ch[g].d - gprev * ch[g].dp) * y);
-                }
-                gprev = gcur;
-            }
-        }
-        __syncthreads();
-
-        // ---- matrix cores ----
-        const int wj0 = j0 + wave * WJ;  // first j of this wave
+    auto mfma_slab = [&](int chunk, int buf) {
+        const int kbase = kbase_of(chunk);
+        const int wj0 = j0 + wave * WJ;  // first j of this consumer wave
         bool active;
         if (MODE == kInverse) {
             const int start = m0 > wj0 ? m0 : wj0;
@@ -241,25 +314,41 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
         } else {
             active = kbase <= wj0 + WJ - 1 && wj0 < L;
         }
-        if (active) {
+        if (!active) return;
+        // operand fragments double-buffered: group idx+1 is read from LDS while
+        // the MFMAs of group idx run
+        constexpr int NKS = TK / 4, NGRP = GM * NKS;
+        T av[2][NCI], bv[2][NJI];
+        auto ldfrag = [&](int idx, int slot) {
+            const int g = idx / NKS, ks = idx % NKS;
+            const int kr = ks * 4 + (lane >> 4);
 #pragma unroll
-            for (int g = 0; g < GM; ++g) {
+            for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = Xt[buf][g][kr][ci * 16 + (lane & 15)];
 #pragma unroll
-                for (int ks = 0; ks < TK / 4; ++ks) {
-                    const int kr = ks * 4 + (lane >> 4);
-                    T av[NCI], bv[NJI];
+            for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = Mt[buf][g][kr][wave * WJ + ji * 16 + (lane & 15)];
+        };
+        ldfrag(0, 0);
 #pragma unroll
-                    for (int ci = 0; ci < NCI; ++ci) av[ci] = Xt[g][kr][ci * 16 + (lane & 15)];
+        for (int idx = 0; idx < NGRP; ++idx) {
+            if (idx + 1 < NGRP) ldfrag(idx + 1, (idx + 1) & 1);
+            const int g = idx / NKS;
 #pragma unroll
-                    for (int ji = 0; ji < NJI; ++ji) bv[ji] = Mt[g][kr][wave * WJ + ji * 16 + (lane & 15)];
+            for (int ci = 0; ci < NCI; ++ci)
 #pragma unroll
-                    for (int ci = 0; ci < NCI; ++ci)
-#pragma unroll
-                        for (int ji = 0; ji < NJI; ++ji)
-                            acc[g][ci][ji] = Mfma<T>::op(av[ci], bv[ji], acc[g][ci][ji]);
-                }
-            }
+                for (int ji = 0; ji < NJI; ++ji)
+                    acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci], bv[idx & 1][ji], acc[g][ci][ji]);
         }
+    };
+
+    __syncthreads();
+    load_x(0);
+    store_x(0);
+    __syncthreads();
+    for (int chunk = 1; chunk <= nchunks; ++chunk) {
+        const int cur = chunk & 1, prev = cur ^ 1;
+        if (chunk < nchunks) load_x(chunk);
+        mfma_slab(chunk - 1, prev);
+        if (chunk < nchunks) store_x(cur);
         __syncthreads();
     }
 
@@ -282,9 +371,9 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
 }
 
 template <typename T, int MODE, int CTILE>
-hipError_t launch_one(const Args<T> &a, hipStream_t st) {
+hipError_t launch_one(Args<T> a, hipStream_t st) {
     const int nmg = (a.L + GM - 1) / GM;
-    const dim3 grid(nmg * a.njt * a.ncb);
+    const dim3 grid(8 * ((nmg + 7) / 8) * a.njt * a.ncb);  // 8 XCDs x groups per XCD x tiles
     hipLaunchKernelGGL((k_contract<T, MODE, CTILE>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }
@@ -293,7 +382,7 @@ hipError_t launch_one(const Args<T> &a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
-                           const SpinState *ss, hipStream_t st) {
+                           const SpinState *ss, const RecTables &rt, hipStream_t st) {
     Args<T> a;
     a.L = L;
     a.s = s;
@@ -304,6 +393,8 @@ hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, cons
     a.Y = Y;
     a.E = E;
     a.ss = ss;
+    a.ri = rt.ri;
+    a.rf = rt.rf;
     if (a.C <= 16) {
         a.ncb = 1;
         return mode == kInverse ? launch_one<T, kInverse, 16>(a, st) : launch_one<T, kForward, 16>(a, st);
@@ -313,9 +404,9 @@ hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, cons
 }
 
 template hipError_t launch_contract<double>(int, int, int, int, const double *, double *, const EdgeTable &,
-                                            const SpinState *, hipStream_t);
+                                            const SpinState *, const RecTables &, hipStream_t);
 template hipError_t launch_contract<float>(int, int, int, int, const float *, float *, const EdgeTable &,
-                                           const SpinState *, hipStream_t);
+                                           const SpinState *, const RecTables &, hipStream_t);
 
 hipError_t launch_contract_bf16x3(int, int, int, int, const float *, float *, const EdgeTable &,
                                   const SpinState *, hipStream_t) {

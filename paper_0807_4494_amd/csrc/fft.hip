@@ -4,19 +4,31 @@
 //
 // Every stage is a chirp-z (Bluestein) row transform
 //     y_k = b_k sum_{n < nin} (a_n x_n) c_{k-n},      k < kout,
-// evaluated as a cyclic convolution of power-of-two length M >= nin + kout - 1
-// in LDS: a decimation-in-frequency FFT (bit-reversed output), a product with
-// the kernel spectrum (stored bit-reversed, 1/M folded in), and an inverse
-// decimation-in-time FFT that takes bit-reversed input.  No bit reversal is
-// ever performed.  The chirps are e^{i pi k / N} with k reduced mod 2N in
-// integer arithmetic.  One workgroup transforms one row.
+// evaluated as a cyclic convolution of power-of-two length M >= nin + kout - 1:
+// a Stockham FFT (radix 16 passes, one 2/4/8 pass when log2 M is not a
+// multiple of 4) whose first pass reads the row straight from HBM with the
+// chirp applied and whose last pass multiplies by the plan kernel's spectrum
+// (1/M folded in), then the inverse FFT as conj(FFT(conj(.))) whose last pass
+// writes the wanted outputs straight to HBM.  Intermediate passes stay in LDS.
+// The chirps are e^{i pi k / N} with k reduced mod 2N in integer arithmetic.
+// One workgroup of M/16 threads transforms one row; each thread holds 16
+// points in registers during every pass.
+#include <type_traits>
+
 #include "sht_internal.h"
 
 namespace sht {
 
 namespace {
 
-constexpr int kRowThreads = 256;
+constexpr int kMaxRowThreads = 512;  // M / 16 threads per row, M <= 8192
+
+// Threads per row: each thread owns 16 of the M points in every pass.
+inline int row_threads(int M) { return M / 16 < 64 ? 64 : M / 16; }
+
+// LDS slot of point i: one pad slot after every 16 points, so that the
+// stride-16 accesses of the Stockham passes spread over the banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
 __device__ inline long long mod2n(long long x, long long twoN) {
     long long r = x % twoN;
@@ -33,43 +45,159 @@ __device__ inline C rot_ipow(C v, int k) {  // v * i^k
     }
 }
 
-template <typename C>
-__device__ void fft_dif(C *buf, const C *tw, int M, int logM) {
-    for (int lg = logM; lg >= 1; --lg) {
-        const int len = 1 << lg, half = len >> 1, stride = M >> lg;
-        for (int idx = threadIdx.x; idx < (M >> 1); idx += blockDim.x) {
-            const int j = idx & (half - 1);
-            const int i0 = ((idx >> (lg - 1)) << lg) + j, i1 = i0 + half;
-            const C u = buf[i0], v = buf[i1];
-            buf[i0] = cadd(u, v);
-            buf[i1] = cmul(csub(u, v), tw[j * stride]);
-        }
-        __syncthreads();
-    }
+template <typename C> __device__ inline C conj(C v) { return C{v.x, -v.y}; }
+template <typename C> __device__ inline C mul_mi(C v) { return C{v.y, -v.x}; }  // v * (-i)
+
+// ---- in-register forward DFTs (sign e^{-2 pi i n k / R}) ----
+template <typename C> __device__ inline void dft2(C &a, C &b) {
+    const C t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
 }
 
-template <typename C>
-__device__ void fft_dit_inv(C *buf, const C *tw, int M, int logM) {
-    for (int lg = 1; lg <= logM; ++lg) {
-        const int len = 1 << lg, half = len >> 1, stride = M >> lg;
-        for (int idx = threadIdx.x; idx < (M >> 1); idx += blockDim.x) {
-            const int j = idx & (half - 1);
-            const int i0 = ((idx >> (lg - 1)) << lg) + j, i1 = i0 + half;
-            const C u = buf[i0], v = cmulc(buf[i1], tw[j * stride]);
-            buf[i0] = cadd(u, v);
-            buf[i1] = csub(u, v);
-        }
-        __syncthreads();
-    }
+template <typename C> __device__ inline void dft4(C &x0, C &x1, C &x2, C &x3) {
+    const C t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3), t3 = mul_mi(csub(x1, x3));
+    x0 = cadd(t0, t2);
+    x2 = csub(t0, t2);
+    x1 = cadd(t1, t3);
+    x3 = csub(t1, t3);
 }
 
-// buf <- IFFT(FFT(buf) * H): the cyclic convolution with the plan kernel.
-template <typename C>
-__device__ void convolve(C *buf, const C *H, const C *tw, int M, int logM) {
-    fft_dif(buf, tw, M, logM);
-    for (int i = threadIdx.x; i < M; i += blockDim.x) buf[i] = cmul(buf[i], H[i]);
+// 8 = 4 x 2: n = n1 + 2 n2, k = 4 k1' ... written out as two radix-4 on even/odd
+template <typename C, typename T> __device__ inline void dft8(C *v) {
+    // x[n1 + 2 n2]: radix-4 over n2 for n1 = 0, 1
+    dft4(v[0], v[2], v[4], v[6]);
+    dft4(v[1], v[3], v[5], v[7]);
+    // twiddle W8^{n1 k1} on the odd branch
+    const T h = T(0.70710678118654752440084436210485);
+    v[3] = C{(v[3].x + v[3].y) * h, (v[3].y - v[3].x) * h};   // * e^{-i pi/4}
+    v[5] = mul_mi(v[5]);                                       // * e^{-i pi/2}
+    v[7] = C{(v[7].y - v[7].x) * h, -(v[7].x + v[7].y) * h};  // * e^{-3 i pi/4}
+    // radix-2 over n1; outputs X[k1 + 4 k2]
+    C o[8];
+    o[0] = cadd(v[0], v[1]); o[4] = csub(v[0], v[1]);
+    o[1] = cadd(v[2], v[3]); o[5] = csub(v[2], v[3]);
+    o[2] = cadd(v[4], v[5]); o[6] = csub(v[4], v[5]);
+    o[3] = cadd(v[6], v[7]); o[7] = csub(v[6], v[7]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = o[i];
+}
+
+// 16 = 4 x 4: x[n1 + 4 n2] -> DFT4 over n2 -> W16^{n1 k1} -> DFT4 over n1 -> X[k1 + 4 k2]
+template <typename C, typename T> __device__ inline void dft16(C *v) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) dft4(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
+    // v[n1 + 4 k1] now holds Y[n1][k1]
+    const T c1 = T(0.92387953251128675612818318939679), s1 = T(0.38268343236508977172845998403040);
+    const T h = T(0.70710678118654752440084436210485);
+    auto tw = [&](C a, T c, T s) { return C{a.x * c + a.y * s, a.y * c - a.x * s}; };  // a * e^{-i theta}
+    v[5] = tw(v[5], c1, s1);     // W16^1
+    v[9] = tw(v[9], h, h);       // W16^2
+    v[13] = tw(v[13], s1, c1);   // W16^3
+    v[6] = tw(v[6], h, h);       // W16^2
+    v[10] = mul_mi(v[10]);       // W16^4
+    v[14] = tw(v[14], -h, h);    // W16^6
+    v[7] = tw(v[7], s1, c1);     // W16^3
+    v[11] = tw(v[11], -h, h);    // W16^6
+    v[15] = tw(v[15], -c1, -s1); // W16^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] holds X[k1 + 4 k2]; transpose to natural order
+    C o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = o[i];
+}
+
+template <int R, typename C, typename T> __device__ inline void dft_r(C *v) {
+    if constexpr (R == 2) dft2(v[0], v[1]);
+    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<C, T>(v);
+    else dft16<C, T>(v);
+}
+
+// One Stockham radix-R pass over M points, in place in LDS or from/to the
+// caller's functors.  Butterfly j < M/R reads src[j + r M/R], multiplies by
+// w^{r (j mod Ns)} with w = e^{-2 pi i / (Ns R)}, takes the R-point DFT and
+// writes dst[(j div Ns) Ns R + (j mod Ns) + r Ns].  All reads finish (barrier)
+// before any write, so src and dst may be the same LDS buffer.
+template <int R, int LOGM, int LOGNS, typename T, typename Ld, typename St>
+__device__ __forceinline__ void stockham_pass(const typename CT<T>::type *tw, Ld ld, St st) {
+    using C = typename CT<T>::type;
+    constexpr int LOGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+    constexpr int M = 1 << LOGM;
+    constexpr int nb = M >> LOGR;
+    constexpr int nt = (M / 16) < 64 ? 64 : (M / 16);  // threads per row
+    constexpr int NP = (nb + nt - 1) / nt;               // butterflies per thread
+    constexpr int logNs = LOGNS;
+    C v[NP][R];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int j = threadIdx.x + q * nt;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = ld(j + r * nb);
+        }
+    }
     __syncthreads();
-    fft_dit_inv(buf, tw, M, logM);
+    constexpr int tshift = LOGM - LOGNS - LOGR;  // twiddle stride M / (Ns R)
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int j = threadIdx.x + q * nt;
+        if (j < nb) {
+            const int k = j & ((1 << logNs) - 1);
+            if constexpr (LOGNS > 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[((r * k) << tshift) & (M - 1)]);
+            }
+            dft_r<R, C, T>(v[q]);
+            const int base = ((j >> logNs) << (logNs + LOGR)) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) st(base + (r << logNs), v[q][r]);
+        }
+    }
+    __syncthreads();
+}
+
+// Forward DFT of M = 2^LOGM points: the first pass reads ld(n), the last pass
+// hands output k to st(k, X_k); intermediate passes live in buf (LDS).  The
+// first pass has radix 2^(LOGM mod 4) when LOGM is not a multiple of 4, all
+// others radix 16.
+template <int LOGM, int P, int LOGNS, typename T, typename Ld, typename St>
+__device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const typename CT<T>::type *tw, Ld ld,
+                                           St st) {
+    using C = typename CT<T>::type;
+    constexpr int R0 = LOGM & 3;
+    constexpr int NPASS = (LOGM + 3) / 4;
+    constexpr int LR = (P == 0 && R0) ? R0 : 4;
+    constexpr int RR = 1 << LR;
+    constexpr bool FIRST = P == 0, LAST = P == NPASS - 1;
+    auto lbuf = [buf](int n) { return buf[pad(n)]; };
+    auto sbuf = [buf](int k, C x) { buf[pad(k)] = x; };
+    if constexpr (FIRST && LAST) stockham_pass<RR, LOGM, LOGNS, T>(tw, ld, st);
+    else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T>(tw, ld, sbuf);
+    else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T>(tw, lbuf, st);
+    else stockham_pass<RR, LOGM, LOGNS, T>(tw, lbuf, sbuf);
+    if constexpr (!LAST) fft_passes<LOGM, P + 1, LOGNS + LR, T>(buf, tw, ld, st);
+}
+
+template <int LOGM, typename T, typename Ld, typename St>
+__device__ __forceinline__ void fft_run(typename CT<T>::type *buf, const typename CT<T>::type *tw, Ld ld, St st) {
+    fft_passes<LOGM, 0, 0, T>(buf, tw, ld, st);
+}
+
+// Cyclic convolution with a plan kernel of spectrum H (natural order, 1/M
+// folded in): y = IFFT(FFT(x) H), the inverse taken as conj(FFT(conj(.))).
+// x is read through ld(n); y_k is handed to st(k, y_k).
+template <int LOGM, typename T, typename Ld, typename St>
+__device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typename CT<T>::type *H,
+                                         const typename CT<T>::type *tw, Ld ld, St st) {
+    using C = typename CT<T>::type;
+    fft_run<LOGM, T>(buf, tw, ld, [buf, H](int k, C x) { buf[pad(k)] = conj(cmul(x, H[k])); });
+    fft_run<LOGM, T>(buf, tw, [buf](int n) { return buf[pad(n)]; }, [&st](int k, C x) { st(k, conj(x)); });
 }
 
 // ---------------------------------------------------------------- kernels --
@@ -81,14 +209,14 @@ __device__ void convolve(C *buf, const C *H, const C *tw, int M, int logM) {
 // F_{mu,-m'} = (-1)^{mu+s} F_{mu m'} (Eq. (Ffourier_sym)); then
 //   g_mu(theta_t) = sum_{m'} F_{mu m'} e^{i m' theta_t},  t < L.
 // Output G[b][t][mu + L - 1].
-template <typename T>
-__global__ __launch_bounds__(kRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B,
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B,
                                                            const T *__restrict__ R,
                                                            typename CT<T>::type *__restrict__ G) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int L = ft.L, N = ft.N, M = ft.M, h = L - 1;
+    const int L = ft.L, N = ft.N, h = L - 1;
     const long long twoN = 2LL * N;
     const int row = blockIdx.x;
     const int mu_idx = row % N, b = row / N;
@@ -99,75 +227,73 @@ __global__ __launch_bounds__(kRowThreads) void k_theta_inv(FftTables<T> ft, int 
     const int phase = -(mu + s);                 // i^{-(mu+s)}
     const T sgn_s = (s & 1) ? T(-1) : T(1);
     const int fill_odd = parity((long long)mu + s);
-    for (int n = threadIdx.x; n < M; n += blockDim.x) {
-        C x{T(0), T(0)};
-        if (n < N) {
-            const int mp = n - h, amp = mp < 0 ? -mp : mp;
-            C F{Rre[amp] * sgn_s, Rim[amp] * sgn_s};
-            F = rot_ipow(F, phase);
-            int flip = (neg && (amp & 1)) ^ (mp < 0 && fill_odd);
-            if (flip) F = C{-F.x, -F.y};
-            x = cmul(F, ft.e2n[mod2n((long long)n * n + n, twoN)]);
-        }
-        buf[n] = x;
-    }
-    __syncthreads();
-    convolve(buf, ft.h_it, ft.tw, M, ft.logM);
-    for (int t = threadIdx.x; t < L; t += blockDim.x) {
-        const C y = cmul(buf[t], ft.e2n[mod2n((long long)t * t - 2LL * h * t - h, twoN)]);
-        G[((size_t)b * L + t) * N + mu_idx] = y;
-    }
+    const C *e2n = ft.e2n;
+    auto ld = [&](int n) -> C {
+        if (n >= N) return C{T(0), T(0)};
+        const int mp = n - h, amp = mp < 0 ? -mp : mp;
+        C F{Rre[amp] * sgn_s, Rim[amp] * sgn_s};
+        F = rot_ipow(F, phase);
+        const int flip = (neg && (amp & 1)) ^ (mp < 0 && fill_odd);
+        if (flip) F = C{-F.x, -F.y};
+        return cmul(F, e2n[mod2n((long long)n * n + n, twoN)]);
+    };
+    C *Gb = G + (size_t)b * L * N + mu_idx;
+    auto st = [&](int t, C y) {
+        if (t < L) Gb[(size_t)t * N] = cmul(y, e2n[mod2n((long long)t * t - 2LL * h * t - h, twoN)]);
+    };
+    convolve<LOGM, T>(buf, ft.h_it, ft.tw, ld, st);
 }
 
 // Inverse phi stage.  Row (b, t): f(theta_t, phi_p) = sum_mu g_mu(theta_t) e^{i mu phi_p}.
-template <typename T>
-__global__ __launch_bounds__(kRowThreads) void k_phi_inv(FftTables<T> ft,
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft,
                                                          const typename CT<T>::type *__restrict__ G,
                                                          typename CT<T>::type *__restrict__ map) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int L = ft.L, N = ft.N, M = ft.M, h = L - 1;
+    const int L = ft.L, N = ft.N, h = L - 1;
     const long long twoN = 2LL * N;
     const size_t row = blockIdx.x;
     const C *in = G + row * N;
-    for (int n = threadIdx.x; n < M; n += blockDim.x) {
-        C x{T(0), T(0)};
-        if (n < N) x = cmul(in[n], ft.e2n[mod2n((long long)n * n + n, twoN)]);
-        buf[n] = x;
-    }
-    __syncthreads();
-    convolve(buf, ft.h_ip, ft.tw, M, ft.logM);
     C *out = map + row * N;
-    for (int p = threadIdx.x; p < N; p += blockDim.x)
-        out[p] = cmul(buf[p], ft.e2n[mod2n((long long)p * p - 2LL * h * p - h, twoN)]);
+    const C *e2n = ft.e2n;
+    auto ld = [&](int n) -> C {
+        if (n >= N) return C{T(0), T(0)};
+        return cmul(in[n], e2n[mod2n((long long)n * n + n, twoN)]);
+    };
+    auto st = [&](int p, C y) {
+        if (p < N) out[p] = cmul(y, e2n[mod2n((long long)p * p - 2LL * h * p - h, twoN)]);
+    };
+    convolve<LOGM, T>(buf, ft.h_ip, ft.tw, ld, st);
 }
 
 // Forward phi stage.  Row (b, t): Q_mu(t) = N^-1 sum_p f(theta_t, phi_p) e^{-i mu phi_p}.
-template <typename T>
-__global__ __launch_bounds__(kRowThreads) void k_phi_fwd(FftTables<T> ft,
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
                                                          const typename CT<T>::type *__restrict__ map,
                                                          typename CT<T>::type *__restrict__ Q) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int L = ft.L, N = ft.N, M = ft.M, h = L - 1;
+    const int L = ft.L, N = ft.N, h = L - 1;
     const long long twoN = 2LL * N;
     const size_t row = blockIdx.x;
     const C *in = map + row * N;
-    for (int n = threadIdx.x; n < M; n += blockDim.x) {
-        C x{T(0), T(0)};
-        if (n < N) x = cmul(in[n], ft.e2n[mod2n(-((long long)n * n - 2LL * h * n - h), twoN)]);
-        buf[n] = x;
-    }
-    __syncthreads();
-    convolve(buf, ft.h_fd, ft.tw, M, ft.logM);
-    const T invN = T(1) / T(N);
     C *out = Q + row * N;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        const C y = cmul(buf[k], ft.e2n[mod2n(-((long long)k * k + k), twoN)]);
-        out[k] = C{y.x * invN, y.y * invN};
-    }
+    const C *e2n = ft.e2n;
+    const T invN = T(1) / T(N);
+    auto ld = [&](int n) -> C {
+        if (n >= N) return C{T(0), T(0)};
+        return cmul(in[n], e2n[mod2n(-((long long)n * n - 2LL * h * n - h), twoN)]);
+    };
+    auto st = [&](int k, C y) {
+        if (k < N) {
+            const C z = cmul(y, e2n[mod2n(-((long long)k * k + k), twoN)]);
+            out[k] = C{z.x * invN, z.y * invN};
+        }
+    };
+    convolve<LOGM, T>(buf, ft.h_fd, ft.tw, ld, st);
 }
 
 // Forward theta stage.  Row (b, mu): parity extension of Q_mu to the torus
@@ -179,75 +305,72 @@ __global__ __launch_bounds__(kRowThreads) void k_phi_fwd(FftTables<T> ft,
 // Written as X[|mu|][c][m'] with c = q*B + b (q = 0,1 for mu >= 0, 2,3 for
 // mu < 0), times (-1)^{m'} for mu < 0 (the d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
 // symmetry; the (-1)^l part is applied on output).
-template <typename T>
-__global__ __launch_bounds__(kRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B,
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B,
                                                            const typename CT<T>::type *__restrict__ Q,
                                                            T *__restrict__ X) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int L = ft.L, N = ft.N, M = ft.M, h = L - 1;
+    const int L = ft.L, N = ft.N, h = L - 1;
     const long long twoN = 2LL * N;
     const int row = blockIdx.x;
     const int mu_idx = row % N, b = row / N;
     const int mu = mu_idx - h, m = mu < 0 ? -mu : mu, neg = mu < 0;
     const int ext_odd = parity((long long)mu + s);
     const C *Qb = Q + (size_t)b * L * N + mu_idx;
-    for (int n = threadIdx.x; n < M; n += blockDim.x) {
-        C x{T(0), T(0)};
-        if (n < N) {
-            if (n < L) {
-                x = Qb[(size_t)n * N];
-            } else {
-                x = Qb[(size_t)(2 * L - 2 - n) * N];
-                if (ext_odd) x = C{-x.x, -x.y};
-            }
-            x = cmul(x, ft.e2n[mod2n(-((long long)n * n - 2LL * h * n - h), twoN)]);
-        }
-        buf[n] = x;
-    }
-    __syncthreads();
-    convolve(buf, ft.h_fd, ft.tw, M, ft.logM);
+    const C *e2n = ft.e2n;
     const T invN = T(1) / T(N);
-    for (int k = threadIdx.x; k < M; k += blockDim.x) {
-        C y{T(0), T(0)};
-        if (k < N) {
-            y = cmul(buf[k], ft.e2n[mod2n(-((long long)k * k + k), twoN)]);
-            y = C{y.x * invN, y.y * invN};
+    auto ld = [&](int n) -> C {
+        if (n >= N) return C{T(0), T(0)};
+        C x;
+        if (n < L) {
+            x = Qb[(size_t)n * N];
+        } else {
+            x = Qb[(size_t)(2 * L - 2 - n) * N];
+            if (ext_odd) x = C{-x.x, -x.y};
         }
-        buf[k] = y;
-    }
-    __syncthreads();
-    convolve(buf, ft.h_fk, ft.tw, M, ft.logM);
+        return cmul(x, e2n[mod2n(-((long long)n * n - 2LL * h * n - h), twoN)]);
+    };
+    // the theta DFT lands in LDS (zero beyond N) as the input of the quadrature convolution
+    auto st_mid = [&](int k, C y) {
+        C z{T(0), T(0)};
+        if (k < N) {
+            z = cmul(y, e2n[mod2n(-((long long)k * k + k), twoN)]);
+            z = C{z.x * invN, z.y * invN};
+        }
+        buf[pad(k)] = z;
+    };
+    convolve<LOGM, T>(buf, ft.h_fd, ft.tw, ld, st_mid);
     const int Cn = 4 * B;
     T *Xre = X + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
     T *Xim = Xre + (size_t)B * L;
     const T twopi = T(6.283185307179586476925286766559);
-    for (int k = threadIdx.x; k < L; k += blockDim.x) {
-        T w = (k == 0 ? T(1) : T(2)) * twopi;
-        if (neg && (k & 1)) w = -w;
-        Xre[k] = buf[k].x * w;
-        Xim[k] = buf[k].y * w;
-    }
+    auto st = [&](int k, C y) {
+        if (k < L) {
+            T w = (k == 0 ? T(1) : T(2)) * twopi;
+            if (neg && (k & 1)) w = -w;
+            Xre[k] = y.x * w;
+            Xim[k] = y.y * w;
+        }
+    };
+    convolve<LOGM, T>(buf, ft.h_fk, ft.tw, [buf](int n) { return buf[pad(n)]; }, st);
 }
 
-// Plan helper: forward DIF of `rows` sequences of length M, in place, scaled.
-template <typename T>
-__global__ __launch_bounds__(kRowThreads) void k_dif_rows(FftTables<T> ft, typename CT<T>::type *data,
+// Plan helper: forward DFT (natural order) of `rows` sequences of length M, in place, scaled.
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_fft_rows(FftTables<T> ft, typename CT<T>::type *data,
                                                           T scale) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int M = ft.M;
-    C *row = data + (size_t)blockIdx.x * M;
-    for (int i = threadIdx.x; i < M; i += blockDim.x) buf[i] = row[i];
-    __syncthreads();
-    fft_dif(buf, ft.tw, M, ft.logM);
-    for (int i = threadIdx.x; i < M; i += blockDim.x) row[i] = C{buf[i].x * scale, buf[i].y * scale};
+    C *row = data + (size_t)blockIdx.x * ft.M;
+    fft_run<LOGM, T>(buf, ft.tw, [row](int n) { return row[n]; },
+                     [row, scale](int k, C x) { row[k] = C{x.x * scale, x.y * scale}; });
 }
 
 template <typename T> size_t lds_bytes(const FftTables<T> &ft) {
-    return (size_t)ft.M * sizeof(typename CT<T>::type);
+    return (size_t)(ft.M + ft.M / 16) * sizeof(typename CT<T>::type);
 }
 
 template <typename K> hipError_t set_lds(K kernel, size_t bytes) {
@@ -258,54 +381,87 @@ template <typename K> hipError_t set_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
+// Calls f(std::integral_constant<int, LOGM>) for the plan's log2 M (3 .. 13).
+template <typename F> hipError_t with_logm(int logM, F f) {
+    switch (logM) {
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 9: return f(std::integral_constant<int, 9>{});
+        case 10: return f(std::integral_constant<int, 10>{});
+        case 11: return f(std::integral_constant<int, 11>{});
+        case 12: return f(std::integral_constant<int, 12>{});
+        case 13: return f(std::integral_constant<int, 13>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, const T *R, void *G, hipStream_t st) {
-    const size_t lds = lds_bytes(ft);
-    hipError_t e = set_lds(k_theta_inv<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_inv<T>, dim3(ft.N * B), dim3(kRowThreads), lds, st, ft, s, B, R,
-                       (typename CT<T>::type *)G);
-    return hipGetLastError();
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_theta_inv<T, LM>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_theta_inv<T, LM>), dim3(ft.N * B), dim3(row_threads(ft.M)), lds, st, ft, s, B, R,
+                           (typename CT<T>::type *)G);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
 hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, hipStream_t st) {
-    const size_t lds = lds_bytes(ft);
-    hipError_t e = set_lds(k_phi_inv<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_phi_inv<T>, dim3(ft.L * B), dim3(kRowThreads), lds, st, ft,
-                       (const typename CT<T>::type *)G, (typename CT<T>::type *)map);
-    return hipGetLastError();
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_phi_inv<T, LM>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_phi_inv<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
+                           (const typename CT<T>::type *)G, (typename CT<T>::type *)map);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
 hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st) {
-    const size_t lds = lds_bytes(ft);
-    hipError_t e = set_lds(k_phi_fwd<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_phi_fwd<T>, dim3(ft.L * B), dim3(kRowThreads), lds, st, ft,
-                       (const typename CT<T>::type *)map, (typename CT<T>::type *)Q);
-    return hipGetLastError();
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_phi_fwd<T, LM>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_phi_fwd<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
+                           (const typename CT<T>::type *)map, (typename CT<T>::type *)Q);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
 hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q, T *X, hipStream_t st) {
-    const size_t lds = lds_bytes(ft);
-    hipError_t e = set_lds(k_theta_fwd<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_theta_fwd<T>, dim3(ft.N * B), dim3(kRowThreads), lds, st, ft, s, B,
-                       (const typename CT<T>::type *)Q, X);
-    return hipGetLastError();
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_theta_fwd<T, LM>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_theta_fwd<T, LM>), dim3(ft.N * B), dim3(row_threads(ft.M)), lds, st, ft, s, B,
+                           (const typename CT<T>::type *)Q, X);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
-hipError_t launch_fft_dif_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows, double scale,
-                                  hipStream_t st) {
-    const size_t lds = lds_bytes(ft);
-    hipError_t e = set_lds(k_dif_rows<T>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dif_rows<T>, dim3(rows), dim3(kRowThreads), lds, st, ft, buf, (T)scale);
-    return hipGetLastError();
+hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows, double scale,
+                              hipStream_t st) {
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_fft_rows<T, LM>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fft_rows<T, LM>), dim3(rows), dim3(row_threads(ft.M)), lds, st, ft, buf, (T)scale);
+        return hipGetLastError();
+    });
 }
 
 #define SHT_INST(T)                                                                                      \
@@ -313,7 +469,7 @@ hipError_t launch_fft_dif_inplace(const FftTables<T> &ft, typename CT<T>::type *
     template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
     template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
     template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, const void *, T *, hipStream_t); \
-    template hipError_t launch_fft_dif_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \
+    template hipError_t launch_fft_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \
                                                   hipStream_t);
 SHT_INST(double)
 SHT_INST(float)

@@ -86,12 +86,36 @@ hipError_t launch_spin_states(const EdgeTable &E, SpinPlan &sp, hipStream_t st) 
     return hipGetLastError();
 }
 
+// ------------------------------------------------ recursion factors ------
+// The arguments are exact integers in double precision; the reciprocal square
+// roots are taken once per L here instead of once per chain step.
+__global__ void k_rec_tables(int L, double *ri, double *rf) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)L * L) return;
+    const int a = (int)(idx / L), b = (int)(idx % L);
+    {   // ri[l][j], l = a, j = b
+        const double X = (double)(a + 1) * (a + 1) - (double)b * b;
+        ri[idx] = (b <= a) ? 1.0 / sqrt(X) : 0.0;
+    }
+    {   // rf[k][l], k = a, l = b
+        const double X = (double)(b + a) * (double)(b - a + 1);
+        rf[idx] = (a <= b && X > 0.0) ? 1.0 / sqrt(X) : 0.0;
+    }
+}
+
+hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st) {
+    const size_t n = (size_t)L * L;
+    const int th = 256;
+    hipLaunchKernelGGL(k_rec_tables, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, L, rt.ri, rt.rf);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- FFT tables ------
 // Angles are pi * (integer) / N or 2 pi * (integer) / M with the integer
 // reduced exactly first, then evaluated with sincospi in double precision.
 __global__ void k_fill_tw(cplx64 *tw, int M) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M / 2) return;
+    if (k >= M) return;
     double s, c;
     sincospi(-2.0 * (double)k / (double)M, &s, &c);
     tw[k] = cplx64{c, s};
@@ -142,7 +166,7 @@ template <>
 hipError_t launch_fft_tables<double>(FftTables<double> &ft, FftTables<double> *, hipStream_t st) {
     const int M = ft.M, N = ft.N, L = ft.L;
     const int th = 256;
-    hipLaunchKernelGGL(k_fill_tw, dim3((M / 2 + th - 1) / th), dim3(th), 0, st, ft.tw, M);
+    hipLaunchKernelGGL(k_fill_tw, dim3((M + th - 1) / th), dim3(th), 0, st, ft.tw, M);
     hipLaunchKernelGGL(k_fill_e2n, dim3((2 * N + th - 1) / th), dim3(th), 0, st, ft.e2n, N);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_it, M, N, L, N, L, 0);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_ip, M, N, L, N, N, 0);
@@ -150,12 +174,12 @@ hipError_t launch_fft_tables<double>(FftTables<double> &ft, FftTables<double> *,
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fk, M, N, L, N, L, 2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // spectra: forward DIF in place, scaled by 1/M (the inverse transform's normalisation)
+    // spectra: forward FFT in place (natural order), scaled by 1/M (the inverse transform's normalisation)
     const double inv = 1.0 / (double)M;
-    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_it, 1, inv, st)) != hipSuccess) return e;
-    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_ip, 1, inv, st)) != hipSuccess) return e;
-    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_fd, 1, inv, st)) != hipSuccess) return e;
-    if ((e = launch_fft_dif_inplace<double>(ft, ft.h_fk, 1, inv, st)) != hipSuccess) return e;
+    if ((e = launch_fft_inplace<double>(ft, ft.h_it, 1, inv, st)) != hipSuccess) return e;
+    if ((e = launch_fft_inplace<double>(ft, ft.h_ip, 1, inv, st)) != hipSuccess) return e;
+    if ((e = launch_fft_inplace<double>(ft, ft.h_fd, 1, inv, st)) != hipSuccess) return e;
+    if ((e = launch_fft_inplace<double>(ft, ft.h_fk, 1, inv, st)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -165,7 +189,7 @@ hipError_t launch_fft_tables<float>(FftTables<float> &ft, FftTables<double> *src
     auto conv = [&](cplx32 *d, const cplx64 *s, int n) {
         hipLaunchKernelGGL(k_convert_table<float>, dim3((n + th - 1) / th), dim3(th), 0, st, d, s, n);
     };
-    conv(ft.tw, src->tw, ft.M / 2);
+    conv(ft.tw, src->tw, ft.M);
     conv(ft.e2n, src->e2n, 2 * ft.N);
     conv(ft.h_it, src->h_it, ft.M);
     conv(ft.h_ip, src->h_ip, ft.M);

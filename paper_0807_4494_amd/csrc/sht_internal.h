@@ -54,18 +54,27 @@ struct SpinState {
 template <typename T> struct FftTables {
     using C = typename CT<T>::type;
     int L = 0, N = 0, M = 0, logM = 0;
-    C *tw = nullptr;      // e^{-2 pi i k / M}, k < M/2
+    C *tw = nullptr;      // e^{-2 pi i k / M}, k < M
     C *e2n = nullptr;     // e^{i pi k / N}, k < 2N
-    C *h_it = nullptr;    // spectra (bit-reversed, 1/M folded in) of the chirp-z kernels
+    C *h_it = nullptr;    // spectra (natural order, 1/M folded in) of the chirp-z kernels
     C *h_ip = nullptr;
     C *h_fd = nullptr;
     C *h_fk = nullptr;
+};
+
+// Per-L reciprocal square roots of the two Wigner recursions (FP64):
+//   ri[l*L + j] = 1/sqrt((l+1)^2 - j^2)        (l-recursion, j <= l; else 0)
+//   rf[k*L + l] = 1/sqrt((l+k)(l-k+1))          (m'-recursion at m' = k; 0 if k > l)
+struct RecTables {
+    double *ri = nullptr;
+    double *rf = nullptr;
 };
 
 struct Plan {
     int device = 0, L = 0, prec = 0;
     FftTables<double> f64;
     FftTables<float> f32;
+    RecTables rec;
 };
 
 struct SpinPlan {
@@ -77,6 +86,7 @@ struct SpinPlan {
 // plan.hip
 hipError_t launch_edge_table(EdgeTable &E, hipStream_t st);
 hipError_t launch_spin_states(const EdgeTable &E, SpinPlan &sp, hipStream_t st);
+hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
 // layout.hip
@@ -94,16 +104,16 @@ template <typename T>
 hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st);
 template <typename T>
 hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q, T *X, hipStream_t st);
-// forward DIF transform of one sequence per block, in place (plan building)
+// forward FFT (natural order) of one sequence per block, in place (plan building)
 template <typename T>
-hipError_t launch_fft_dif_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows,
+hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows,
                                   double scale, hipStream_t st);
 
 // contract.hip
 enum ContractMode { kInverse = 0, kForward = 1 };
 template <typename T>
 hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
-                           const SpinState *ss, hipStream_t st);
+                           const SpinState *ss, const RecTables &rt, hipStream_t st);
 hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y,
                                   const EdgeTable &E, const SpinState *ss, hipStream_t st);
 
