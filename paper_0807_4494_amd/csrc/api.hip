@@ -152,7 +152,9 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     if (rc == SHT_OK) rc = alloc_fft(p->f32, L);
     if (rc != SHT_OK) { delete p; return rc; }
     if (hipMalloc(&p->rec.ri, (size_t)L * L * sizeof(double)) != hipSuccess ||
-        hipMalloc(&p->rec.rf, (size_t)L * L * sizeof(double)) != hipSuccess) {
+        hipMalloc(&p->rec.rf, (size_t)L * L * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->rec.fab, (size_t)L * L * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->rec.cl, (size_t)L * sizeof(double)) != hipSuccess) {
         delete p;
         return SHT_ERR_OOM;
     }
@@ -318,6 +320,8 @@ int sht_release_all(void) {
         if (hipFree(kv.second->f32.tw) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.ri) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.rf) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.fab) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.cl) != hipSuccess) rc = SHT_ERR_HIP;
         delete kv.second;
     }
     g_plans.clear();

@@ -66,6 +66,8 @@ template <typename T> struct Args {
     const SpinState *ss;  // [L][L], inverse only
     const double *ri;     // [L][L] 1/sqrt((l+1)^2 - j^2)
     const double *rf;     // [L][L] 1/sqrt((l+k)(l-k+1)) at [k][l]
+    const double2 *fab;   // [L][L] order-side l-recursion factors
+    const double *cl;     // [L] sqrt((2l+1)/4pi)
 };
 
 template <typename T, int MODE, int CTILE>
@@ -77,8 +79,10 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
     constexpr int XPT = GM * CTILE * TK / NC;  // X slab elements per consumer thread
     using acc_t = typename Mfma<T>::acc;
 
-    __shared__ T Mt[2][GM][TK][TJ];
-    __shared__ T Xt[2][GM][TK][CTILE];
+    // M slab rows padded by 16 so the four K rows an MFMA fragment spans hit
+    // disjoint banks; X slab stored [c][k] with an odd row length.
+    __shared__ T Mt[2][GM][TK][TJ + 16];
+    __shared__ T Xt[2][GM][CTILE][TK + 1];
     __shared__ double fam[2][GM + 1][TK], fbm[2][GM + 1][TK], fcl[2][TK];
 
     const int L = a.L, s = a.s, Cn = a.C;
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
     const int tiles = a.njt * a.ncb;
     const int xcd = (int)(blockIdx.x % 8), slot = (int)(blockIdx.x / 8);
     const int mg = (slot / tiles) * 8 + xcd;
-    if (mg * GM >= a.L) return;
+    if (mg * GM >= L) return;
     const int cb = (slot % tiles) % a.ncb;
     const int jt = (slot % tiles) / a.ncb;
     const int m0 = mg * GM, j0 = jt * TJ, c0 = cb * CTILE;
@@ -119,167 +123,180 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
         return MODE == kInverse ? kfirst + chunk * TK : kfirst - (chunk + 1) * TK + 1;
     };
 
-    // ---- producer state ----
-    const int ptid = tid - NC;
-    const int jl = producer ? ptid % TJ : 0, sub = producer ? ptid / TJ : 0;
-    const int j = j0 + jl;
-    const bool jvalid = producer && j < L;
-    Chain ch[NCH], sc;
-    int mch[NCH];
-    bool vch[NCH];
-    Seed seed[NCH], sseed;  // chain seeds, loaded once before the K loop
-    double q = 0.0, gprev = 0.0, clj = 0.0;
-    int l0s = 0;
-
-    // inverse: l-recursion factors of the workgroup's orders and of sigma for one slab
-    auto fill_factors = [&](int chunk, int buf) {
-        if (MODE == kInverse && producer && ptid < (GM + 1) * TK && chunk < nchunks) {
-            const int gi = ptid / TK, kk = ptid % TK;
-            const int l = kbase_of(chunk) + kk;
-            const int idx = gi < GM ? m0 + gi : sigma;
-            double am, bm;
-            lrec_factor_full(l, idx, am, bm);
-            fam[buf][gi][kk] = am;
-            fbm[buf][gi][kk] = bm;
-            if (gi == 0) fcl[buf][kk] = sqrt((2.0 * l + 1.0) / (4.0 * 3.14159265358979323846));
-        }
-    };
-
     if (producer) {
+        // ================= producers: FP64 Wigner chains =================
+        const int ptid = tid - NC;
+        const int jl = ptid % TJ, sub = ptid / TJ;
+        const int j = j0 + jl;
+        const bool jvalid = j < L;
+        const double jd = (double)j;
+        Chain ch[NCH], sc;
+        int l0[NCH];
+        double sv[NCH], twom[NCH];
+        bool vch[NCH];
+        int l0s;
+        double ssv;
+        // chains start at zero with the scale of their seed; the seed is
+        // added by the step that reaches the chain's edge degree / order
 #pragma unroll
         for (int g = 0; g < NCH; ++g) {
-            mch[g] = m0 + sub * NCH + g;
-            ch[g].zero();
+            const int m = m0 + sub * NCH + g;
+            vch[g] = jvalid && m < L && (MODE == kInverse || j >= m);
+            const Seed sd = vch[g] ? edge_seed(a.E, j, m) : Seed{0.0, 0};
+            ch[g].d = 0.0;
+            ch[g].dp = 0.0;
+            ch[g].k = sd.k;
+            ch[g].es = emit_scale(sd.k);
+            sv[g] = sd.v;
+            l0[g] = MODE == kInverse ? (j > m ? j : m) : j;
+            twom[g] = 2.0 * m;
         }
-        sc.zero();
+        {
+            const bool vs = jvalid && (MODE == kInverse || j >= asg);
+            const Seed sd = vs ? edge_seed(a.E, j, sigma) : Seed{0.0, 0};
+            sc.d = 0.0;
+            sc.dp = 0.0;
+            sc.k = sd.k;
+            sc.es = emit_scale(sd.k);
+            ssv = sd.v;
+            l0s = MODE == kInverse ? (j > asg ? j : asg) : (vs ? j : -1);
+        }
+        double q = 0.0;      // inverse: sqrt(l^2 - j^2) at the current l
+        double gprev = 0.0;  // forward: sqrt((l+m'+1)(l-m')) of the previous m'
+        double clj = 0.0;    // forward: sqrt((2l+1)/4pi)
         if (MODE == kInverse) {
-#pragma unroll
-            for (int g = 0; g < NCH; ++g) vch[g] = jvalid && mch[g] < L;
-            l0s = j > asg ? j : asg;
-#pragma unroll
-            for (int g = 0; g < NCH; ++g) seed[g] = vch[g] ? edge_seed(a.E, j, mch[g]) : Seed{0.0, 0};
-            sseed = jvalid ? edge_seed(a.E, j, sigma) : Seed{0.0, 0};
-            if (jvalid && l0s < kfirst) {
+            if (jvalid && l0s < kfirst) {  // resume the spin chain from the plan
                 const SpinState st = a.ss[(size_t)kfirst * L + j];
                 sc.d = st.d;
                 sc.dp = st.dp;
                 sc.k = st.k;
                 sc.es = emit_scale(st.k);
             }
-            const double Y = (double)kfirst * kfirst - (double)j * j;
+            if (l0s == kfirst) sc.d = ssv;
+#pragma unroll
+            for (int g = 0; g < NCH; ++g)
+                if (vch[g] && l0[g] == kfirst) ch[g].d = sv[g];
+            const double Y = (double)kfirst * kfirst - jd * jd;
             q = Y > 0.0 ? sqrt(Y) : 0.0;
         } else {
+            clj = jvalid ? a.cl[j] : 0.0;
+            if (jvalid && l0s == kfirst) sc.d = ssv;
 #pragma unroll
-            for (int g = 0; g < NCH; ++g) vch[g] = jvalid && mch[g] < L && j >= mch[g];
-            clj = sqrt((2.0 * j + 1.0) / (4.0 * 3.14159265358979323846));
-#pragma unroll
-            for (int g = 0; g < NCH; ++g) seed[g] = vch[g] ? edge_seed(a.E, j, mch[g]) : Seed{0.0, 0};
-            sseed = (jvalid && j >= asg) ? edge_seed(a.E, j, sigma) : Seed{0.0, 0};
+            for (int g = 0; g < NCH; ++g)
+                if (vch[g] && j == kfirst) ch[g].d = sv[g];
         }
-    }
 
-    // producers: emit slab `chunk` of M into Mt[buf]
-    auto generate = [&](int chunk, int buf) {
-        const int kbase = kbase_of(chunk);
-        // this slab's reciprocal square roots for the thread's j, loaded up front
-        double rr[TK];
+        // reciprocal square roots of the recursion for this j, one slab ahead
+        const double *rtab = (MODE == kInverse ? a.ri : a.rf) + (jvalid ? j : 0);
+        double rr[TK], rn[TK];
+        auto load_rec = [&](int chunk, double *dst) {
+            const int kbase = kbase_of(chunk);
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            const int k = kbase + kk;
-            const bool ok = jvalid && k >= 0 && k < L;
-            rr[kk] = ok ? (MODE == kInverse ? a.ri[(size_t)k * L + j] : a.rf[(size_t)k * L + j]) : 0.0;
-        }
-        if (MODE == kInverse) {
-#pragma unroll 4
             for (int kk = 0; kk < TK; ++kk) {
-                const int l = kbase + kk;
-                if (l == l0s && jvalid) sc.inject(sseed);
-#pragma unroll
-                for (int g = 0; g < NCH; ++g) {
-                    const int l0 = j > mch[g] ? j : mch[g];
-                    if (vch[g] && l == l0) ch[g].inject(seed[g]);
-                }
-                const double W = (l < L) ? fcl[buf][kk] * sc.value() : 0.0;
-#pragma unroll
-                for (int g = 0; g < NCH; ++g)
-                    Mt[buf][sub * NCH + g][kk][jl] = (T)(vch[g] ? ch[g].value() * W : 0.0);
-                // step l -> l+1
-                const double Xl = (double)(l + 1) * (l + 1) - (double)j * j;
-                const double r = rr[kk];
-                const double ap = (double)j * r, bp = q * r;
-                q = Xl * r;
-                {
-                    const double dn = -(ap * fam[buf][GM][kk] * sc.d + bp * fbm[buf][GM][kk] * sc.dp);
-                    if (l >= l0s) sc.push(dn);
-                }
-#pragma unroll
-                for (int g = 0; g < NCH; ++g) {
-                    const int gi = sub * NCH + g;
-                    const double dn = -(ap * fam[buf][gi][kk] * ch[g].d + bp * fbm[buf][gi][kk] * ch[g].dp);
-                    const int l0 = j > mch[g] ? j : mch[g];
-                    if (l >= l0) ch[g].push(dn);
-                }
+                const int k = kbase + kk;
+                const bool ok = jvalid && chunk < nchunks && k >= 0 && k < L;
+                dst[kk] = ok ? rtab[k * L] : 0.0;
             }
-        } else {
+        };
+        // order-side factors of the l-recursion for one slab (inverse)
+        auto fill_factors = [&](int chunk, int buf) {
+            if (MODE == kInverse && ptid < (GM + 1) * TK && chunk < nchunks) {
+                const int gi = ptid / TK, kk = ptid % TK;
+                const int l = kbase_of(chunk) + kk;
+                const int idx = gi < GM ? m0 + gi : asg;
+                double am = 0.0, bm = 0.0, c = 0.0;
+                if (l < L && idx < L) {
+                    const double2 f = a.fab[idx * L + l];
+                    am = f.x;
+                    bm = f.y;
+                }
+                if (gi == GM && sigma < 0) am = -am;  // am is odd in the order, bm even
+                fam[buf][gi][kk] = am;
+                fbm[buf][gi][kk] = bm;
+                if (gi == 0) fcl[buf][kk] = l < L ? a.cl[l] : 0.0;
+            }
+        };
+        // keep |d| < 2^512 for chains still below the double range (checked once
+        // per slab: one slab grows a chain by far less than 2^400)
+        auto renorm = [&](Chain &c) {
+            if (c.k > 1 && fabs(c.d) > kBig) {
+                c.d *= kSmall;
+                c.dp *= kSmall;
+                --c.k;
+                c.es = emit_scale(c.k);
+            }
+        };
+        auto generate = [&](int chunk, int buf) {
+            const int kbase = kbase_of(chunk);
+            load_rec(chunk + 1, rn);
+            if (MODE == kInverse) {
+                double Xl = (double)(kbase + 1) * (kbase + 1) - jd * jd;
 #pragma unroll 4
-            for (int kk = TK - 1; kk >= 0; --kk) {
-                const int k = kbase + kk;  // m'
-                if (k == j && jvalid) {
-                    if (j >= asg) sc.inject(sseed);
+                for (int kk = 0; kk < TK; ++kk) {
+                    const int l = kbase + kk;
+                    const double W = fcl[buf][kk] * sc.d * sc.es;
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        if (vch[g]) ch[g].inject(seed[g]);
-                    gprev = 0.0;
-                }
-                const bool live = k >= 0 && k <= j && jvalid;
-                const double W = live ? clj * sc.value() : 0.0;
+                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es * W);
+                    // step l -> l+1
+                    const double r = rr[kk];
+                    const double ap = jd * r, bp = q * r;
+                    q = Xl * r;
+                    Xl += 2.0 * l + 3.0;
+                    {
+                        double dn = -(ap * fam[buf][GM][kk] * sc.d + bp * fbm[buf][GM][kk] * sc.dp);
+                        dn += (l + 1 == l0s) ? ssv : 0.0;
+                        sc.dp = sc.d;
+                        sc.d = dn;
+                    }
 #pragma unroll
-                for (int g = 0; g < NCH; ++g)
-                    Mt[buf][sub * NCH + g][kk][jl] = (T)(vch[g] ? ch[g].value() * W : 0.0);
-                // step m' -> m'-1
-                const double Xk = (double)(j + k) * (double)(j - k + 1);
-                const double y = rr[kk];
-                const double gcur = Xk * y;
-                if (live) {
-                    sc.push((2.0 * sigma * sc.d - gprev * sc.dp) * y);
+                    for (int g = 0; g < NCH; ++g) {
+                        const int gi = sub * NCH + g;
+                        double dn = -(ap * fam[buf][gi][kk] * ch[g].d + bp * fbm[buf][gi][kk] * ch[g].dp);
+                        dn += (vch[g] && l + 1 == l0[g]) ? sv[g] : 0.0;
+                        ch[g].dp = ch[g].d;
+                        ch[g].d = dn;
+                    }
+                }
+            } else {
+                const double W0 = clj;
+#pragma unroll 4
+                for (int kk = TK - 1; kk >= 0; --kk) {
+                    const int k = kbase + kk;  // m'
+                    const double W = W0 * sc.d * sc.es;
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        ch[g].push((2.0 * mch[g] * ch[g].d - gprev * ch[g].dp) * y);
+                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es * W);
+                    // step m' -> m'-1
+                    const double y = rr[kk];
+                    const double gcur = (double)(j + k) * (double)(j - k + 1) * y;
+                    {
+                        double dn = (2.0 * sigma * sc.d - gprev * sc.dp) * y;
+                        dn += (k - 1 == l0s) ? ssv : 0.0;
+                        sc.dp = sc.d;
+                        sc.d = dn;
+                    }
+#pragma unroll
+                    for (int g = 0; g < NCH; ++g) {
+                        double dn = (twom[g] * ch[g].d - gprev * ch[g].dp) * y;
+                        dn += (vch[g] && k - 1 == j) ? sv[g] : 0.0;
+                        ch[g].dp = ch[g].d;
+                        ch[g].d = dn;
+                    }
+                    gprev = gcur;
                 }
-                gprev = gcur;
             }
-        }
-    };
-
-    // consumers: X slab for `chunk` into registers, then into Xt[buf]
-    T xr[XPT];
-    auto load_x = [&](int chunk) {
-        const int kbase = kbase_of(chunk);
+            renorm(sc);
 #pragma unroll
-        for (int i = 0; i < XPT; ++i) {
-            const int e = tid + i * NC;           // over [GM][CTILE][TK]
-            const int g = e / (CTILE * TK), rem = e % (CTILE * TK);
-            const int c = rem / TK, kk = rem % TK;
-            const int m = m0 + g, k = kbase + kk;
-            bool ok = m < L && (c0 + c) < Cn && k >= 0 && k < L;
-            if (MODE == kInverse) ok = ok && k >= m;
-            xr[i] = ok ? a.X[((size_t)m * Cn + c0 + c) * L + k] : T(0);
-        }
-    };
-    auto store_x = [&](int buf) {
+            for (int g = 0; g < NCH; ++g) renorm(ch[g]);
 #pragma unroll
-        for (int i = 0; i < XPT; ++i) {
-            const int e = tid + i * NC;
-            const int g = e / (CTILE * TK), rem = e % (CTILE * TK);
-            const int c = rem / TK, kk = rem % TK;
-            Xt[buf][g][kk][c] = xr[i];
-        }
-    };
+            for (int kk = 0; kk < TK; ++kk) rr[kk] = rn[kk];
+        };
 
-    // ---- pipeline: producers run one slab ahead of the consumers.  Each role
-    // has its own loop (disjoint register live ranges); both execute the same
-    // number of workgroup barriers, and every wave takes one role as a whole.
-    if (producer) {
+        // ---- pipeline: producers run one slab ahead of the consumers.  Each
+        // role has its own loop (disjoint register live ranges); both execute
+        // the same number of workgroup barriers, and every wave takes one role.
+        load_rec(0, rr);
         fill_factors(0, 0);
         __syncthreads();
         generate(0, 0);
@@ -295,6 +312,40 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
         }
         return;
     }
+
+    // ================= consumers: MFMA =================
+    // X slab: element i of this thread is (g, c, kk); 32-bit offsets from the
+    // group's panel base, fixed for the whole K loop
+    int xoff[XPT], xsl[XPT];
+    bool xok[XPT];
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+        const int e = tid + i * NC;  // over [GM][CTILE][TK]
+        const int g = e / (CTILE * TK), rem = e % (CTILE * TK);
+        const int c = rem / TK, kk = rem % TK;
+        xok[i] = (m0 + g) < L && (c0 + c) < Cn;
+        xoff[i] = (g * Cn + c0 + c) * L + kk;
+        xsl[i] = (g * CTILE + c) * (TK + 1) + kk;
+    }
+    const T *xbase = a.X + (size_t)m0 * Cn * L;
+    T xr[XPT];
+    auto load_x = [&](int chunk) {
+        const int kbase = kbase_of(chunk);
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int e = tid + i * NC;
+            const int g = e / (CTILE * TK), kk = e % TK;
+            const int k = kbase + kk;
+            bool ok = xok[i] && k >= 0 && k < L;
+            if (MODE == kInverse) ok = ok && k >= m0 + g;
+            xr[i] = ok ? xbase[xoff[i] + kbase] : T(0);
+        }
+    };
+    auto store_x = [&](int buf) {
+        T *xt = &Xt[buf][0][0][0];
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) xt[xsl[i]] = xr[i];
+    };
 
     acc_t acc[GM][NCI][NJI];
 #pragma unroll
@@ -323,7 +374,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
             const int g = idx / NKS, ks = idx % NKS;
             const int kr = ks * 4 + (lane >> 4);
 #pragma unroll
-            for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = Xt[buf][g][kr][ci * 16 + (lane & 15)];
+            for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = Xt[buf][g][ci * 16 + (lane & 15)][kr];
 #pragma unroll
             for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = Mt[buf][g][kr][wave * WJ + ji * 16 + (lane & 15)];
         };
@@ -357,6 +408,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
     for (int g = 0; g < GM; ++g) {
         const int m = m0 + g;
         if (m >= L) continue;
+        T *yrow = a.Y + (size_t)m * Cn * L;
 #pragma unroll
         for (int ci = 0; ci < NCI; ++ci)
 #pragma unroll
@@ -365,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
                 for (int r = 0; r < 4; ++r) {
                     const int c = c0 + ci * 16 + Mfma<T>::row(lane, r);
                     const int jj = j0 + wave * WJ + ji * 16 + (lane & 15);
-                    if (c < Cn && jj < L) a.Y[((size_t)m * Cn + c) * L + jj] = acc[g][ci][ji][r];
+                    if (c < Cn && jj < L) yrow[c * L + jj] = acc[g][ci][ji][r];
                 }
     }
 }
@@ -395,6 +447,8 @@ hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, cons
     a.ss = ss;
     a.ri = rt.ri;
     a.rf = rt.rf;
+    a.fab = rt.fab;
+    a.cl = rt.cl;
     if (a.C <= 16) {
         a.ncb = 1;
         return mode == kInverse ? launch_one<T, kInverse, 16>(a, st) : launch_one<T, kForward, 16>(a, st);

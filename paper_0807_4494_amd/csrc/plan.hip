@@ -89,10 +89,16 @@ hipError_t launch_spin_states(const EdgeTable &E, SpinPlan &sp, hipStream_t st) 
 // ------------------------------------------------ recursion factors ------
 // The arguments are exact integers in double precision; the reciprocal square
 // roots are taken once per L here instead of once per chain step.
-__global__ void k_rec_tables(int L, double *ri, double *rf) {
+__global__ void k_rec_tables(int L, double *ri, double *rf, double2 *fab, double *cl) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)L * L) return;
     const int a = (int)(idx / L), b = (int)(idx % L);
+    {   // fab[a][l], l = b
+        double am = 0.0, bm = 0.0;
+        if (b >= 1 && a <= b) lrec_factor_full(b, a, am, bm);
+        fab[idx] = make_double2(am, bm);
+        if (a == 0) cl[b] = sqrt((2.0 * b + 1.0) / (4.0 * 3.14159265358979323846));
+    }
     {   // ri[l][j], l = a, j = b
         const double X = (double)(a + 1) * (a + 1) - (double)b * b;
         ri[idx] = (b <= a) ? 1.0 / sqrt(X) : 0.0;
@@ -106,7 +112,8 @@ __global__ void k_rec_tables(int L, double *ri, double *rf) {
 hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st) {
     const size_t n = (size_t)L * L;
     const int th = 256;
-    hipLaunchKernelGGL(k_rec_tables, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, L, rt.ri, rt.rf);
+    hipLaunchKernelGGL(k_rec_tables, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, L, rt.ri, rt.rf,
+                       rt.fab, rt.cl);
     return hipGetLastError();
 }
 

@@ -65,9 +65,15 @@ template <typename T> struct FftTables {
 // Per-L reciprocal square roots of the two Wigner recursions (FP64):
 //   ri[l*L + j] = 1/sqrt((l+1)^2 - j^2)        (l-recursion, j <= l; else 0)
 //   rf[k*L + l] = 1/sqrt((l+k)(l-k+1))          (m'-recursion at m' = k; 0 if k > l)
+// and the order-side factors of the l-recursion, for a >= 0 and l < L:
+//   fab[a*L + l] = { a (2l+1) / (l sqrt((l+1)^2 - a^2)),
+//                    sqrt(l^2 - a^2) (l+1) / (l sqrt((l+1)^2 - a^2)) }  (0 at l = 0 or a > l)
+//   cl[l] = sqrt((2l+1)/(4 pi))
 struct RecTables {
     double *ri = nullptr;
     double *rf = nullptr;
+    double2 *fab = nullptr;
+    double *cl = nullptr;
 };
 
 struct Plan {
