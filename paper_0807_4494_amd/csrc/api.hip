@@ -87,15 +87,16 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t elem_bytes(int precision) { return precision == SHT_FP64 ? 8 : 4; }
 
-// Workspace: two regions. A holds the layout panels / phi-stage output, B the
-// contraction input or output; see the launch sequences below.
+// Workspace: two regions, each large enough for a set of order-major panels
+// [L][4B][L] and for a B x L x N complex grid; the launch sequences below
+// alternate between them.
 void regions(int L, int batch, int precision, size_t &ra, size_t &rb) {
     const size_t T = elem_bytes(precision);
     const size_t C = 4 * (size_t)batch, N = 2 * (size_t)L - 1;
     const size_t panel = (size_t)L * C * L * T;
     const size_t grid = (size_t)batch * L * N * 2 * T;
     ra = align256(panel > grid ? panel : grid);
-    rb = align256(panel);
+    rb = ra;
 }
 
 int check_args(int L, int spin, int batch, int sampling, int precision) {
@@ -129,12 +130,16 @@ template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
     ft.N = 2 * L - 1;
     ft.M = fft_size(L);
     ft.logM = ilog2(ft.M);
-    const size_t n = (size_t)ft.M + 2 * (size_t)ft.N + 4 * (size_t)ft.M;
+    const size_t nptw = (size_t)fft_pass_offset(ft.logM, fft_npass(ft.logM));
+    const size_t n = (size_t)ft.M + 2 * (size_t)ft.N + 2 * (size_t)ft.N + nptw + 4 * (size_t)ft.M;
     C *base = nullptr;
     if (hipMalloc(&base, n * sizeof(C)) != hipSuccess) return SHT_ERR_OOM;
     ft.tw = base;
     ft.e2n = ft.tw + ft.M;
-    ft.h_it = ft.e2n + 2 * ft.N;
+    ft.cha = ft.e2n + 2 * ft.N;
+    ft.chb = ft.cha + ft.N;
+    ft.ptw = ft.chb + ft.N;
+    ft.h_it = ft.ptw + nptw;
     ft.h_ip = ft.h_it + ft.M;
     ft.h_fd = ft.h_ip + ft.M;
     ft.h_fk = ft.h_fd + ft.M;
@@ -220,10 +225,16 @@ int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const RecTab
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
                    [&] { return launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, sp->ss, rec, st); }),
             "contract inverse");
+    // theta stage writes rows g_mu(theta_t) over t (region A); the transpose
+    // makes rings over mu (region B) for the phi stage
     SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
-                   [&] { return launch_theta_inv<T>(ft, spin, batch, R, (void *)P, st); }),
+                   [&] {
+                       hipError_t e = launch_theta_inv<T>(ft, spin, batch, R, (void *)P, st);
+                       if (e != hipSuccess) return e;
+                       return launch_transpose<T>(batch, ft.N, L, (const void *)P, (void *)R, st);
+                   }),
             "theta inverse");
-    SHT_HIP(traced(SHT_STAGE_PHI_INV, st, [&] { return launch_phi_inv<T>(ft, batch, (const void *)P, map, st); }),
+    SHT_HIP(traced(SHT_STAGE_PHI_INV, st, [&] { return launch_phi_inv<T>(ft, batch, (const void *)R, map, st); }),
             "phi inverse");
     return SHT_OK;
 }
@@ -234,13 +245,19 @@ int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const RecTab
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
-    void *Q = (void *)w;      // region A: phi-stage output, later the contraction output
-    T *X = (T *)(w + ra);     // region B: weighted theta coefficients
+    void *Q = (void *)w;          // region A: phi-stage output (rings over mu)
+    void *Qt = (void *)(w + ra);  // region B: the same as rows over t
+    T *X = (T *)w;                // region A: weighted theta coefficients
     SHT_HIP(traced(SHT_STAGE_PHI_FWD, st, [&] { return launch_phi_fwd<T>(ft, batch, map, Q, st); }),
             "phi forward");
-    SHT_HIP(traced(SHT_STAGE_THETA_FWD, st, [&] { return launch_theta_fwd<T>(ft, spin, batch, Q, X, st); }),
+    SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
+                   [&] {
+                       hipError_t e = launch_transpose<T>(batch, L, ft.N, Q, Qt, st);
+                       if (e != hipSuccess) return e;
+                       return launch_theta_fwd<T>(ft, spin, batch, (const void *)Qt, X, st);
+                   }),
             "theta forward");
-    T *R = (T *)w;
+    T *R = (T *)(w + ra);
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
                    [&] { return launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, sp->ss, rec, st); }),
             "contract forward");

@@ -30,11 +30,6 @@ inline int row_threads(int M) { return M / 16 < 64 ? 64 : M / 16; }
 // stride-16 accesses of the Stockham passes spread over the banks.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
-__device__ inline long long mod2n(long long x, long long twoN) {
-    long long r = x % twoN;
-    return r < 0 ? r + twoN : r;
-}
-
 template <typename C>
 __device__ inline C rot_ipow(C v, int k) {  // v * i^k
     switch (k & 3) {
@@ -125,7 +120,7 @@ template <int R, typename C, typename T> __device__ inline void dft_r(C *v) {
 // writes dst[(j div Ns) Ns R + (j mod Ns) + r Ns].  All reads finish (barrier)
 // before any write, so src and dst may be the same LDS buffer.
 template <int R, int LOGM, int LOGNS, typename T, typename Ld, typename St>
-__device__ __forceinline__ void stockham_pass(const typename CT<T>::type *tw, Ld ld, St st) {
+__device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, Ld ld, St st) {
     using C = typename CT<T>::type;
     constexpr int LOGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
     constexpr int M = 1 << LOGM;
@@ -143,15 +138,15 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *tw, Ld
         }
     }
     __syncthreads();
-    constexpr int tshift = LOGM - LOGNS - LOGR;  // twiddle stride M / (Ns R)
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         const int j = threadIdx.x + q * nt;
         if (j < nb) {
             const int k = j & ((1 << logNs) - 1);
             if constexpr (LOGNS > 0) {
+                const C *w = ptw + k * R;  // w^{r k}, r < R, contiguous
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[((r * k) << tshift) & (M - 1)]);
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
             }
             dft_r<R, C, T>(v[q]);
             const int base = ((j >> logNs) << (logNs + LOGR)) + k;
@@ -167,26 +162,26 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *tw, Ld
 // first pass has radix 2^(LOGM mod 4) when LOGM is not a multiple of 4, all
 // others radix 16.
 template <int LOGM, int P, int LOGNS, typename T, typename Ld, typename St>
-__device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const typename CT<T>::type *tw, Ld ld,
+__device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const typename CT<T>::type *ptw, Ld ld,
                                            St st) {
     using C = typename CT<T>::type;
-    constexpr int R0 = LOGM & 3;
-    constexpr int NPASS = (LOGM + 3) / 4;
-    constexpr int LR = (P == 0 && R0) ? R0 : 4;
+    constexpr int NPASS = fft_npass(LOGM);
+    constexpr int LR = fft_pass_lr(LOGM, P);
     constexpr int RR = 1 << LR;
     constexpr bool FIRST = P == 0, LAST = P == NPASS - 1;
+    const C *tp = ptw + fft_pass_offset(LOGM, P);
     auto lbuf = [buf](int n) { return buf[pad(n)]; };
     auto sbuf = [buf](int k, C x) { buf[pad(k)] = x; };
-    if constexpr (FIRST && LAST) stockham_pass<RR, LOGM, LOGNS, T>(tw, ld, st);
-    else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T>(tw, ld, sbuf);
-    else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T>(tw, lbuf, st);
-    else stockham_pass<RR, LOGM, LOGNS, T>(tw, lbuf, sbuf);
-    if constexpr (!LAST) fft_passes<LOGM, P + 1, LOGNS + LR, T>(buf, tw, ld, st);
+    if constexpr (FIRST && LAST) stockham_pass<RR, LOGM, LOGNS, T>(tp, ld, st);
+    else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T>(tp, ld, sbuf);
+    else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T>(tp, lbuf, st);
+    else stockham_pass<RR, LOGM, LOGNS, T>(tp, lbuf, sbuf);
+    if constexpr (!LAST) fft_passes<LOGM, P + 1, LOGNS + LR, T>(buf, ptw, ld, st);
 }
 
 template <int LOGM, typename T, typename Ld, typename St>
-__device__ __forceinline__ void fft_run(typename CT<T>::type *buf, const typename CT<T>::type *tw, Ld ld, St st) {
-    fft_passes<LOGM, 0, 0, T>(buf, tw, ld, st);
+__device__ __forceinline__ void fft_run(typename CT<T>::type *buf, const typename CT<T>::type *ptw, Ld ld, St st) {
+    fft_passes<LOGM, 0, 0, T>(buf, ptw, ld, st);
 }
 
 // Cyclic convolution with a plan kernel of spectrum H (natural order, 1/M
@@ -208,7 +203,7 @@ __device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typena
 // (-1)^s i^{-(mu+s)} (and (-1)^{m'} for mu < 0); m' < 0 filled with
 // F_{mu,-m'} = (-1)^{mu+s} F_{mu m'} (Eq. (Ffourier_sym)); then
 //   g_mu(theta_t) = sum_{m'} F_{mu m'} e^{i m' theta_t},  t < L.
-// Output G[b][t][mu + L - 1].
+// Output G'[b][mu + L - 1][t] (rows; transposed for the phi stage afterwards).
 template <typename T, int LOGM>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B,
                                                            const T *__restrict__ R,
@@ -217,7 +212,6 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const long long twoN = 2LL * N;
     const int row = blockIdx.x;
     const int mu_idx = row % N, b = row / N;
     const int mu = mu_idx - h, m = mu < 0 ? -mu : mu, neg = mu < 0;
@@ -227,7 +221,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     const int phase = -(mu + s);                 // i^{-(mu+s)}
     const T sgn_s = (s & 1) ? T(-1) : T(1);
     const int fill_odd = parity((long long)mu + s);
-    const C *e2n = ft.e2n;
+    const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
         const int mp = n - h, amp = mp < 0 ? -mp : mp;
@@ -235,13 +229,13 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
         F = rot_ipow(F, phase);
         const int flip = (neg && (amp & 1)) ^ (mp < 0 && fill_odd);
         if (flip) F = C{-F.x, -F.y};
-        return cmul(F, e2n[mod2n((long long)n * n + n, twoN)]);
+        return cmul(F, cha[n]);
     };
-    C *Gb = G + (size_t)b * L * N + mu_idx;
+    C *Gr = G + ((size_t)b * N + mu_idx) * L;
     auto st = [&](int t, C y) {
-        if (t < L) Gb[(size_t)t * N] = cmul(y, e2n[mod2n((long long)t * t - 2LL * h * t - h, twoN)]);
+        if (t < L) Gr[t] = cmul(y, chb[t]);
     };
-    convolve<LOGM, T>(buf, ft.h_it, ft.tw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_it, ft.ptw, ld, st);
 }
 
 // Inverse phi stage.  Row (b, t): f(theta_t, phi_p) = sum_mu g_mu(theta_t) e^{i mu phi_p}.
@@ -252,20 +246,19 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft,
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int L = ft.L, N = ft.N, h = L - 1;
-    const long long twoN = 2LL * N;
+    const int N = ft.N;
     const size_t row = blockIdx.x;
     const C *in = G + row * N;
     C *out = map + row * N;
-    const C *e2n = ft.e2n;
+    const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
-        return cmul(in[n], e2n[mod2n((long long)n * n + n, twoN)]);
+        return cmul(in[n], cha[n]);
     };
     auto st = [&](int p, C y) {
-        if (p < N) out[p] = cmul(y, e2n[mod2n((long long)p * p - 2LL * h * p - h, twoN)]);
+        if (p < N) out[p] = cmul(y, chb[p]);
     };
-    convolve<LOGM, T>(buf, ft.h_ip, ft.tw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
 }
 
 // Forward phi stage.  Row (b, t): Q_mu(t) = N^-1 sum_p f(theta_t, phi_p) e^{-i mu phi_p}.
@@ -276,27 +269,27 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
-    const int L = ft.L, N = ft.N, h = L - 1;
-    const long long twoN = 2LL * N;
+    const int N = ft.N;
     const size_t row = blockIdx.x;
     const C *in = map + row * N;
     C *out = Q + row * N;
-    const C *e2n = ft.e2n;
+    const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
-        return cmul(in[n], e2n[mod2n(-((long long)n * n - 2LL * h * n - h), twoN)]);
+        return cmulc(in[n], chb[n]);
     };
     auto st = [&](int k, C y) {
         if (k < N) {
-            const C z = cmul(y, e2n[mod2n(-((long long)k * k + k), twoN)]);
+            const C z = cmulc(y, cha[k]);
             out[k] = C{z.x * invN, z.y * invN};
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.tw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
 }
 
-// Forward theta stage.  Row (b, mu): parity extension of Q_mu to the torus
+// Forward theta stage.  Row (b, mu) of Q'[b][mu][t] (the phi-stage output
+// transposed): parity extension of Q_mu to the torus
 // rings t < N (Section 3.2: even for mu+s even, odd otherwise), the theta DFT
 //   F_{mu m''} = N^-1 sum_t Q~_mu(t) e^{-i m'' theta_t},
 // then the exact sin(theta) quadrature folded over +-m' with its real
@@ -313,35 +306,34 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const long long twoN = 2LL * N;
     const int row = blockIdx.x;
     const int mu_idx = row % N, b = row / N;
     const int mu = mu_idx - h, m = mu < 0 ? -mu : mu, neg = mu < 0;
     const int ext_odd = parity((long long)mu + s);
-    const C *Qb = Q + (size_t)b * L * N + mu_idx;
-    const C *e2n = ft.e2n;
+    const C *Qr = Q + ((size_t)b * N + mu_idx) * L;  // row over t < L
+    const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
         C x;
         if (n < L) {
-            x = Qb[(size_t)n * N];
+            x = Qr[n];
         } else {
-            x = Qb[(size_t)(2 * L - 2 - n) * N];
+            x = Qr[2 * L - 2 - n];
             if (ext_odd) x = C{-x.x, -x.y};
         }
-        return cmul(x, e2n[mod2n(-((long long)n * n - 2LL * h * n - h), twoN)]);
+        return cmulc(x, chb[n]);
     };
     // the theta DFT lands in LDS (zero beyond N) as the input of the quadrature convolution
     auto st_mid = [&](int k, C y) {
         C z{T(0), T(0)};
         if (k < N) {
-            z = cmul(y, e2n[mod2n(-((long long)k * k + k), twoN)]);
+            z = cmulc(y, cha[k]);
             z = C{z.x * invN, z.y * invN};
         }
         buf[pad(k)] = z;
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.tw, ld, st_mid);
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st_mid);
     const int Cn = 4 * B;
     T *Xre = X + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
     T *Xim = Xre + (size_t)B * L;
@@ -354,7 +346,28 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
             Xim[k] = y.y * w;
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fk, ft.tw, [buf](int n) { return buf[pad(n)]; }, st);
+    convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, [buf](int n) { return buf[pad(n)]; }, st);
+}
+
+// out[b][c][r] = in[b][r][c], 32 x 32 tiles through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const typename CT<T>::type *__restrict__ in,
+                                                   typename CT<T>::type *__restrict__ out) {
+    using C = typename CT<T>::type;
+    __shared__ C tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32, b = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const C *ib = in + (size_t)b * rows * cols;
+    C *ob = out + (size_t)b * rows * cols;
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        if (r < rows && c < cols) tile[i][tx] = ib[(size_t)r * cols + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int c = c0 + i, r = r0 + tx;
+        if (r < rows && c < cols) ob[(size_t)c * rows + r] = tile[tx][i];
+    }
 }
 
 // Plan helper: forward DFT (natural order) of `rows` sequences of length M, in place, scaled.
@@ -365,7 +378,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_fft_rows(FftTables<T> ft, ty
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     C *row = data + (size_t)blockIdx.x * ft.M;
-    fft_run<LOGM, T>(buf, ft.tw, [row](int n) { return row[n]; },
+    fft_run<LOGM, T>(buf, ft.ptw, [row](int n) { return row[n]; },
                      [row, scale](int k, C x) { row[k] = C{x.x * scale, x.y * scale}; });
 }
 
@@ -464,11 +477,20 @@ hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf,
     });
 }
 
+template <typename T>
+hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out, hipStream_t st) {
+    const dim3 grid((cols + 31) / 32, (rows + 31) / 32, B);
+    hipLaunchKernelGGL(k_transpose<T>, grid, dim3(256), 0, st, rows, cols, (const typename CT<T>::type *)in,
+                       (typename CT<T>::type *)out);
+    return hipGetLastError();
+}
+
 #define SHT_INST(T)                                                                                      \
     template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, const T *, void *, hipStream_t); \
     template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
     template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
     template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, const void *, T *, hipStream_t); \
+    template hipError_t launch_transpose<T>(int, int, int, const void *, void *, hipStream_t);                \
     template hipError_t launch_fft_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \
                                                   hipStream_t);
 SHT_INST(double)

@@ -162,6 +162,33 @@ __global__ void k_fill_kernel_seq(cplx64 *c, int M, int N, int L, int nin, int k
     c[i] = cplx64{cc, type == 0 ? -s : s};
 }
 
+// Stage chirps: cha[n] = e^{i pi (n^2+n)/N}, chb[n] = e^{i pi (n^2 - 2hn - h)/N}.
+__global__ void k_fill_chirps(cplx64 *cha, cplx64 *chb, int N, int L) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const long long twoN = 2LL * N, h = L - 1;
+    long long ra = ((long long)n * n + n) % twoN;
+    long long rb = ((long long)n * n - 2 * h * n - h) % twoN;
+    if (rb < 0) rb += twoN;
+    double s, c;
+    sincospi((double)ra / (double)N, &s, &c);
+    cha[n] = cplx64{c, s};
+    sincospi((double)rb / (double)N, &s, &c);
+    chb[n] = cplx64{c, s};
+}
+
+// Twiddles of Stockham pass p: ptw[off + k R + r] = e^{-2 pi i r k / (Ns R)}.
+__global__ void k_fill_pass_tw(cplx64 *ptw, int off, int logNs, int logR) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = 1 << (logNs + logR);
+    if (i >= n) return;
+    const int k = i >> logR, r = i & ((1 << logR) - 1);
+    const long long num = ((long long)r * k) % n;
+    double s, c;
+    sincospi(-2.0 * (double)num / (double)n, &s, &c);
+    ptw[off + i] = cplx64{c, s};
+}
+
 template <typename T> __global__ void k_convert_table(typename CT<T>::type *dst, const cplx64 *src, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -175,6 +202,13 @@ hipError_t launch_fft_tables<double>(FftTables<double> &ft, FftTables<double> *,
     const int th = 256;
     hipLaunchKernelGGL(k_fill_tw, dim3((M + th - 1) / th), dim3(th), 0, st, ft.tw, M);
     hipLaunchKernelGGL(k_fill_e2n, dim3((2 * N + th - 1) / th), dim3(th), 0, st, ft.e2n, N);
+    hipLaunchKernelGGL(k_fill_chirps, dim3((N + th - 1) / th), dim3(th), 0, st, ft.cha, ft.chb, N, L);
+    for (int p = 1; p < fft_npass(ft.logM); ++p) {
+        const int lns = fft_pass_logns(ft.logM, p), lr = fft_pass_lr(ft.logM, p);
+        const int n = 1 << (lns + lr);
+        hipLaunchKernelGGL(k_fill_pass_tw, dim3((n + th - 1) / th), dim3(th), 0, st, ft.ptw,
+                           fft_pass_offset(ft.logM, p), lns, lr);
+    }
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_it, M, N, L, N, L, 0);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_ip, M, N, L, N, N, 0);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fd, M, N, L, N, N, 1);
@@ -194,10 +228,13 @@ template <>
 hipError_t launch_fft_tables<float>(FftTables<float> &ft, FftTables<double> *src, hipStream_t st) {
     const int th = 256;
     auto conv = [&](cplx32 *d, const cplx64 *s, int n) {
-        hipLaunchKernelGGL(k_convert_table<float>, dim3((n + th - 1) / th), dim3(th), 0, st, d, s, n);
+        if (n > 0) hipLaunchKernelGGL(k_convert_table<float>, dim3((n + th - 1) / th), dim3(th), 0, st, d, s, n);
     };
     conv(ft.tw, src->tw, ft.M);
     conv(ft.e2n, src->e2n, 2 * ft.N);
+    conv(ft.cha, src->cha, ft.N);
+    conv(ft.chb, src->chb, ft.N);
+    conv(ft.ptw, src->ptw, fft_pass_offset(ft.logM, fft_npass(ft.logM)));
     conv(ft.h_it, src->h_it, ft.M);
     conv(ft.h_ip, src->h_ip, ft.M);
     conv(ft.h_fd, src->h_fd, ft.M);

@@ -56,6 +56,9 @@ template <typename T> struct FftTables {
     int L = 0, N = 0, M = 0, logM = 0;
     C *tw = nullptr;      // e^{-2 pi i k / M}, k < M
     C *e2n = nullptr;     // e^{i pi k / N}, k < 2N
+    C *cha = nullptr;     // e^{i pi (n^2 + n) / N}, n < N          (chirps of the stages)
+    C *chb = nullptr;     // e^{i pi (n^2 - 2 h n - h) / N}, n < N, h = L - 1
+    C *ptw = nullptr;     // per-pass Stockham twiddles (fft_pass_offset)
     C *h_it = nullptr;    // spectra (natural order, 1/M folded in) of the chirp-z kernels
     C *h_ip = nullptr;
     C *h_fd = nullptr;
@@ -110,6 +113,9 @@ template <typename T>
 hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st);
 template <typename T>
 hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q, T *X, hipStream_t st);
+// out[b][c][r] = in[b][r][c] for complex T
+template <typename T>
+hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out, hipStream_t st);
 // forward FFT (natural order) of one sequence per block, in place (plan building)
 template <typename T>
 hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows,
@@ -126,5 +132,22 @@ hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X,
 // ------------------------------------------------------------- helpers -----
 inline int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
 inline int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+// Stockham pass structure of an M = 2^logM point FFT: pass 0 has radix
+// 2^(logM mod 4) when that is non-zero, every other pass radix 16.  Pass p
+// (p >= 1) keeps its twiddles w^{r k}, k < Ns_p, r < R_p, at
+// ptw[fft_pass_offset(logM, p) + k R_p + r].
+__host__ __device__ constexpr int fft_pass_lr(int logM, int p) { return (p == 0 && (logM & 3)) ? (logM & 3) : 4; }
+__host__ __device__ constexpr int fft_npass(int logM) { return (logM + 3) / 4; }
+__host__ __device__ constexpr int fft_pass_logns(int logM, int p) {
+    int s = 0;
+    for (int q = 0; q < p; ++q) s += fft_pass_lr(logM, q);
+    return s;
+}
+__host__ __device__ constexpr int fft_pass_offset(int logM, int p) {
+    int o = 0;
+    for (int q = 1; q < p; ++q) o += 1 << (fft_pass_logns(logM, q) + fft_pass_lr(logM, q));
+    return o;
+}
 
 }  // namespace sht

@@ -75,7 +75,7 @@ def test_workspace_size_formula():
         C, Nn = 4 * B, 2 * L - 1
         al = lambda x: (x + 255) // 256 * 256
         ra = al(max(L * C * L * T, B * L * Nn * 2 * T))
-        rb = al(L * C * L * T)
+        rb = ra
         assert lib.sht_workspace_bytes(L, 0, B, 0, p) == ra + rb
     assert lib.sht_workspace_bytes(8, 9, 1, 0, 0) == 0
     assert lib.sht_workspace_bytes(8, 0, 1, 3, 0) == 0
