@@ -172,7 +172,8 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     return SHT_OK;
 }
 
-int get_spin_plan(int dev, int L, int spin, const DeviceState *ds, hipStream_t st, SpinPlan **out) {
+int get_spin_plan(int dev, int L, int spin, const DeviceState *ds, const Plan *plan, hipStream_t st,
+                  SpinPlan **out) {
     auto key = std::make_tuple(dev, L, spin);
     auto it = g_spin.find(key);
     if (it != g_spin.end()) { *out = it->second; return SHT_OK; }
@@ -180,8 +181,15 @@ int get_spin_plan(int dev, int L, int spin, const DeviceState *ds, hipStream_t s
     sp->device = dev;
     sp->L = L;
     sp->spin = spin;
-    if (hipMalloc(&sp->ss, (size_t)L * L * sizeof(SpinState)) != hipSuccess) { delete sp; return SHT_ERR_OOM; }
-    SHT_HIP(launch_spin_states(ds->E, *sp, st), "spin states");
+    // one block: wi, wf (FP64) then wi32, wf32 (FP32)
+    const size_t n = (size_t)L * L;
+    char *blk = nullptr;
+    if (hipMalloc(&blk, n * (2 * sizeof(double) + 2 * sizeof(float))) != hipSuccess) { delete sp; return SHT_ERR_OOM; }
+    sp->wi = (double *)blk;
+    sp->wf = sp->wi + n;
+    sp->wi32 = (float *)(sp->wf + n);
+    sp->wf32 = sp->wi32 + n;
+    SHT_HIP(launch_spin_tables(ds->E, plan->rec, *sp, st), "spin tables");
     SHT_HIP(hipStreamSynchronize(st), "spin plan sync");
     g_spin[key] = sp;
     *out = sp;
@@ -196,7 +204,7 @@ int prepare(int L, int spin, hipStream_t st, DeviceState **ds, Plan **plan, Spin
     if (rc != SHT_OK) return rc;
     rc = get_plan(dev, L, st, plan);
     if (rc != SHT_OK) return rc;
-    return get_spin_plan(dev, L, spin, *ds, st, sp);
+    return get_spin_plan(dev, L, spin, *ds, *plan, st, sp);
 }
 
 bool misaligned(const void *p, size_t a) { return ((uintptr_t)p) % a != 0; }
@@ -223,7 +231,7 @@ int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const RecTab
     SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st, [&] { return launch_layout_in<T>(L, spin, batch, flm, P, st); }),
             "layout_in");
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
-                   [&] { return launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, sp->ss, rec, st); }),
+                   [&] { return launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, *sp, rec, st); }),
             "contract inverse");
     // theta stage writes rows g_mu(theta_t) over t (region A); the transpose
     // makes rings over mu (region B) for the phi stage
@@ -259,7 +267,7 @@ int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const RecTab
             "theta forward");
     T *R = (T *)(w + ra);
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
-                   [&] { return launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, sp->ss, rec, st); }),
+                   [&] { return launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, *sp, rec, st); }),
             "contract forward");
     SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st, [&] { return launch_layout_out<T>(L, spin, batch, R, flm, st); }),
             "layout_out");
@@ -327,7 +335,7 @@ int sht_release_all(void) {
     if (hipGetDevice(&cur) != hipSuccess) cur = 0;
     for (auto &kv : g_spin) {
         (void)hipSetDevice(kv.second->device);
-        if (hipFree(kv.second->ss) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->wi) != hipSuccess) rc = SHT_ERR_HIP;
         delete kv.second;
     }
     g_spin.clear();

@@ -11,12 +11,16 @@
 // M is never stored.  Each workgroup owns GM consecutive orders, a tile of TJ
 // output indices j (m' for the inverse, l for the forward) and up to CTILE
 // columns.  Its producer waves own the Wigner chains of the tile's j:
-//   inverse: chains in l (the GEMM's K axis) for (m', m) and (m', -s);
-//   forward: chains in m' (the K axis) for (l, m) and (l, -s),
-// run them in FP64 (chain.h) and emit one K-slab of M at a time into LDS;
+//   inverse: chains in l (the GEMM's K axis) for (m', m);
+//   forward: chains in m' (the K axis) for (l, m),
+// run them in FP64 (chain.h), multiply by the spin factor
+// sqrt((2l+1)/4pi) d^l_{m',-s}(pi/2) (the same for every order, so it is
+// tabulated once per (L, s) in the plan) and emit one K-slab of M at a time;
 // its consumer waves multiply the previous slab on the matrix cores
 //   out[c][j] += sum_k X^T[c][k] M[k][j]   (v_mfma 16x16x4, f32 or f64)
 // while the producers fill the next one (double-buffered LDS).
+#include <type_traits>
+
 #include "chain.h"
 
 namespace sht {
@@ -63,9 +67,8 @@ template <typename T> struct Args {
     const T *X;           // [L][C][L]
     T *Y;                 // [L][C][L]
     EdgeTable E;
-    const SpinState *ss;  // [L][L], inverse only
-    const double *ri;     // [L][L] 1/sqrt((l+1)^2 - j^2)
-    const double *rf;     // [L][L] 1/sqrt((l+k)(l-k+1)) at [k][l]
+    const double *rtab;   // [L][L] recursion rsqrt at [k][j] (ri or rf)
+    const T *wtab;        // [L][L] spin factor at [k][j] (wi or wf)
     const double2 *fab;   // [L][L] order-side l-recursion factors
     const double *cl;     // [L] sqrt((2l+1)/4pi)
 };
@@ -83,10 +86,10 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
     // disjoint banks; X slab stored [c][k] with an odd row length.
     __shared__ T Mt[2][GM][TK][TJ + 16];
     __shared__ T Xt[2][GM][CTILE][TK + 1];
-    __shared__ double fam[2][GM + 1][TK], fbm[2][GM + 1][TK], fcl[2][TK];
+    __shared__ double fam[2][GM][TK], fbm[2][GM][TK];
 
     const int L = a.L, s = a.s, Cn = a.C;
-    const int sigma = -s, asg = s < 0 ? -s : s;
+    const int asg = s < 0 ? -s : s;
     // Hardware workgroup b runs on XCD b mod 8.  Order group mg goes to XCD
     // mg mod 8 with all its j tiles and column blocks (they stream the same X
     // panel through that XCD's L2); each XCD takes its groups in ascending
@@ -130,14 +133,13 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
         const int j = j0 + jl;
         const bool jvalid = j < L;
         const double jd = (double)j;
-        Chain ch[NCH], sc;
+        Chain ch[NCH];
         int l0[NCH];
         double sv[NCH], twom[NCH];
         bool vch[NCH];
-        int l0s;
-        double ssv;
-        // chains start at zero with the scale of their seed; the seed is
-        // added by the step that reaches the chain's edge degree / order
+        // chains start at zero with the scale of their seed; the seed is added
+        // by the step that reaches the chain's edge (degree for the inverse,
+        // order for the forward)
 #pragma unroll
         for (int g = 0; g < NCH; ++g) {
             const int m = m0 + sub * NCH + g;
@@ -148,72 +150,55 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
             ch[g].k = sd.k;
             ch[g].es = emit_scale(sd.k);
             sv[g] = sd.v;
-            l0[g] = MODE == kInverse ? (j > m ? j : m) : j;
+            l0[g] = !vch[g] ? -2 : (MODE == kInverse ? (j > m ? j : m) : j);
             twom[g] = 2.0 * m;
-        }
-        {
-            const bool vs = jvalid && (MODE == kInverse || j >= asg);
-            const Seed sd = vs ? edge_seed(a.E, j, sigma) : Seed{0.0, 0};
-            sc.d = 0.0;
-            sc.dp = 0.0;
-            sc.k = sd.k;
-            sc.es = emit_scale(sd.k);
-            ssv = sd.v;
-            l0s = MODE == kInverse ? (j > asg ? j : asg) : (vs ? j : -1);
         }
         double q = 0.0;      // inverse: sqrt(l^2 - j^2) at the current l
         double gprev = 0.0;  // forward: sqrt((l+m'+1)(l-m')) of the previous m'
-        double clj = 0.0;    // forward: sqrt((2l+1)/4pi)
         if (MODE == kInverse) {
-            if (jvalid && l0s < kfirst) {  // resume the spin chain from the plan
-                const SpinState st = a.ss[(size_t)kfirst * L + j];
-                sc.d = st.d;
-                sc.dp = st.dp;
-                sc.k = st.k;
-                sc.es = emit_scale(st.k);
-            }
-            if (l0s == kfirst) sc.d = ssv;
 #pragma unroll
             for (int g = 0; g < NCH; ++g)
-                if (vch[g] && l0[g] == kfirst) ch[g].d = sv[g];
+                if (l0[g] == kfirst) ch[g].d = sv[g];
             const double Y = (double)kfirst * kfirst - jd * jd;
             q = Y > 0.0 ? sqrt(Y) : 0.0;
         } else {
-            clj = jvalid ? a.cl[j] : 0.0;
-            if (jvalid && l0s == kfirst) sc.d = ssv;
 #pragma unroll
             for (int g = 0; g < NCH; ++g)
-                if (vch[g] && j == kfirst) ch[g].d = sv[g];
+                if (l0[g] == kfirst) ch[g].d = sv[g];
         }
 
-        // reciprocal square roots of the recursion for this j, one slab ahead
-        const double *rtab = (MODE == kInverse ? a.ri : a.rf) + (jvalid ? j : 0);
+        // per-step recursion rsqrt and spin factor sqrt((2l+1)/4pi) d^l_{.,-s}
+        // for this j, one slab ahead: rr/wr hold slab `chunk`, rn/wn are
+        // loaded for `chunk + 1` (the spin factor is held in the output
+        // precision: it multiplies a value rounded to T on emission anyway)
+        const double *rtab = a.rtab + (jvalid ? j : 0);
+        const T *wtab = a.wtab + (jvalid ? j : 0);
         double rr[TK], rn[TK];
-        auto load_rec = [&](int chunk, double *dst) {
+        T wr[TK], wn[TK];
+        auto load_steps = [&](int chunk, double *dr, T *dw) {
             const int kbase = kbase_of(chunk);
 #pragma unroll
             for (int kk = 0; kk < TK; ++kk) {
                 const int k = kbase + kk;
                 const bool ok = jvalid && chunk < nchunks && k >= 0 && k < L;
-                dst[kk] = ok ? rtab[k * L] : 0.0;
+                dr[kk] = ok ? rtab[k * L] : 0.0;
+                dw[kk] = ok ? wtab[k * L] : T(0);
             }
         };
         // order-side factors of the l-recursion for one slab (inverse)
         auto fill_factors = [&](int chunk, int buf) {
-            if (MODE == kInverse && ptid < (GM + 1) * TK && chunk < nchunks) {
+            if (MODE == kInverse && ptid < GM * TK && chunk < nchunks) {
                 const int gi = ptid / TK, kk = ptid % TK;
                 const int l = kbase_of(chunk) + kk;
-                const int idx = gi < GM ? m0 + gi : asg;
-                double am = 0.0, bm = 0.0, c = 0.0;
+                const int idx = m0 + gi;
+                double am = 0.0, bm = 0.0;
                 if (l < L && idx < L) {
                     const double2 f = a.fab[idx * L + l];
                     am = f.x;
                     bm = f.y;
                 }
-                if (gi == GM && sigma < 0) am = -am;  // am is odd in the order, bm even
                 fam[buf][gi][kk] = am;
                 fbm[buf][gi][kk] = bm;
-                if (gi == 0) fcl[buf][kk] = l < L ? a.cl[l] : 0.0;
             }
         };
         // keep |d| < 2^512 for chains still below the double range (checked once
@@ -226,77 +211,81 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
                 c.es = emit_scale(c.k);
             }
         };
-        auto generate = [&](int chunk, int buf) {
+        // one slab; INJ = some lane of the wave reaches a chain edge in it
+        auto steps = [&](int chunk, int buf, auto inj_tag) {
+            constexpr bool INJ = decltype(inj_tag)::value;
             const int kbase = kbase_of(chunk);
-            load_rec(chunk + 1, rn);
             if (MODE == kInverse) {
                 double Xl = (double)(kbase + 1) * (kbase + 1) - jd * jd;
-#pragma unroll 4
+#pragma unroll
                 for (int kk = 0; kk < TK; ++kk) {
                     const int l = kbase + kk;
-                    const double W = fcl[buf][kk] * sc.d * sc.es;
+                    const T W = wr[kk];
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es * W);
+                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es) * W;
                     // step l -> l+1
                     const double r = rr[kk];
                     const double ap = jd * r, bp = q * r;
                     q = Xl * r;
                     Xl += 2.0 * l + 3.0;
-                    {
-                        double dn = -(ap * fam[buf][GM][kk] * sc.d + bp * fbm[buf][GM][kk] * sc.dp);
-                        dn += (l + 1 == l0s) ? ssv : 0.0;
-                        sc.dp = sc.d;
-                        sc.d = dn;
-                    }
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
                         const int gi = sub * NCH + g;
                         double dn = -(ap * fam[buf][gi][kk] * ch[g].d + bp * fbm[buf][gi][kk] * ch[g].dp);
-                        dn += (vch[g] && l + 1 == l0[g]) ? sv[g] : 0.0;
+                        if constexpr (INJ) dn += (l + 1 == l0[g]) ? sv[g] : 0.0;
                         ch[g].dp = ch[g].d;
                         ch[g].d = dn;
                     }
                 }
             } else {
-                const double W0 = clj;
-#pragma unroll 4
+#pragma unroll
                 for (int kk = TK - 1; kk >= 0; --kk) {
                     const int k = kbase + kk;  // m'
-                    const double W = W0 * sc.d * sc.es;
+                    const T W = wr[kk];
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es * W);
+                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es) * W;
                     // step m' -> m'-1
                     const double y = rr[kk];
                     const double gcur = (double)(j + k) * (double)(j - k + 1) * y;
-                    {
-                        double dn = (2.0 * sigma * sc.d - gprev * sc.dp) * y;
-                        dn += (k - 1 == l0s) ? ssv : 0.0;
-                        sc.dp = sc.d;
-                        sc.d = dn;
-                    }
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
                         double dn = (twom[g] * ch[g].d - gprev * ch[g].dp) * y;
-                        dn += (vch[g] && k - 1 == j) ? sv[g] : 0.0;
+                        if constexpr (INJ) dn += (k - 1 == l0[g]) ? sv[g] : 0.0;
                         ch[g].dp = ch[g].d;
                         ch[g].d = dn;
                     }
                     gprev = gcur;
                 }
             }
-            renorm(sc);
+        };
+        auto generate = [&](int chunk, int buf) {
+            const int kbase = kbase_of(chunk);
+            load_steps(chunk + 1, rn, wn);
+            // edges reached in this slab: inverse l+1 in (kbase, kbase+TK],
+            // forward m'-1 in [kbase-1, kbase+TK-2]
+            bool mine = false;
+#pragma unroll
+            for (int g = 0; g < NCH; ++g) {
+                const int e = l0[g];
+                mine |= MODE == kInverse ? (e > kbase && e <= kbase + TK) : (e >= kbase - 1 && e <= kbase + TK - 2);
+            }
+            if (__any(mine)) steps(chunk, buf, std::true_type{});
+            else steps(chunk, buf, std::false_type{});
 #pragma unroll
             for (int g = 0; g < NCH; ++g) renorm(ch[g]);
 #pragma unroll
-            for (int kk = 0; kk < TK; ++kk) rr[kk] = rn[kk];
+            for (int kk = 0; kk < TK; ++kk) {
+                rr[kk] = rn[kk];
+                wr[kk] = wn[kk];
+            }
         };
 
         // ---- pipeline: producers run one slab ahead of the consumers.  Each
         // role has its own loop (disjoint register live ranges); both execute
         // the same number of workgroup barriers, and every wave takes one role.
-        load_rec(0, rr);
+        load_steps(0, rr, wr);
         fill_factors(0, 0);
         __syncthreads();
         generate(0, 0);
@@ -434,7 +423,7 @@ hipError_t launch_one(Args<T> a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
-                           const SpinState *ss, const RecTables &rt, hipStream_t st) {
+                           const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
     Args<T> a;
     a.L = L;
     a.s = s;
@@ -444,9 +433,9 @@ hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, cons
     a.X = X;
     a.Y = Y;
     a.E = E;
-    a.ss = ss;
-    a.ri = rt.ri;
-    a.rf = rt.rf;
+    a.rtab = mode == kInverse ? rt.ri : rt.rf;
+    if constexpr (sizeof(T) == 8) a.wtab = (const T *)(mode == kInverse ? sp.wi : sp.wf);
+    else a.wtab = (const T *)(mode == kInverse ? sp.wi32 : sp.wf32);
     a.fab = rt.fab;
     a.cl = rt.cl;
     if (a.C <= 16) {
@@ -458,12 +447,12 @@ hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, cons
 }
 
 template hipError_t launch_contract<double>(int, int, int, int, const double *, double *, const EdgeTable &,
-                                            const SpinState *, const RecTables &, hipStream_t);
+                                            const SpinPlan &, const RecTables &, hipStream_t);
 template hipError_t launch_contract<float>(int, int, int, int, const float *, float *, const EdgeTable &,
-                                           const SpinState *, const RecTables &, hipStream_t);
+                                           const SpinPlan &, const RecTables &, hipStream_t);
 
 hipError_t launch_contract_bf16x3(int, int, int, int, const float *, float *, const EdgeTable &,
-                                  const SpinState *, hipStream_t) {
+                                  const SpinPlan &, const RecTables &, hipStream_t) {
     return hipErrorNotSupported;
 }
 

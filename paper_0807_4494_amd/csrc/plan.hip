@@ -47,11 +47,13 @@ hipError_t launch_edge_table(EdgeTable &E, hipStream_t st) {
     return hipGetLastError();
 }
 
-// ------------------------------------------------------- spin states -----
+// ------------------------------------------------------- spin tables -----
 // For each m' in [0, L): the chain d^l_{m', sigma}(pi/2), sigma = -s, run in l
-// from its edge l0 = max(m', |sigma|), storing (d^l, d^{l-1}, scale) at every l.
-// The inverse contraction resumes these chains at the first degree of its tile.
-__global__ void k_spin_states(EdgeTable E, SpinState *ss, int L, int sigma) {
+// from its edge l0 = max(m', |sigma|) with the l-recursion, written as
+// wi[l][m'] = cl[l] d^l_{m',sigma}.  Values below the double
+// range (scale level >= 1) are stored as their unscaled product, i.e. 0 or a
+// subnormal: they multiply Wigner values <= 1 and vanish in the sums.
+__global__ void k_spin_inverse(EdgeTable E, const double *ri, const double *cl, double *wi, int L, int sigma) {
     const int mp = blockIdx.x * blockDim.x + threadIdx.x;
     if (mp >= L) return;
     const int asg = sigma < 0 ? -sigma : sigma;
@@ -61,15 +63,11 @@ __global__ void k_spin_states(EdgeTable E, SpinState *ss, int L, int sigma) {
     double q = 0.0;  // sqrt(l^2 - m'^2) at the current l
     for (int l = 0; l < L; ++l) {
         if (l == l0) c.inject(edge_seed(E, mp, sigma));
-        SpinState st;
-        st.d = c.d;
-        st.dp = c.dp;
-        st.k = c.k;
-        st.pad = 0;
-        ss[(size_t)l * L + mp] = st;
+        const size_t idx = (size_t)l * L + mp;
+        wi[idx] = cl[l] * c.value();
         // transition l -> l+1
         const double X = (double)(l + 1) * (l + 1) - (double)mp * mp;
-        const double r = rsqrt(X > 1.0 ? X : 1.0);
+        const double r = ri[idx];
         const double ap = (double)mp * r, bp = q * r;
         q = X > 0.0 ? X * r : 0.0;
         double am, bm;
@@ -79,10 +77,24 @@ __global__ void k_spin_states(EdgeTable E, SpinState *ss, int L, int sigma) {
     }
 }
 
-hipError_t launch_spin_states(const EdgeTable &E, SpinPlan &sp, hipStream_t st) {
+// wf[m'][l] = wi[l][m'], and both rounded to FP32
+__global__ void k_spin_forward(const double *wi, double *wf, float *wi32, float *wf32, int L) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)L * L) return;
+    const int k = (int)(idx / L), l = (int)(idx % L);
+    const double w = wi[(size_t)l * L + k];
+    wf[idx] = w;
+    wf32[idx] = (float)w;
+    wi32[idx] = (float)wi[idx];
+}
+
+hipError_t launch_spin_tables(const EdgeTable &E, const RecTables &rt, SpinPlan &sp, hipStream_t st) {
     const int threads = 64;
-    hipLaunchKernelGGL(k_spin_states, dim3((sp.L + threads - 1) / threads), dim3(threads), 0, st,
-                       E, sp.ss, sp.L, -sp.spin);
+    hipLaunchKernelGGL(k_spin_inverse, dim3((sp.L + threads - 1) / threads), dim3(threads), 0, st, E, rt.ri,
+                       rt.cl, sp.wi, sp.L, -sp.spin);
+    const size_t n = (size_t)sp.L * sp.L;
+    hipLaunchKernelGGL(k_spin_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sp.wi, sp.wf, sp.wi32,
+                       sp.wf32, sp.L);
     return hipGetLastError();
 }
 

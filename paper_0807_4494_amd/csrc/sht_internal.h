@@ -43,13 +43,6 @@ struct EdgeTable {
     int lmax = 0;
 };
 
-// State of the spin chain d^l_{m', -s}(pi/2) over l, per (l, m'):
-// d = value at l, dp = value at l-1, both scaled by 2^(512 k).
-struct SpinState {
-    double d, dp;
-    int k, pad;
-};
-
 // Per-(L, precision) tables for the torus FFT stages.
 template <typename T> struct FftTables {
     using C = typename CT<T>::type;
@@ -86,15 +79,20 @@ struct Plan {
     RecTables rec;
 };
 
+// Per-(L, spin) spin factors of the contraction, sqrt((2l+1)/4pi) d^l_{m',-s}(pi/2),
+// in the two layouts the K loops stream (FP64, and rounded to FP32 for the
+// FP32 path):
+//   wi[l*L + m'] (inverse, K = l),   wf[m'*L + l] (forward, K = m')
 struct SpinPlan {
     int device = 0, L = 0, spin = 0;
-    SpinState *ss = nullptr;  // [L][L]
+    double *wi = nullptr, *wf = nullptr;
+    float *wi32 = nullptr, *wf32 = nullptr;
 };
 
 // -------------------------------------------------------- kernel launches ---
 // plan.hip
 hipError_t launch_edge_table(EdgeTable &E, hipStream_t st);
-hipError_t launch_spin_states(const EdgeTable &E, SpinPlan &sp, hipStream_t st);
+hipError_t launch_spin_tables(const EdgeTable &E, const RecTables &rt, SpinPlan &sp, hipStream_t st);
 hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
@@ -125,9 +123,9 @@ hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf,
 enum ContractMode { kInverse = 0, kForward = 1 };
 template <typename T>
 hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
-                           const SpinState *ss, const RecTables &rt, hipStream_t st);
+                           const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y,
-                                  const EdgeTable &E, const SpinState *ss, hipStream_t st);
+                                  const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 
 // ------------------------------------------------------------- helpers -----
 inline int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
