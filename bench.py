@@ -62,6 +62,34 @@ def stage_bytes(stage: str, L: int, B: int, cbytes: int) -> float:
     raise KeyError(stage)
 
 
+def recorded_traffic(kernel: str, workload: str, prec: str):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the same counters on a plain
+    copy), or None when there is none for this workload and precision or the
+    kernel's sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*_pmc.md"))):
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#")):
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
+        if fields.get("kernel") != kernel or fields.get("workload") != f"{workload} {prec}":
+            continue
+        h = hashlib.sha256()
+        try:
+            for src in fields["sources"].split():
+                with open(os.path.join(ROOT, src), "rb") as fh:
+                    h.update(fh.read())
+        except (OSError, KeyError):
+            return None
+        if h.hexdigest() != fields.get("source_sha256"):
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def run_steps(sht, torch, wl, prec, flm, steps, warmup, trace):
     L, B = wl.L, wl.batch
     dev = flm[wl.spins[0]].device
@@ -159,25 +187,30 @@ def main() -> int:
     cbytes = 16 if prec == "fp64" else 8
     stages_ms = {k: v[0] / args.steps for k, v in stages.items()}
     counts = {k: v[1] for k, v in stages.items()}
-    dominant = max(stages_ms, key=lambda k: stages_ms[k])
-    if dominant.startswith("contract"):
-        launches = [(st_, s) for s in wl.spins for st_ in ("contract_inv", "contract_fwd")]
-        flops = sum(contraction_flops(L, s, B) for _, s in launches) * args.steps
-        t = (stages["contract_inv"][0] + stages["contract_fwd"][0]) / 1e3
+    # the dominant kernel by total time per step: the contraction kernel serves
+    # two stages (inverse and forward launches), every other stage is its own
+    groups = {"k_contract": ("contract_inv", "contract_fwd")}
+    groups.update({k: (k,) for k in stages_ms if not k.startswith("contract")})
+    dominant = max(groups, key=lambda g: sum(stages_ms[k] for k in groups[g]))
+    members = groups[dominant]
+    n_launch = sum(counts[k] for k in members)
+    t = sum(stages[k][0] for k in members) / 1e3
+    if dominant == "k_contract":
+        flops = sum(contraction_flops(L, s, B) for s in wl.spins for _ in members) * args.steps
         achieved = flops / t / 1e12
         peak = PEAK["fp64_mfma_TFs"] if prec == "fp64" else PEAK["fp32_mfma_TFs"]
         roof = {"bound": "mfma", "kernel": "k_contract (inverse + forward launches)",
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "launches": counts["contract_inv"] + counts["contract_fwd"],
-                "avg_launch_ms": round(t * 1e3 / (counts["contract_inv"] + counts["contract_fwd"]), 4)}
+                "frac": round(achieved / peak, 4),
+                "traffic": recorded_traffic("k_contract", wl.name, prec),
+                "launches": n_launch, "avg_launch_ms": round(t * 1e3 / n_launch, 4)}
     else:
         by = stage_bytes(dominant, L, B, cbytes) * counts[dominant]
-        t = stages[dominant][0] / 1e3
         achieved = by / t / 1e9
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK["hbm_GBs"],
-                "unit": "GB/s", "frac": round(achieved / PEAK["hbm_GBs"], 4), "traffic": None,
-                "launches": counts[dominant], "avg_launch_ms": round(stages[dominant][0] / counts[dominant], 4)}
+                "unit": "GB/s", "frac": round(achieved / PEAK["hbm_GBs"], 4),
+                "traffic": recorded_traffic(dominant, wl.name, prec),
+                "launches": n_launch, "avg_launch_ms": round(t * 1e3 / n_launch, 4)}
 
     # every stage against its own roofline
     stage_roof = {}

@@ -10,7 +10,8 @@
  * ---------------------------------------
  * L        band-limit: degrees 0 <= l < L.  N = 2L - 1 samples per torus axis.
  *          (The paper writes the largest degree as its band-limit, with
- *          N = 2 L_paper + 1; L here is L_paper + 1.)  2 <= L <= SHT_L_MAX.
+ *          N = 2 L_paper + 1; L here is L_paper + 1.)  1 <= L <= SHT_L_MAX
+ *          (L = 1 is the single monopole sample).
  * spin     integer s with |s| < L.  Coefficients with l < |s| do not exist
  *          (Section 2.3): they are ignored on input and written as 0.
  * batch    number of maps per call, 1 <= batch <= SHT_BATCH_MAX.
@@ -29,7 +30,9 @@
  *   flm  [batch][L*L]        coefficient f_lm at index l*l + l + m.
  *   map  [batch][L][N]       sample f(theta_t, phi_p) at [t][p].
  *   Element type: complex double for SHT_FP64, complex float otherwise.
- *   Pointers must be 16-byte aligned (SHT_ERR_ALIGNMENT otherwise).
+ *   flm and map must be aligned to their complex element (16 bytes for
+ *   SHT_FP64, 8 otherwise) and the workspace to 256 bytes
+ *   (SHT_ERR_ALIGNMENT otherwise).
  *
  * Ownership: the caller owns flm, map and workspace and keeps them alive
  * until the stream reaches the call.  The library owns its plan cache (Wigner
@@ -65,7 +68,7 @@ enum sht_status {
     SHT_ERR_INVALID_ARG = -1,   /* L, spin, batch out of range, NULL pointer */
     SHT_ERR_UNSUPPORTED = -2,   /* unknown sampling or precision */
     SHT_ERR_WORKSPACE = -3,     /* ws_bytes < sht_workspace_bytes(...) */
-    SHT_ERR_ALIGNMENT = -4,     /* flm, map or workspace not 16-byte aligned */
+    SHT_ERR_ALIGNMENT = -4,     /* flm / map not element-aligned, workspace not 256-byte aligned */
     SHT_ERR_OOM = -5,           /* plan allocation failed */
     SHT_ERR_HIP = -6            /* a HIP call or kernel launch failed */
 };
