@@ -11,12 +11,14 @@ Prints one JSON line (rank 0):
   metric, value (transforms/s), ms_per_step, dtype, config,
   roofline   the dominant kernel's achieved rate from HIP events recorded
              around every stage (library stage tracing, same stream) against
-             its roofline; algorithmic flops / bytes per launch as documented
-             in DESIGN.md,
+             its roofline; algorithmic flops / bytes per launch from
+             contraction_flops / stage_bytes below; traffic = HBM bytes per
+             launch from the committed counter summary (null if stale),
   cpu_baseline  the CPU oracle timed on a bounded sample (one map through
              inverse + forward) on this host,
-  fp64_path  the all-FP64 GPU path on the same workload, for comparison,
-  stages_ms  per-step time of every stage.
+  fp64_path, bf16x3_path  the same workload on the all-FP64 path and with the
+             BF16x3 contraction, for comparison,
+  stages     per-launch time and roofline fraction of every stage.
 """
 
 from __future__ import annotations
@@ -31,6 +33,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+# MFMA work per algorithmic flop and the peak it runs against: BF16x3 issues
+# three BF16 products per flop of the contraction
+MFMA_COST = {"fp64": (1.0, "fp64_mfma_TFs"), "fp32": (1.0, "fp32_mfma_TFs"), "bf16x3": (3.0, "bf16_mfma_TFs")}
 
 PEAK = {  # MI355X published peaks
     "hbm_GBs": 8000.0,
@@ -153,6 +159,7 @@ def main() -> int:
     ap.add_argument("--workload", default="L1024_s0pm2_b16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-bf16x3", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -196,9 +203,10 @@ def main() -> int:
     n_launch = sum(counts[k] for k in members)
     t = sum(stages[k][0] for k in members) / 1e3
     if dominant == "k_contract":
-        flops = sum(contraction_flops(L, s, B) for s in wl.spins for _ in members) * args.steps
+        mult, pkey = MFMA_COST[prec]
+        flops = mult * sum(contraction_flops(L, s, B) for s in wl.spins for _ in members) * args.steps
         achieved = flops / t / 1e12
-        peak = PEAK["fp64_mfma_TFs"] if prec == "fp64" else PEAK["fp32_mfma_TFs"]
+        peak = PEAK[pkey]
         roof = {"bound": "mfma", "kernel": "k_contract (inverse + forward launches)",
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
@@ -219,8 +227,9 @@ def main() -> int:
             continue
         avg_s = tot[0] / tot[1] / 1e3
         if k.startswith("contract"):
-            f = sum(contraction_flops(L, s, B) for s in wl.spins) / len(wl.spins)
-            pk = PEAK["fp64_mfma_TFs"] if prec == "fp64" else PEAK["fp32_mfma_TFs"]
+            mult, pkey = MFMA_COST[prec]
+            f = mult * sum(contraction_flops(L, s, B) for s in wl.spins) / len(wl.spins)
+            pk = PEAK[pkey]
             stage_roof[k] = {"ms": round(avg_s * 1e3, 4), "TFLOP/s": round(f / avg_s / 1e12, 2),
                              "frac": round(f / avg_s / 1e12 / pk, 4)}
         else:
@@ -256,6 +265,13 @@ def main() -> int:
                    for s in wl.spins)
         out["fp64_path"] = {"value": round(per_step / (ms64 / 1e3), 2), "ms_per_step": round(ms64, 4),
                             "steps": n64, "round_trip_rel_l2": rt64}
+    if not args.no_bf16x3 and prec == "fp32":
+        n3 = max(2, min(args.steps, 10))
+        ms3, _, back3 = run_steps(sht, torch, wl, "bf16x3", flm, n3, 1, trace=False)
+        rt3 = max(float(torch.linalg.vector_norm(back3[s] - flm[s]) / torch.linalg.vector_norm(flm[s]))
+                  for s in wl.spins)
+        out["bf16x3_path"] = {"value": round(per_step / (ms3 / 1e3), 2), "ms_per_step": round(ms3, 4),
+                              "steps": n3, "round_trip_rel_l2": rt3}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

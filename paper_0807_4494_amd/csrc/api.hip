@@ -102,7 +102,6 @@ void regions(int L, int batch, int precision, size_t &ra, size_t &rb) {
 int check_args(int L, int spin, int batch, int sampling, int precision) {
     if (sampling != SHT_SAMPLING_MW) return SHT_ERR_UNSUPPORTED;
     if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_ERR_UNSUPPORTED;
-    if (precision == SHT_BF16X3) return SHT_ERR_UNSUPPORTED;
     if (L < 1 || L > SHT_L_MAX) return SHT_ERR_INVALID_ARG;
     if (spin <= -L || spin >= L) return SHT_ERR_INVALID_ARG;
     if (batch < 1 || batch > SHT_BATCH_MAX) return SHT_ERR_INVALID_ARG;
@@ -220,9 +219,19 @@ int check_buffers(int L, int batch, int precision, const void *in, const void *o
     return SHT_OK;
 }
 
+// The contraction in the path's own precision, or as BF16x3 on FP32 data.
 template <typename T>
-int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const RecTables &rec, const DeviceState *ds,
-                const SpinPlan *sp, const void *flm, void *map, void *ws, hipStream_t st) {
+hipError_t contract(int mode, bool bf16x3, int L, int spin, int batch, const T *X, T *Y, const DeviceState *ds,
+                    const SpinPlan *sp, const RecTables &rec, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        if (bf16x3) return launch_contract_bf16x3(mode, L, spin, batch, X, Y, ds->E, *sp, rec, st);
+    }
+    return launch_contract<T>(mode, L, spin, batch, X, Y, ds->E, *sp, rec, st);
+}
+
+template <typename T>
+int run_inverse(int L, int spin, int batch, bool bf16x3, const FftTables<T> &ft, const RecTables &rec,
+                const DeviceState *ds, const SpinPlan *sp, const void *flm, void *map, void *ws, hipStream_t st) {
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
@@ -231,7 +240,7 @@ int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const RecTab
     SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st, [&] { return launch_layout_in<T>(L, spin, batch, flm, P, st); }),
             "layout_in");
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
-                   [&] { return launch_contract<T>(kInverse, L, spin, batch, P, R, ds->E, *sp, rec, st); }),
+                   [&] { return contract<T>(kInverse, bf16x3, L, spin, batch, P, R, ds, sp, rec, st); }),
             "contract inverse");
     // theta stage writes rows g_mu(theta_t) over t (region A); the transpose
     // makes rings over mu (region B) for the phi stage
@@ -248,8 +257,8 @@ int run_inverse(int L, int spin, int batch, const FftTables<T> &ft, const RecTab
 }
 
 template <typename T>
-int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const RecTables &rec, const DeviceState *ds,
-                const SpinPlan *sp, const void *map, void *flm, void *ws, hipStream_t st) {
+int run_forward(int L, int spin, int batch, bool bf16x3, const FftTables<T> &ft, const RecTables &rec,
+                const DeviceState *ds, const SpinPlan *sp, const void *map, void *flm, void *ws, hipStream_t st) {
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
@@ -267,7 +276,7 @@ int run_forward(int L, int spin, int batch, const FftTables<T> &ft, const RecTab
             "theta forward");
     T *R = (T *)(w + ra);
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
-                   [&] { return launch_contract<T>(kForward, L, spin, batch, X, R, ds->E, *sp, rec, st); }),
+                   [&] { return contract<T>(kForward, bf16x3, L, spin, batch, X, R, ds, sp, rec, st); }),
             "contract forward");
     SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st, [&] { return launch_layout_out<T>(L, spin, batch, R, flm, st); }),
             "layout_out");
@@ -298,8 +307,9 @@ int sht_inverse(int L, int spin, int batch, int sampling, int precision, const v
     rc = prepare(L, spin, st, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     if (precision == SHT_FP64)
-        return run_inverse<double>(L, spin, batch, plan->f64, plan->rec, ds, sp, flm, map, workspace, st);
-    return run_inverse<float>(L, spin, batch, plan->f32, plan->rec, ds, sp, flm, map, workspace, st);
+        return run_inverse<double>(L, spin, batch, false, plan->f64, plan->rec, ds, sp, flm, map, workspace, st);
+    return run_inverse<float>(L, spin, batch, precision == SHT_BF16X3, plan->f32, plan->rec, ds, sp, flm, map,
+                              workspace, st);
 }
 
 int sht_forward(int L, int spin, int batch, int sampling, int precision, const void *map, void *flm,
@@ -315,8 +325,9 @@ int sht_forward(int L, int spin, int batch, int sampling, int precision, const v
     rc = prepare(L, spin, st, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     if (precision == SHT_FP64)
-        return run_forward<double>(L, spin, batch, plan->f64, plan->rec, ds, sp, map, flm, workspace, st);
-    return run_forward<float>(L, spin, batch, plan->f32, plan->rec, ds, sp, map, flm, workspace, st);
+        return run_forward<double>(L, spin, batch, false, plan->f64, plan->rec, ds, sp, map, flm, workspace, st);
+    return run_forward<float>(L, spin, batch, precision == SHT_BF16X3, plan->f32, plan->rec, ds, sp, map, flm,
+                              workspace, st);
 }
 
 int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) {

@@ -17,8 +17,14 @@
 // sqrt((2l+1)/4pi) d^l_{m',-s}(pi/2) (the same for every order, so it is
 // tabulated once per (L, s) in the plan) and emit one K-slab of M at a time;
 // its consumer waves multiply the previous slab on the matrix cores
-//   out[c][j] += sum_k X^T[c][k] M[k][j]   (v_mfma 16x16x4, f32 or f64)
-// while the producers fill the next one (double-buffered LDS).
+//   out[c][j] += sum_k X^T[c][k] M[k][j]
+// while the producers fill the next one (double-buffered LDS).  Three
+// precisions share the kernel:
+//   FP64    M and X in FP64, v_mfma_f64_16x16x4;
+//   FP32    M rounded to FP32, v_mfma_f32_16x16x4;
+//   BF16x3  M and X split into BF16 pairs hi + lo, three v_mfma_f32_16x16x16
+//           BF16 products hi*hi + hi*lo + lo*hi accumulated in FP32 (the
+//           lo*lo term, ~2^-16 relative, is dropped).
 #include <type_traits>
 
 #include "chain.h"
@@ -29,6 +35,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
 // Output layout of the 16x16x4 MFMAs (measured on gfx950): element r of lane
@@ -49,17 +56,50 @@ template <> struct Mfma<double> {
     }
 };
 
-// Tile shapes.  A workgroup is 8 waves: waves 0-3 consume (MFMA), waves 4-7
-// produce (FP64 Wigner chains).  TJ output indices j per workgroup, WJ per
-// consumer wave; GM orders m; TK rows of K per slab.
-template <typename T> struct Tile;
-template <> struct Tile<float> { static constexpr int TJ = 128, WJ = 32; };
-template <> struct Tile<double> { static constexpr int TJ = 64, WJ = 16; };
+// BF16 pair of an FP32 value: hi = v rounded to BF16 (nearest, ties to
+// even), lo = the remainder v - hi rounded the same way; hi + lo carries
+// about 16 significant bits.  Finite inputs only.
+__device__ inline unsigned short bf16_rne(float v) {
+    const unsigned u = __float_as_uint(v);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ inline void bf16_split(float v, unsigned short &hi, unsigned short &lo) {
+    hi = bf16_rne(v);
+    lo = bf16_rne(v - bf16_value(hi));
+}
 
 constexpr int GM = 4;    // orders per workgroup
 constexpr int TK = 16;   // K slab
 constexpr int NT = 512;  // threads: 256 consumers + 256 producers
 constexpr int NC = 256;  // consumer threads
+
+// Precision policies.  A workgroup is 8 waves: waves 0-3 consume (MFMA),
+// waves 4-7 produce (FP64 Wigner chains).  TJ output indices j per
+// workgroup, WJ per consumer wave; GM orders m; TK rows of K per slab.
+enum { kP64 = 0, kP32 = 1, kPBF = 2 };
+template <int P> struct Prec;
+template <> struct Prec<kP64> { using T = double; static constexpr int TJ = 64, WJ = 16; };
+template <> struct Prec<kP32> { using T = float; static constexpr int TJ = 128, WJ = 32; };
+template <> struct Prec<kPBF> { using T = float; static constexpr int TJ = 128, WJ = 32; };
+
+// LDS slabs.  FP32 / FP64: M slab [k][j] with rows padded by 16 so the four K
+// rows an MFMA fragment spans hit disjoint banks; X slab [c][k] with an odd
+// row length.  BF16x3: the 16x16x16 BF16 fragments hold four consecutive k
+// per lane, so M is stored [k/4][j][k%4] and X [c][k] (row of TK + 4, so a
+// lane's four k are one aligned 8-byte read), each as hi and lo planes.
+template <int P, int CTILE> struct Slabs {
+    using T = typename Prec<P>::T;
+    T M[2][GM][TK][Prec<P>::TJ + 16];
+    T X[2][GM][CTILE][TK + 1];
+};
+template <int CTILE> struct Slabs<kPBF, CTILE> {
+    static constexpr int TJ = Prec<kPBF>::TJ;
+    alignas(16) unsigned short Mh[2][GM][TK / 4][TJ + 16][4];
+    alignas(16) unsigned short Ml[2][GM][TK / 4][TJ + 16][4];
+    alignas(16) unsigned short Xh[2][GM][CTILE][TK + 4];
+    alignas(16) unsigned short Xl[2][GM][CTILE][TK + 4];
+};
 
 template <typename T> struct Args {
     int L, s, B, C;       // C = 4B columns
@@ -73,19 +113,18 @@ template <typename T> struct Args {
     const double *cl;     // [L] sqrt((2l+1)/4pi)
 };
 
-template <typename T, int MODE, int CTILE>
-__global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
-    constexpr int TJ = Tile<T>::TJ, WJ = Tile<T>::WJ;
+template <int P, int MODE, int CTILE>
+__global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
+    using T = typename Prec<P>::T;
+    constexpr bool BF = P == kPBF;
+    constexpr int TJ = Prec<P>::TJ, WJ = Prec<P>::WJ;
     constexpr int NPJ = NC / TJ;    // producer threads sharing one j
     constexpr int NCH = GM / NPJ;   // main chains per producer thread
     constexpr int NCI = CTILE / 16, NJI = WJ / 16;
     constexpr int XPT = GM * CTILE * TK / NC;  // X slab elements per consumer thread
     using acc_t = typename Mfma<T>::acc;
 
-    // M slab rows padded by 16 so the four K rows an MFMA fragment spans hit
-    // disjoint banks; X slab stored [c][k] with an odd row length.
-    __shared__ T Mt[2][GM][TK][TJ + 16];
-    __shared__ T Xt[2][GM][CTILE][TK + 1];
+    __shared__ Slabs<P, CTILE> sm;
     __shared__ double fam[2][GM][TK], fbm[2][GM][TK];
 
     const int L = a.L, s = a.s, Cn = a.C;
@@ -201,6 +240,17 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
                 fbm[buf][gi][kk] = bm;
             }
         };
+        // one entry of M, rounded to the MFMA precision, into LDS
+        auto emit = [&](int buf, int gi, int kk, double dv, T W) {
+            if constexpr (BF) {
+                unsigned short hi, lo;
+                bf16_split((float)dv * W, hi, lo);
+                sm.Mh[buf][gi][kk >> 2][jl][kk & 3] = hi;
+                sm.Ml[buf][gi][kk >> 2][jl][kk & 3] = lo;
+            } else {
+                sm.M[buf][gi][kk][jl] = (T)dv * W;
+            }
+        };
         // keep |d| < 2^512 for chains still below the double range (checked once
         // per slab: one slab grows a chain by far less than 2^400)
         auto renorm = [&](Chain &c) {
@@ -223,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
                     const T W = wr[kk];
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es) * W;
+                        emit(buf, sub * NCH + g, kk, ch[g].d * ch[g].es, W);
                     // step l -> l+1
                     const double r = rr[kk];
                     const double ap = jd * r, bp = q * r;
@@ -245,7 +295,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
                     const T W = wr[kk];
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        Mt[buf][sub * NCH + g][kk][jl] = (T)(ch[g].d * ch[g].es) * W;
+                        emit(buf, sub * NCH + g, kk, ch[g].d * ch[g].es, W);
                     // step m' -> m'-1
                     const double y = rr[kk];
                     const double gcur = (double)(j + k) * (double)(j - k + 1) * y;
@@ -314,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
         const int c = rem / TK, kk = rem % TK;
         xok[i] = (m0 + g) < L && (c0 + c) < Cn;
         xoff[i] = (g * Cn + c0 + c) * L + kk;
-        xsl[i] = (g * CTILE + c) * (TK + 1) + kk;
+        xsl[i] = (g * CTILE + c) * (BF ? TK + 4 : TK + 1) + kk;
     }
     const T *xbase = a.X + (size_t)m0 * Cn * L;
     T xr[XPT];
@@ -331,9 +381,20 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
         }
     };
     auto store_x = [&](int buf) {
-        T *xt = &Xt[buf][0][0][0];
+        if constexpr (BF) {
+            unsigned short *xh = &sm.Xh[buf][0][0][0], *xl = &sm.Xl[buf][0][0][0];
 #pragma unroll
-        for (int i = 0; i < XPT; ++i) xt[xsl[i]] = xr[i];
+            for (int i = 0; i < XPT; ++i) {
+                unsigned short hi, lo;
+                bf16_split(xr[i], hi, lo);
+                xh[xsl[i]] = hi;
+                xl[xsl[i]] = lo;
+            }
+        } else {
+            T *xt = &sm.X[buf][0][0][0];
+#pragma unroll
+            for (int i = 0; i < XPT; ++i) xt[xsl[i]] = xr[i];
+        }
     };
 
     acc_t acc[GM][NCI][NJI];
@@ -355,28 +416,65 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
             active = kbase <= wj0 + WJ - 1 && wj0 < L;
         }
         if (!active) return;
-        // operand fragments double-buffered: group idx+1 is read from LDS while
-        // the MFMAs of group idx run
-        constexpr int NKS = TK / 4, NGRP = GM * NKS;
-        T av[2][NCI], bv[2][NJI];
-        auto ldfrag = [&](int idx, int slot) {
-            const int g = idx / NKS, ks = idx % NKS;
-            const int kr = ks * 4 + (lane >> 4);
+        if constexpr (BF) {
+            // one 16x16x16 BF16 MFMA spans the whole slab: per order, fragments
+            // of group g+1 are read while the 3 NCI NJI MFMAs of group g run
+            s16x4 ah[2][NCI], al[2][NCI], bh[2][NJI], bl[2][NJI];
+            const int kg = lane >> 4;
+            auto ldfrag = [&](int g, int slot) {
 #pragma unroll
-            for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = Xt[buf][g][ci * 16 + (lane & 15)][kr];
+                for (int ci = 0; ci < NCI; ++ci) {
+                    const int c = ci * 16 + (lane & 15);
+                    ah[slot][ci] = *(const s16x4 *)&sm.Xh[buf][g][c][4 * kg];
+                    al[slot][ci] = *(const s16x4 *)&sm.Xl[buf][g][c][4 * kg];
+                }
 #pragma unroll
-            for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = Mt[buf][g][kr][wave * WJ + ji * 16 + (lane & 15)];
-        };
-        ldfrag(0, 0);
+                for (int ji = 0; ji < NJI; ++ji) {
+                    const int jj = wave * WJ + ji * 16 + (lane & 15);
+                    bh[slot][ji] = *(const s16x4 *)&sm.Mh[buf][g][kg][jj][0];
+                    bl[slot][ji] = *(const s16x4 *)&sm.Ml[buf][g][kg][jj][0];
+                }
+            };
+            ldfrag(0, 0);
 #pragma unroll
-        for (int idx = 0; idx < NGRP; ++idx) {
-            if (idx + 1 < NGRP) ldfrag(idx + 1, (idx + 1) & 1);
-            const int g = idx / NKS;
+            for (int g = 0; g < GM; ++g) {
+                if (g + 1 < GM) ldfrag(g + 1, (g + 1) & 1);
+                const int sl = g & 1;
 #pragma unroll
-            for (int ci = 0; ci < NCI; ++ci)
+                for (int ci = 0; ci < NCI; ++ci)
 #pragma unroll
-                for (int ji = 0; ji < NJI; ++ji)
-                    acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci], bv[idx & 1][ji], acc[g][ci][ji]);
+                    for (int ji = 0; ji < NJI; ++ji) {
+                        acc_t c = acc[g][ci][ji];
+                        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[sl][ci], bh[sl][ji], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[sl][ci], bl[sl][ji], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[sl][ci], bh[sl][ji], c, 0, 0, 0);
+                        acc[g][ci][ji] = c;
+                    }
+            }
+        } else {
+            // operand fragments double-buffered: group idx+1 is read from LDS
+            // while the MFMAs of group idx run
+            constexpr int NKS = TK / 4, NGRP = GM * NKS;
+            T av[2][NCI], bv[2][NJI];
+            auto ldfrag = [&](int idx, int slot) {
+                const int g = idx / NKS, ks = idx % NKS;
+                const int kr = ks * 4 + (lane >> 4);
+#pragma unroll
+                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = sm.X[buf][g][ci * 16 + (lane & 15)][kr];
+#pragma unroll
+                for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = sm.M[buf][g][kr][wave * WJ + ji * 16 + (lane & 15)];
+            };
+            ldfrag(0, 0);
+#pragma unroll
+            for (int idx = 0; idx < NGRP; ++idx) {
+                if (idx + 1 < NGRP) ldfrag(idx + 1, (idx + 1) & 1);
+                const int g = idx / NKS;
+#pragma unroll
+                for (int ci = 0; ci < NCI; ++ci)
+#pragma unroll
+                    for (int ji = 0; ji < NJI; ++ji)
+                        acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci], bv[idx & 1][ji], acc[g][ci][ji]);
+            }
         }
     };
 
@@ -411,12 +509,38 @@ __global__ __launch_bounds__(NT) void k_contract(Args<T> a) {
     }
 }
 
-template <typename T, int MODE, int CTILE>
-hipError_t launch_one(Args<T> a, hipStream_t st) {
+template <int P, int MODE, int CTILE>
+hipError_t launch_one(Args<typename Prec<P>::T> a, hipStream_t st) {
     const int nmg = (a.L + GM - 1) / GM;
     const dim3 grid(8 * ((nmg + 7) / 8) * a.njt * a.ncb);  // 8 XCDs x groups per XCD x tiles
-    hipLaunchKernelGGL((k_contract<T, MODE, CTILE>), grid, dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((k_contract<P, MODE, CTILE>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_prec(int mode, int L, int s, int B, const typename Prec<P>::T *X, typename Prec<P>::T *Y,
+                       const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
+    using T = typename Prec<P>::T;
+    Args<T> a;
+    a.L = L;
+    a.s = s;
+    a.B = B;
+    a.C = 4 * B;
+    a.njt = (L + Prec<P>::TJ - 1) / Prec<P>::TJ;
+    a.X = X;
+    a.Y = Y;
+    a.E = E;
+    a.rtab = mode == kInverse ? rt.ri : rt.rf;
+    if constexpr (P == kP64) a.wtab = mode == kInverse ? sp.wi : sp.wf;
+    else a.wtab = mode == kInverse ? sp.wi32 : sp.wf32;
+    a.fab = rt.fab;
+    a.cl = rt.cl;
+    if (a.C <= 16) {
+        a.ncb = 1;
+        return mode == kInverse ? launch_one<P, kInverse, 16>(a, st) : launch_one<P, kForward, 16>(a, st);
+    }
+    a.ncb = (a.C + 63) / 64;
+    return mode == kInverse ? launch_one<P, kInverse, 64>(a, st) : launch_one<P, kForward, 64>(a, st);
 }
 
 }  // namespace
@@ -424,26 +548,8 @@ hipError_t launch_one(Args<T> a, hipStream_t st) {
 template <typename T>
 hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
                            const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
-    Args<T> a;
-    a.L = L;
-    a.s = s;
-    a.B = B;
-    a.C = 4 * B;
-    a.njt = (L + Tile<T>::TJ - 1) / Tile<T>::TJ;
-    a.X = X;
-    a.Y = Y;
-    a.E = E;
-    a.rtab = mode == kInverse ? rt.ri : rt.rf;
-    if constexpr (sizeof(T) == 8) a.wtab = (const T *)(mode == kInverse ? sp.wi : sp.wf);
-    else a.wtab = (const T *)(mode == kInverse ? sp.wi32 : sp.wf32);
-    a.fab = rt.fab;
-    a.cl = rt.cl;
-    if (a.C <= 16) {
-        a.ncb = 1;
-        return mode == kInverse ? launch_one<T, kInverse, 16>(a, st) : launch_one<T, kForward, 16>(a, st);
-    }
-    a.ncb = (a.C + 63) / 64;
-    return mode == kInverse ? launch_one<T, kInverse, 64>(a, st) : launch_one<T, kForward, 64>(a, st);
+    constexpr int P = sizeof(T) == 8 ? kP64 : kP32;
+    return launch_prec<P>(mode, L, s, B, X, Y, E, sp, rt, st);
 }
 
 template hipError_t launch_contract<double>(int, int, int, int, const double *, double *, const EdgeTable &,
@@ -451,9 +557,9 @@ template hipError_t launch_contract<double>(int, int, int, int, const double *, 
 template hipError_t launch_contract<float>(int, int, int, int, const float *, float *, const EdgeTable &,
                                            const SpinPlan &, const RecTables &, hipStream_t);
 
-hipError_t launch_contract_bf16x3(int, int, int, int, const float *, float *, const EdgeTable &,
-                                  const SpinPlan &, const RecTables &, hipStream_t) {
-    return hipErrorNotSupported;
+hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y, const EdgeTable &E,
+                                  const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
+    return launch_prec<kPBF>(mode, L, s, B, X, Y, E, sp, rt, st);
 }
 
 }  // namespace sht

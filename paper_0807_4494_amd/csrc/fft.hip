@@ -294,7 +294,9 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
 //   F_{mu m''} = N^-1 sum_t Q~_mu(t) e^{-i m'' theta_t},
 // then the exact sin(theta) quadrature folded over +-m' with its real
 // even-offset kernel K(p) = 2/(1-p^2) (p even), 0 (p odd):
-//   G'_{mu m'} = c_{m'} 2 pi sum_{m''} F_{mu m''} K(m'' - m'),  c_0 = 1, c_{m'>0} = 2.
+//   G'_{mu m'} = c_{m'} 2 pi sum_{m''} (F_{mu m''} + sigma F_{mu,-m''}) K(m'' - m'),
+// sigma = (-1)^{mu+s}, c_0 = 1/2, c_{m'>0} = 1.  The weights +-i pi/2 of the
+// integral at p = +-1 cancel in the fold.
 // Written as X[|mu|][c][m'] with c = q*B + b (q = 0,1 for mu >= 0, 2,3 for
 // mu < 0), times (-1)^{m'} for mu < 0 (the d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
 // symmetry; the (-1)^l part is applied on output).
@@ -334,16 +336,42 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
         buf[pad(k)] = z;
     };
     convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st_mid);
+    // Fold m' -> -m' (Eq. (wignerd_sym6)): the contraction runs over m' >= 0
+    // with G_{m'} + sigma G_{-m'}, sigma = (-1)^{m+s}, which is the quadrature
+    // of the symmetrised coefficients F_{m''} + sigma F_{-m''}.  (The
+    // extension makes F (anti)symmetric except for the theta = pi sample of an
+    // odd row, which is zero for band-limited maps; symmetrising here keeps
+    // the result the same linear operator for any map.)  buf[k] holds m'' = k - h.
+    // The weights +-i pi/2 at p = +-1 add i pi^2 (A_{m'+1} - A_{m'-1}) to the
+    // folded G at m' > 0, A_k = F_k - sigma F_{-k}.  A_k is zero for an even
+    // row and alternates in sign (the theta = pi sample) for an odd one, so the
+    // sum telescopes to the top order alone, where F_{h+1} does not exist:
+    // -i pi^2 A_{h-1}, kept in corr_h.
+    __shared__ C corr_h;
+    {
+        const T sg = ext_odd ? T(-1) : T(1);
+        const T pi2 = T(9.8696044010893586188344909998762);
+        for (int k = threadIdx.x; k <= h; k += blockDim.x) {
+            const C lo = buf[pad(k)], hi = buf[pad(N - 1 - k)];
+            if (k == 1) corr_h = C{pi2 * (hi.y - sg * lo.y), -pi2 * (hi.x - sg * lo.x)};
+            const C f{lo.x + sg * hi.x, lo.y + sg * hi.y};
+            buf[pad(k)] = f;
+            buf[pad(N - 1 - k)] = C{sg * f.x, sg * f.y};
+        }
+        __syncthreads();
+    }
     const int Cn = 4 * B;
     T *Xre = X + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
     T *Xim = Xre + (size_t)B * L;
     const T twopi = T(6.283185307179586476925286766559);
     auto st = [&](int k, C y) {
         if (k < L) {
-            T w = (k == 0 ? T(1) : T(2)) * twopi;
-            if (neg && (k & 1)) w = -w;
-            Xre[k] = y.x * w;
-            Xim[k] = y.y * w;
+            T w = (k == 0 ? T(0.5) : T(1)) * twopi;
+            const T sgn = (neg && (k & 1)) ? T(-1) : T(1);
+            C x{y.x * w, y.y * w};
+            if (k == h && h >= 1) x = C{x.x + corr_h.x, x.y + corr_h.y};
+            Xre[k] = x.x * sgn;
+            Xim[k] = x.y * sgn;
         }
     };
     convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, [buf](int n) { return buf[pad(n)]; }, st);

@@ -1,0 +1,108 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (one call per spin over the whole batch).
+
+* Sampled outputs against stored oracle values (tests/golden/*.npz, written by
+  tests/golden/make_golden.py, which calls only the oracle): the inverse at
+  seeded random pixels of the first and last map of the batch, and the forward
+  of unstructured random maps at every degree of a few orders.
+* A property that holds at any size: the forward of the inverse returns the
+  band-limited coefficients (the transform is exact, Section 3).
+
+Bars (relative l2 over the compared entries): FP64 <= 1e-10, FP32 <= 1e-5,
+BF16x3 <= 2e-5 (L=2048 only, where it is part of the workload's comparison).
+"""
+
+import functools
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import sht_synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 2e-5}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+NAMES = ["L1024_s0pm2_b16", "L2048_s0_b4"]
+# (workload, precision) pairs: FP32 and FP64 everywhere, BF16x3 at L = 2048
+CASES = [(n, p) for n in NAMES for p in ("fp32", "fp64")] + [("L2048_s0_b4", "bf16x3")]
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _sht():
+    import paper_0807_4494_amd as sht
+    return sht
+
+
+def _rel(ref, got):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+@functools.lru_cache(maxsize=2)
+def _golden(name):
+    with np.load(os.path.join(GOLDEN, f"{name}.npz"), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _workload(name):
+    return {w.name: w for w in sht_synth.WORKLOADS}[name]
+
+
+@functools.lru_cache(maxsize=1)
+def _random_maps(name):
+    wl, g = _workload(name), _golden(name)
+    seed = int(g["fwd_map_seed"])
+    return np.stack([sht_synth.random_complex_map(wl.L, seed + b) for b in range(wl.batch)])
+
+
+@pytest.mark.parametrize("name,prec", CASES)
+def test_inverse_full_size_sampled_pixels(name, prec):
+    sht, dev = _sht(), _dev()
+    wl, g = _workload(name), _golden(name)
+    L = wl.L
+    assert int(g["L"]) == L and int(g["batch"]) == wl.batch
+    t = torch.from_numpy(g["pix_t"]).to(dev)
+    p = torch.from_numpy(g["pix_p"]).to(dev)
+    for s in wl.spins:
+        flm = torch.from_numpy(wl.flm(s)).to(dev, sht.io_dtype(prec))
+        fmap = sht.inverse(flm, L, s, prec)
+        assert fmap.shape == (wl.batch, L, 2 * L - 1)
+        for i, b in enumerate(g["members"]):
+            got = fmap[int(b)][t, p].cpu().numpy().astype(np.complex128)
+            err = _rel(g[f"inv_s{s}"][i], got)
+            assert err <= TOL[prec], (name, s, int(b), prec, err)
+
+
+@pytest.mark.parametrize("name,prec", CASES)
+def test_forward_full_size_sampled_orders(name, prec):
+    sht, dev = _sht(), _dev()
+    wl, g = _workload(name), _golden(name)
+    L = wl.L
+    maps = torch.from_numpy(_random_maps(name)).to(dev, sht.io_dtype(prec))
+    idx = torch.from_numpy(g["fwd_index"]).to(dev)
+    for s in wl.spins:
+        flm = sht.forward(maps, L, s, prec)
+        assert flm.shape == (wl.batch, L * L)
+        for i, b in enumerate(g["members"]):
+            got = flm[int(b)][idx].cpu().numpy().astype(np.complex128)
+            err = _rel(g[f"fwd_s{s}"][i], got)
+            assert err <= TOL[prec], (name, s, int(b), prec, err)
+
+
+@pytest.mark.parametrize("name,prec", CASES)
+def test_round_trip_full_size(name, prec):
+    sht, dev = _sht(), _dev()
+    wl = _workload(name)
+    for s in wl.spins:
+        flm = torch.from_numpy(wl.flm(s)).to(dev, sht.io_dtype(prec))
+        back = sht.forward(sht.inverse(flm, wl.L, s, prec), wl.L, s, prec)
+        err = float(torch.linalg.vector_norm(back - flm) / torch.linalg.vector_norm(flm))
+        assert err <= TOL[prec], (name, s, prec, err)
