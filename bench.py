@@ -150,6 +150,32 @@ def cpu_baseline(wl, seconds_hint: float = 30.0) -> dict:
                       f"{dt:.1f} s; oracle round trip rel_l2 {err:.1e}"}
 
 
+def serving(n_requests: int, fractions, precision: str = "fp32", budget_gb: float = 16.0) -> dict:
+    """The mixed serving stream: closed-loop replay for the saturation rate X,
+    then open-loop Poisson arrivals at each fraction of X."""
+    import sht_synth
+    from paper_0807_4494_amd.serving import GpuServer
+
+    server = GpuServer(precision, streams=4, budget_bytes=int(budget_gb * (1 << 30)))
+    base = sht_synth.trace(n_requests=n_requests)
+    server.warm((r.L, r.spin) for r in base)
+    _, _, sat = server.run(base, closed_loop=True)
+    x = sat["requests_per_s"]
+    out = {"requests": n_requests, "precision": precision, "budget_GB": budget_gb, "streams": sat["streams"],
+           "mix": "L log-uniform [64, 2048] step 32, spin {0, +-1, +-2}, batch 1..32, C_l = 1/(l+1)^2",
+           "saturation": {"requests_per_s": round(x, 2), "transforms_per_s": round(sat["transforms_per_s"], 1),
+                          "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3)}}
+    for f in fractions:
+        tr = sht_synth.trace(n_requests=n_requests, rate_per_s=f * x)
+        _, _, st = server.run(tr)
+        out[f"open_loop_{f:g}X"] = {"rate_per_s": round(f * x, 2), "p50_ms": round(st["p50_ms"], 3),
+                                   "p99_ms": round(st["p99_ms"], 3),
+                                   "transforms_per_s": round(st["transforms_per_s"], 1),
+                                   "mean_group_size": round(st["mean_group_size"], 3),
+                                   "max_inflight_groups": st["max_inflight_groups"]}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +186,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="0.7", help="comma-separated fractions of the saturation rate")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -272,6 +301,12 @@ def main() -> int:
                   for s in wl.spins)
         out["bf16x3_path"] = {"value": round(per_step / (ms3 / 1e3), 2), "ms_per_step": round(ms3, 4),
                               "steps": n3, "round_trip_rel_l2": rt3}
+    rates = [float(f) for f in args.serve_rates.split(",") if f.strip()]
+    if not args.no_serve and rates:
+        out["serving"] = serving(args.serve_requests, rates)
+        head = out["serving"][f"open_loop_{rates[0]:g}X"]
+        out["latency_mixed_L"] = {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+                                  "rate": f"{rates[0]:g} x saturation"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
