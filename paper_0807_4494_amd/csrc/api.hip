@@ -130,7 +130,7 @@ template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
     ft.M = fft_size(L);
     ft.logM = ilog2(ft.M);
     const size_t nptw = (size_t)fft_pass_offset(ft.logM, fft_npass(ft.logM));
-    const size_t n = (size_t)ft.M + 2 * (size_t)ft.N + 2 * (size_t)ft.N + nptw + 4 * (size_t)ft.M;
+    const size_t n = (size_t)ft.M + 2 * (size_t)ft.N + 2 * (size_t)ft.N + nptw + 3 * (size_t)ft.M;
     C *base = nullptr;
     if (hipMalloc(&base, n * sizeof(C)) != hipSuccess) return SHT_ERR_OOM;
     ft.tw = base;
@@ -138,8 +138,7 @@ template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
     ft.cha = ft.e2n + 2 * ft.N;
     ft.chb = ft.cha + ft.N;
     ft.ptw = ft.chb + ft.N;
-    ft.h_it = ft.ptw + nptw;
-    ft.h_ip = ft.h_it + ft.M;
+    ft.h_ip = ft.ptw + nptw;
     ft.h_fd = ft.h_ip + ft.M;
     ft.h_fk = ft.h_fd + ft.M;
     return SHT_OK;

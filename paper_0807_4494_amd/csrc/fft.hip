@@ -197,13 +197,19 @@ __device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typena
 
 // ---------------------------------------------------------------- kernels --
 
-// Inverse theta stage.  Row (b, mu): the Fourier coefficients F_{mu m'},
-// m' >= 0, from the contraction output R[|mu|][c][m'] (c = q*B + b with
-// q = 0,1 the real/imag part for mu >= 0 and q = 2,3 for mu < 0), times
-// (-1)^s i^{-(mu+s)} (and (-1)^{m'} for mu < 0); m' < 0 filled with
-// F_{mu,-m'} = (-1)^{mu+s} F_{mu m'} (Eq. (Ffourier_sym)); then
-//   g_mu(theta_t) = sum_{m'} F_{mu m'} e^{i m' theta_t},  t < L.
-// Output G'[b][mu + L - 1][t] (rows; transposed for the phi stage afterwards).
+// Inverse theta stage, two rows per block.  Row (b, mu): the Fourier
+// coefficients F_{mu m'}, m' >= 0, from the contraction output R[|mu|][c][m']
+// (c = q*B + b with q = 0,1 the real/imag part for mu >= 0 and q = 2,3 for
+// mu < 0), times (-1)^s i^{-(mu+s)} (and (-1)^{m'} for mu < 0); m' < 0 filled
+// with F_{mu,-m'} = sigma F_{mu m'}, sigma = (-1)^{mu+s} (Eq. (Ffourier_sym));
+// then g_mu(theta_t) = sum_{m'} F_{mu m'} e^{i m' theta_t}, t < L.
+// That symmetry makes g_mu even (sigma = 1) or odd (sigma = -1) under
+// theta -> 2 pi - theta, i.e. t -> N-1-t.  Rows mu and mu+1 have opposite
+// sigma, so one length-N transform of their sum Z gives both:
+//   g_mu(theta_t) = (Z(theta_t) + sigma_mu Z(theta_{N-1-t})) / 2.
+// Block (b, i) takes mu = 2i - (L-1) and mu + 1 (the last block of a map
+// takes mu = L-1 alone).  Output G'[b][mu + L - 1][t] (rows; transposed for
+// the phi stage afterwards).
 template <typename T, int LOGM>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B,
                                                            const T *__restrict__ R,
@@ -212,30 +218,53 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const int row = blockIdx.x;
-    const int mu_idx = row % N, b = row / N;
-    const int mu = mu_idx - h, m = mu < 0 ? -mu : mu, neg = mu < 0;
+    const int pair = blockIdx.x % L, b = blockIdx.x / L;
     const int Cn = 4 * B;
-    const T *Rre = R + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
-    const T *Rim = Rre + (size_t)B * L;
-    const int phase = -(mu + s);                 // i^{-(mu+s)}
     const T sgn_s = (s & 1) ? T(-1) : T(1);
-    const int fill_odd = parity((long long)mu + s);
+    struct Row {
+        const T *re, *im;
+        int phase, neg, odd;
+    };
+    auto row_of = [&](int mu) {
+        const int m = mu < 0 ? -mu : mu, neg = mu < 0;
+        Row r;
+        r.re = R + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
+        r.im = r.re + (size_t)B * L;
+        r.phase = -(mu + s);  // i^{-(mu+s)}
+        r.neg = neg;
+        r.odd = parity((long long)mu + s);
+        return r;
+    };
+    const int mua = 2 * pair - h;
+    const bool two = mua < h;
+    const Row ra = row_of(mua), rb = row_of(two ? mua + 1 : mua);
+    auto coef = [&](const Row &r, int n) -> C {
+        const int mp = n - h, amp = mp < 0 ? -mp : mp;
+        C F{r.re[amp] * sgn_s, r.im[amp] * sgn_s};
+        F = rot_ipow(F, r.phase);
+        const int flip = (r.neg && (amp & 1)) ^ (mp < 0 && r.odd);
+        return flip ? C{-F.x, -F.y} : F;
+    };
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
-        const int mp = n - h, amp = mp < 0 ? -mp : mp;
-        C F{Rre[amp] * sgn_s, Rim[amp] * sgn_s};
-        F = rot_ipow(F, phase);
-        const int flip = (neg && (amp & 1)) ^ (mp < 0 && fill_odd);
-        if (flip) F = C{-F.x, -F.y};
+        C F = coef(ra, n);
+        if (two) F = cadd(F, coef(rb, n));
         return cmul(F, cha[n]);
     };
-    C *Gr = G + ((size_t)b * N + mu_idx) * L;
+    // Z(theta_t), t < N, lands in LDS
     auto st = [&](int t, C y) {
-        if (t < L) Gr[t] = cmul(y, chb[t]);
+        if (t < N) buf[pad(t)] = cmul(y, chb[t]);
     };
-    convolve<LOGM, T>(buf, ft.h_it, ft.ptw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
+    C *Ga = G + ((size_t)b * N + (mua + h)) * L;
+    C *Gb = Ga + L;
+    const T sa = ra.odd ? T(-0.5) : T(0.5);
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const C z = buf[pad(t)], zr = buf[pad(N - 1 - t)];
+        Ga[t] = C{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
+        if (two) Gb[t] = C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y};
+    }
 }
 
 // Inverse phi stage.  Row (b, t): f(theta_t, phi_p) = sum_mu g_mu(theta_t) e^{i mu phi_p}.
@@ -288,15 +317,23 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
     convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
 }
 
-// Forward theta stage.  Row (b, mu) of Q'[b][mu][t] (the phi-stage output
-// transposed): parity extension of Q_mu to the torus
-// rings t < N (Section 3.2: even for mu+s even, odd otherwise), the theta DFT
+// Forward theta stage, two rows per block.  Row (b, mu) of Q'[b][mu][t] (the
+// phi-stage output transposed): parity extension of Q_mu to the torus rings
+// t < N (Section 3.2: Q~(t) = sigma Q(2L-2-t) for t >= L, sigma = (-1)^{mu+s}),
+// the theta DFT
 //   F_{mu m''} = N^-1 sum_t Q~_mu(t) e^{-i m'' theta_t},
-// then the exact sin(theta) quadrature folded over +-m' with its real
-// even-offset kernel K(p) = 2/(1-p^2) (p even), 0 (p odd):
-//   G'_{mu m'} = c_{m'} 2 pi sum_{m''} (F_{mu m''} + sigma F_{mu,-m''}) K(m'' - m'),
-// sigma = (-1)^{mu+s}, c_0 = 1/2, c_{m'>0} = 1.  The weights +-i pi/2 of the
-// integral at p = +-1 cancel in the fold.
+// then the exact sin(theta) quadrature, folded over +-m' (Eq. (wignerd_sym6)):
+//   X_{mu m'} = c_{m'} 2 pi sum_{m''} (F_{mu m''} + sigma F_{mu,-m''}) K(m'' - m'),
+// K(p) = 2/(1-p^2) (p even), 0 (p odd), c_0 = 1/2, c_{m'>0} = 1.
+// The weights +-i pi/2 of the integral at p = +-1 cancel in the fold except
+// at the top order m' = L-1 of an odd row, where they leave
+// -i pi^2 (F_{h-1} + F_{1-h}) = -2 i pi^2 (-1)^{h-1} Q_mu(L-1) / N, the part of
+// the theta = pi sample that the odd extension cannot mirror.
+// Rows mu and mu+1 have opposite sigma.  With the theta = pi sample of the
+// odd row set aside, their extensions are exactly even and odd, so one DFT of
+// the summed extension Z gives F_mu + F_{mu+1} with F_mu even and F_{mu+1} odd
+// in m'' (or the reverse), and one correlation Y = Z * K over m' in
+// [-(L-1), L-1] gives both rows: X_{mu m'} = c_{m'} 2 pi (Y(m') + sigma Y(-m')).
 // Written as X[|mu|][c][m'] with c = q*B + b (q = 0,1 for mu >= 0, 2,3 for
 // mu < 0), times (-1)^{m'} for mu < 0 (the d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
 // symmetry; the (-1)^l part is applied on output).
@@ -308,25 +345,27 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const int row = blockIdx.x;
-    const int mu_idx = row % N, b = row / N;
-    const int mu = mu_idx - h, m = mu < 0 ? -mu : mu, neg = mu < 0;
-    const int ext_odd = parity((long long)mu + s);
-    const C *Qr = Q + ((size_t)b * N + mu_idx) * L;  // row over t < L
+    const int pair = blockIdx.x % L, b = blockIdx.x / L;
+    const int mua = 2 * pair - h;
+    const bool two = mua < h;
+    const int oddA = parity((long long)mua + s);
+    const C *Qa = Q + ((size_t)b * N + (mua + h)) * L;  // rows over t < L
+    const C *Qb = Qa + L;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
+    // extension of one row; the theta = pi sample (t = L-1) of an odd row is left out
+    auto ext = [&](const C *Qr, int odd, int n) -> C {
+        if (n < L) return (odd && n == h) ? C{T(0), T(0)} : Qr[n];
+        const C x = Qr[2 * L - 2 - n];
+        return odd ? C{-x.x, -x.y} : x;
+    };
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
-        C x;
-        if (n < L) {
-            x = Qr[n];
-        } else {
-            x = Qr[2 * L - 2 - n];
-            if (ext_odd) x = C{-x.x, -x.y};
-        }
+        C x = ext(Qa, oddA, n);
+        if (two) x = cadd(x, ext(Qb, !oddA, n));
         return cmulc(x, chb[n]);
     };
-    // the theta DFT lands in LDS (zero beyond N) as the input of the quadrature convolution
+    // the theta DFT lands in LDS (zero beyond N) as the input of the correlation
     auto st_mid = [&](int k, C y) {
         C z{T(0), T(0)};
         if (k < N) {
@@ -336,45 +375,36 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
         buf[pad(k)] = z;
     };
     convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st_mid);
-    // Fold m' -> -m' (Eq. (wignerd_sym6)): the contraction runs over m' >= 0
-    // with G_{m'} + sigma G_{-m'}, sigma = (-1)^{m+s}, which is the quadrature
-    // of the symmetrised coefficients F_{m''} + sigma F_{-m''}.  (The
-    // extension makes F (anti)symmetric except for the theta = pi sample of an
-    // odd row, which is zero for band-limited maps; symmetrising here keeps
-    // the result the same linear operator for any map.)  buf[k] holds m'' = k - h.
-    // The weights +-i pi/2 at p = +-1 add i pi^2 (A_{m'+1} - A_{m'-1}) to the
-    // folded G at m' > 0, A_k = F_k - sigma F_{-k}.  A_k is zero for an even
-    // row and alternates in sign (the theta = pi sample) for an odd one, so the
-    // sum telescopes to the top order alone, where F_{h+1} does not exist:
-    // -i pi^2 A_{h-1}, kept in corr_h.
-    __shared__ C corr_h;
-    {
-        const T sg = ext_odd ? T(-1) : T(1);
-        const T pi2 = T(9.8696044010893586188344909998762);
-        for (int k = threadIdx.x; k <= h; k += blockDim.x) {
-            const C lo = buf[pad(k)], hi = buf[pad(N - 1 - k)];
-            if (k == 1) corr_h = C{pi2 * (hi.y - sg * lo.y), -pi2 * (hi.x - sg * lo.x)};
-            const C f{lo.x + sg * hi.x, lo.y + sg * hi.y};
-            buf[pad(k)] = f;
-            buf[pad(N - 1 - k)] = C{sg * f.x, sg * f.y};
-        }
-        __syncthreads();
-    }
+    // Y(m') at buf[m' + h], |m'| <= h
+    convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, [buf](int n) { return buf[pad(n)]; },
+                      [buf, N](int k, C y) { if (k < N) buf[pad(k)] = y; });
     const int Cn = 4 * B;
-    T *Xre = X + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
-    T *Xim = Xre + (size_t)B * L;
     const T twopi = T(6.283185307179586476925286766559);
-    auto st = [&](int k, C y) {
-        if (k < L) {
-            T w = (k == 0 ? T(0.5) : T(1)) * twopi;
+    const T pi2 = T(9.8696044010893586188344909998762);
+    auto store = [&](int mu, int odd, const C *Qr) {
+        const int m = mu < 0 ? -mu : mu, neg = mu < 0;
+        T *Xre = X + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
+        T *Xim = Xre + (size_t)B * L;
+        const T sg = odd ? T(-1) : T(1);
+        // top-order term of an odd row: -2 i pi^2 (-1)^{h-1} Q(L-1) / N
+        C top{T(0), T(0)};
+        if (odd && h >= 1) {
+            const C q = Qr[h];
+            const T f = T(2) * pi2 * invN * ((h - 1) & 1 ? T(-1) : T(1));
+            top = C{f * q.y, -f * q.x};
+        }
+        for (int k = threadIdx.x; k < L; k += blockDim.x) {
+            const C yp = buf[pad(h + k)], ym = buf[pad(h - k)];
+            const T w = (k == 0 ? T(0.5) : T(1)) * twopi;
+            C x{(yp.x + sg * ym.x) * w, (yp.y + sg * ym.y) * w};
+            if (k == h) x = cadd(x, top);
             const T sgn = (neg && (k & 1)) ? T(-1) : T(1);
-            C x{y.x * w, y.y * w};
-            if (k == h && h >= 1) x = C{x.x + corr_h.x, x.y + corr_h.y};
             Xre[k] = x.x * sgn;
             Xim[k] = x.y * sgn;
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, [buf](int n) { return buf[pad(n)]; }, st);
+    store(mua, oddA, Qa);
+    if (two) store(mua + 1, !oddA, Qb);
 }
 
 // out[b][c][r] = in[b][r][c], 32 x 32 tiles through LDS.
@@ -447,7 +477,7 @@ hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, const T *R, vo
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_theta_inv<T, LM>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_theta_inv<T, LM>), dim3(ft.N * B), dim3(row_threads(ft.M)), lds, st, ft, s, B, R,
+        hipLaunchKernelGGL((k_theta_inv<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft, s, B, R,
                            (typename CT<T>::type *)G);
         return hipGetLastError();
     });
@@ -486,7 +516,7 @@ hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q,
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_theta_fwd<T, LM>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_theta_fwd<T, LM>), dim3(ft.N * B), dim3(row_threads(ft.M)), lds, st, ft, s, B,
+        hipLaunchKernelGGL((k_theta_fwd<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft, s, B,
                            (const typename CT<T>::type *)Q, X);
         return hipGetLastError();
     });

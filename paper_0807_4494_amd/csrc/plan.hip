@@ -151,7 +151,7 @@ __global__ void k_fill_e2n(cplx64 *e, int N) {
 // Chirp-z kernel sequence c_j for j in [-(nin-1), kout-1], stored at j mod M.
 //   type 0: e^{-i pi j^2 / N}      (inverse stages)
 //   type 1: e^{+i pi j^2 / N}      (forward DFT stages)
-//   type 2: K(j + h), h = L-1      (forward sin-theta quadrature, real)
+//   type 2: K(j)                   (forward sin-theta quadrature, real)
 //           K(p) = 2/(1-p^2) for even p, 0 for odd p
 __global__ void k_fill_kernel_seq(cplx64 *c, int M, int N, int L, int nin, int kout, int type) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,7 +162,7 @@ __global__ void k_fill_kernel_seq(cplx64 *c, int M, int N, int L, int nin, int k
     else if (i >= M - (nin - 1)) j = (long long)i - M;
     else { c[i] = cplx64{0.0, 0.0}; return; }
     if (type == 2) {
-        const long long p = j + (L - 1);
+        const long long p = j;
         const double v = (p & 1) ? 0.0 : 2.0 / (1.0 - (double)p * (double)p);
         c[i] = cplx64{v, 0.0};
         return;
@@ -221,15 +221,13 @@ hipError_t launch_fft_tables<double>(FftTables<double> &ft, FftTables<double> *,
         hipLaunchKernelGGL(k_fill_pass_tw, dim3((n + th - 1) / th), dim3(th), 0, st, ft.ptw,
                            fft_pass_offset(ft.logM, p), lns, lr);
     }
-    hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_it, M, N, L, N, L, 0);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_ip, M, N, L, N, N, 0);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fd, M, N, L, N, N, 1);
-    hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fk, M, N, L, N, L, 2);
+    hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fk, M, N, L, N, N, 2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // spectra: forward FFT in place (natural order), scaled by 1/M (the inverse transform's normalisation)
     const double inv = 1.0 / (double)M;
-    if ((e = launch_fft_inplace<double>(ft, ft.h_it, 1, inv, st)) != hipSuccess) return e;
     if ((e = launch_fft_inplace<double>(ft, ft.h_ip, 1, inv, st)) != hipSuccess) return e;
     if ((e = launch_fft_inplace<double>(ft, ft.h_fd, 1, inv, st)) != hipSuccess) return e;
     if ((e = launch_fft_inplace<double>(ft, ft.h_fk, 1, inv, st)) != hipSuccess) return e;
@@ -247,7 +245,6 @@ hipError_t launch_fft_tables<float>(FftTables<float> &ft, FftTables<double> *src
     conv(ft.cha, src->cha, ft.N);
     conv(ft.chb, src->chb, ft.N);
     conv(ft.ptw, src->ptw, fft_pass_offset(ft.logM, fft_npass(ft.logM)));
-    conv(ft.h_it, src->h_it, ft.M);
     conv(ft.h_ip, src->h_ip, ft.M);
     conv(ft.h_fd, src->h_fd, ft.M);
     conv(ft.h_fk, src->h_fk, ft.M);

@@ -52,10 +52,9 @@ template <typename T> struct FftTables {
     C *cha = nullptr;     // e^{i pi (n^2 + n) / N}, n < N          (chirps of the stages)
     C *chb = nullptr;     // e^{i pi (n^2 - 2 h n - h) / N}, n < N, h = L - 1
     C *ptw = nullptr;     // per-pass Stockham twiddles (fft_pass_offset)
-    C *h_it = nullptr;    // spectra (natural order, 1/M folded in) of the chirp-z kernels
-    C *h_ip = nullptr;
-    C *h_fd = nullptr;
-    C *h_fk = nullptr;
+    C *h_ip = nullptr;    // spectra (natural order, 1/M folded in) of the chirp-z kernels:
+    C *h_fd = nullptr;    //   inverse DFT, forward DFT,
+    C *h_fk = nullptr;    //   and the forward quadrature's real kernel K
 };
 
 // Per-L reciprocal square roots of the two Wigner recursions (FP64):
