@@ -266,6 +266,21 @@ def main() -> int:
             stage_roof[k] = {"ms": round(avg_s * 1e3, 4), "GB/s": round(b / avg_s / 1e9, 1),
                              "frac": round(b / avg_s / 1e9 / PEAK["hbm_GBs"], 4)}
 
+    # end to end: the stages run one after another, so the roofline time of a
+    # step is the sum of every launch's own bound (flops / MFMA peak for the
+    # contraction, algorithmic bytes / HBM peak for the other stages)
+    t_roof = 0.0
+    for k, tot in stages.items():
+        per_launch = tot[1] / args.steps
+        if k.startswith("contract"):
+            mult, pkey = MFMA_COST[prec]
+            t_roof += sum(mult * contraction_flops(L, s, B) for s in wl.spins) / (PEAK[pkey] * 1e12) \
+                * per_launch / len(wl.spins)
+        else:
+            t_roof += stage_bytes(k, L, B, cbytes) / (PEAK["hbm_GBs"] * 1e9) * per_launch
+    end_to_end = {"roofline_ms_per_step": round(t_roof * 1e3, 4), "measured_ms_per_step": round(ms, 4),
+                  "frac": round(t_roof * 1e3 / ms, 4)}
+
     out = {
         "metric": "spin SHT fwd+inv transforms/sec at L=1024 batch 16",
         "value": round(value, 2),
@@ -285,6 +300,7 @@ def main() -> int:
         "roofline": roof,
         "round_trip_rel_l2": rt,
         "stages": stage_roof,
+        "end_to_end_roofline": end_to_end,
     }
     if not args.no_fp64 and prec != "fp64":
         flm64 = {s: torch.from_numpy(host_flm[s]).to(dev, torch.complex128) for s in wl.spins}

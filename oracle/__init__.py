@@ -15,6 +15,9 @@ transforms", arXiv:0807.4494):
   Eq. (sht_inv_fast); the forward transform as the exact quadrature of
   Eq. (ssht_fwd) on the periodically extended torus (Sections 3.2, 3.4.1).
 * :mod:`oracle.metrics` -- the five error metrics of Section 4.2.
+* :mod:`oracle.triangular` -- the paper's own forward transform (per-order
+  triangular systems, Section 3.4.2), its least-squares variant and the
+  stability experiment of Section 4.2.
 
 Everything is float64 / complex128.  Pins (tests that tie each function to
 something other than itself) live in ``tests/test_oracle_*.py``.
@@ -25,6 +28,7 @@ from .transform import (inverse, forward, fourier_coefficients, torus_synthesis,
                         theta_nodes, phi_nodes, quadrature_weight, inverse_batch,
                         forward_batch, forward_rows)
 from .metrics import error_metrics, rel_l2
+from . import triangular
 
 __all__ = ["delta_planes", "delta_plane", "DeltaRisbo", "inverse", "forward",
            "fourier_coefficients", "torus_synthesis", "theta_nodes", "phi_nodes",

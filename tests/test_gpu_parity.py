@@ -92,6 +92,27 @@ def test_forward_of_unstructured_maps_matches_oracle(L, s, B, prec):
     assert rel(ref, got) < TOL[prec], rel(ref, got)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["L32_s0_b1", "L256_s2_b1"])
+def test_small_workloads_exactly_as_configured(name, prec):
+    """The single-map FP64 workloads (L=32 spin 0 flat spectrum; L=256 spin 2
+    with C_l = 1/(l(l+1)), l >= 2): inverse and forward against the oracle,
+    and the GPU round trip."""
+    sht = _sht()
+    wl = {w.name: w for w in sht_synth.WORKLOADS}[name]
+    L, s = wl.L, wl.spins[0]
+    print(f"[workload] {name} {prec}", flush=True)
+    flm = wl.flm(s)
+    ref_map = oracle.inverse_batch(flm, L, s)
+    got_map = sht.inverse(to_dev(flm, prec), L, s, prec)
+    assert rel(ref_map, got_map.cpu().numpy()) < TOL[prec]
+    ref_f = oracle.forward_batch(ref_map, L, s)
+    got_f = sht.forward(to_dev(ref_map, prec), L, s, prec).cpu().numpy()
+    assert rel(ref_f, got_f) < TOL[prec]
+    back = sht.forward(got_map, L, s, prec).cpu().numpy()
+    assert rel(flm, back) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_round_trip_L512(prec):
     sht = _sht()
