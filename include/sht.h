@@ -62,6 +62,7 @@ extern "C" {
 #define SHT_VERSION 10000          /* 1.0.0 */
 #define SHT_L_MAX 2048
 #define SHT_BATCH_MAX 64
+#define SHT_TRI_L_MAX 128          /* largest L of sht_forward_triangular */
 
 enum sht_status {
     SHT_OK = 0,
@@ -103,6 +104,25 @@ int sht_inverse(int L, int spin, int batch, int sampling, int precision,
 int sht_forward(int L, int spin, int batch, int sampling, int precision,
                 const void *map, void *flm, void *workspace, size_t ws_bytes,
                 void *stream);
+
+/*
+ * The paper's own forward transform (Section 3.4.2): phi DFT, the per-order
+ * extension and theta DFT of Section 3.2 (Eq. (fourier_series)), then for
+ * each order m0 the triangular system of Eq. (matrix_fwd),
+ *   F_{m0 m'} = sum_{l >= m'} (-1)^s i^{-(m0+s)} sqrt((2l+1)/4pi)
+ *               d^l_{m' m0}(pi/2) d^l_{m',-s}(pi/2) f_{l m0},
+ * solved on its square block of rows and columns max(|m0|, |s|) .. L-1 by
+ * back substitution.  Exact for band-limited maps in exact arithmetic, but
+ * the systems are ill conditioned (Section 4.2: condition number ~6e14 at
+ * band-limit 50); use sht_forward for accurate results.  Provided as the
+ * paper's method for comparison.
+ *   precision  SHT_FP64 only (SHT_ERR_UNSUPPORTED otherwise)
+ *   L          1 <= L <= SHT_TRI_L_MAX (SHT_ERR_UNSUPPORTED above)
+ *   map, flm, workspace, stream: as for sht_forward (same workspace size).
+ */
+int sht_forward_triangular(int L, int spin, int batch, int sampling, int precision,
+                           const void *map, void *flm, void *workspace, size_t ws_bytes,
+                           void *stream);
 
 /* Workspace bytes needed by sht_inverse / sht_forward with these arguments
  * (the same size serves both directions).  0 if the arguments are invalid. */

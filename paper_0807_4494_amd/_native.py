@@ -22,9 +22,10 @@ SHT_ERR_HIP = -6
 
 SHT_SAMPLING_MW = 0
 SHT_FP64, SHT_FP32, SHT_BF16X3 = 0, 1, 2
+SHT_TRI_L_MAX = 128
 
 #: every symbol include/sht.h declares
-EXPORTS = ("sht_inverse", "sht_forward", "sht_workspace_bytes", "sht_plan_warmup",
+EXPORTS = ("sht_inverse", "sht_forward", "sht_forward_triangular", "sht_workspace_bytes", "sht_plan_warmup",
            "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error",
            "sht_trace_enable", "sht_trace_read")
 
@@ -55,7 +56,7 @@ def load() -> ctypes.CDLL:
                           "(or __graft_entry__.build()) first")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
-    for name in ("sht_inverse", "sht_forward"):
+    for name in ("sht_inverse", "sht_forward", "sht_forward_triangular"):
         f = getattr(lib, name)
         f.argtypes = [i, i, i, i, i, vp, vp, vp, sz, vp]
         f.restype = i

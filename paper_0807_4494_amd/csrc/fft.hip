@@ -407,6 +407,46 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     if (two) store(mua + 1, !oddA, Qb);
 }
 
+// Theta DFT alone, for the paper's own forward transform (per-order
+// triangular systems).  Row (b, mu) of Q'[b][mu][t]: the extension of
+// Section 3.2 chosen by the parity of mu+s (the theta = pi sample kept as it
+// is) and F_{mu m'} = N^-1 sum_t Q~_mu(t) e^{-i m' theta_t} for m' in [0, L),
+// written to F[b][mu + L - 1][m'].
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_theta_dft(FftTables<T> ft, int s,
+                                                           const typename CT<T>::type *__restrict__ Q,
+                                                           typename CT<T>::type *__restrict__ F) {
+    using C = typename CT<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int L = ft.L, N = ft.N, h = L - 1;
+    const size_t row = blockIdx.x;                  // b * N + mu_idx
+    const int mu = (int)(row % N) - h;
+    const int odd = parity((long long)mu + s);
+    const C *Qr = Q + row * L;
+    C *Fr = F + row * L;
+    const C *cha = ft.cha, *chb = ft.chb;
+    const T invN = T(1) / T(N);
+    auto ld = [&](int n) -> C {
+        if (n >= N) return C{T(0), T(0)};
+        C x;
+        if (n < L) {
+            x = Qr[n];
+        } else {
+            x = Qr[2 * L - 2 - n];
+            if (odd) x = C{-x.x, -x.y};
+        }
+        return cmulc(x, chb[n]);
+    };
+    auto st = [&](int k, C y) {
+        if (k >= h && k < N) {
+            const C z = cmulc(y, cha[k]);
+            Fr[k - h] = C{z.x * invN, z.y * invN};
+        }
+    };
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
+}
+
 // out[b][c][r] = in[b][r][c], 32 x 32 tiles through LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const typename CT<T>::type *__restrict__ in,
@@ -523,6 +563,19 @@ hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q,
 }
 
 template <typename T>
+hipError_t launch_theta_dft(const FftTables<T> &ft, int s, int B, const void *Q, void *F, hipStream_t st) {
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_theta_dft<T, LM>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_theta_dft<T, LM>), dim3(ft.N * B), dim3(row_threads(ft.M)), lds, st, ft, s,
+                           (const typename CT<T>::type *)Q, (typename CT<T>::type *)F);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
 hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows, double scale,
                               hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
@@ -547,6 +600,7 @@ hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out
     template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, const T *, void *, hipStream_t); \
     template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
     template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
+    template hipError_t launch_theta_dft<T>(const FftTables<T> &, int, int, const void *, void *, hipStream_t); \
     template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, const void *, T *, hipStream_t); \
     template hipError_t launch_transpose<T>(int, int, int, const void *, void *, hipStream_t);                \
     template hipError_t launch_fft_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \

@@ -110,6 +110,9 @@ template <typename T>
 hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st);
 template <typename T>
 hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q, T *X, hipStream_t st);
+// theta DFT of the extended rows alone, F[b][mu][m'] for m' in [0, L)
+template <typename T>
+hipError_t launch_theta_dft(const FftTables<T> &ft, int s, int B, const void *Q, void *F, hipStream_t st);
 // out[b][c][r] = in[b][r][c] for complex T
 template <typename T>
 hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out, hipStream_t st);
@@ -125,6 +128,10 @@ hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, cons
                            const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y,
                                   const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st);
+
+// tri.hip: the paper's per-order triangular systems (FP64, L <= SHT_TRI_L_MAX)
+hipError_t launch_tri_solve(int L, int s, int B, const void *F, void *flm, const EdgeTable &E,
+                            const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 
 // ------------------------------------------------------------- helpers -----
 inline int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }

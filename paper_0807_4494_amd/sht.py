@@ -94,6 +94,29 @@ def forward(fmap: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Op
     return out[0] if single else out
 
 
+def forward_triangular(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch.Tensor] = None,
+                       workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The paper's own forward transform (per-order triangular systems), FP64,
+    L <= 128.  Ill conditioned beyond small L; see :func:`forward`."""
+    p = N.SHT_FP64
+    single = fmap.dim() == 2
+    g = fmap.reshape(1, *fmap.shape) if single else fmap
+    if tuple(g.shape[-2:]) != (L, 2 * L - 1):
+        raise ValueError(f"map shape {tuple(g.shape[-2:])}, expected ({L}, {2 * L - 1})")
+    if not g.is_cuda:
+        raise ValueError("map must be a GPU tensor")
+    g = g.to(torch.complex128).contiguous()
+    B = g.shape[0]
+    if out is None:
+        out = torch.empty((B, L * L), dtype=torch.complex128, device=g.device)
+    ws, nbytes = _workspace(L, spin, B, p, g.device, workspace)
+    rc = N.load().sht_forward_triangular(L, spin, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
+                                         ws.data_ptr() if ws is not None else None, nbytes,
+                                         _stream_handle(g.device))
+    N.check(rc, "sht_forward_triangular")
+    return out[0] if single else out
+
+
 def plan_warmup(L: int, spin: int = 0, precision="fp64", device=None) -> None:
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     N.check(N.load().sht_plan_warmup(L, spin, N.SHT_SAMPLING_MW, _prec(precision), _stream_handle(dev)),

@@ -66,6 +66,12 @@ def test_argument_checks_run_before_any_hip_call():
     need = lib.sht_workspace_bytes(8, 0, 1, 0, 0)
     assert call(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
     assert lib.sht_forward(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
+    # the triangular forward: FP64 only, L <= SHT_TRI_L_MAX
+    tri = lib.sht_forward_triangular
+    assert tri(8, 0, 1, 0, 1, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
+    assert tri(N.SHT_TRI_L_MAX + 1, 0, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
+    assert tri(8, 8, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert tri(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
 
 
 def test_workspace_size_formula():

@@ -146,3 +146,43 @@ def test_input_rows_below_spin_are_ignored():
     a = sht.inverse(to_dev(flm, "fp64"), L, s, "fp64")
     b = sht.inverse(to_dev(noisy, "fp64"), L, s, "fp64")
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("L,s", [(1, 0), (2, 1), (5, 0), (8, -2), (12, 3), (16, 0), (16, 2)])
+def test_triangular_forward_matches_oracle(L, s):
+    """The paper's own forward (per-order triangular systems) against the
+    oracle's back substitution; both recover the band-limited coefficients at
+    these small L, where the systems are still well enough conditioned."""
+    sht = _sht()
+    print(f"[triangular] L={L} s={s}", flush=True)
+    from oracle import triangular as T
+    B = 3
+    flm = np.stack([sht_synth.gaussian_flm(L, s, 600 + 17 * L + b) for b in range(B)])
+    fmap = oracle.inverse_batch(flm, L, s)
+    ref = np.stack([T.forward_triangular(fmap[b], L, s, split_spin0=False) for b in range(B)])
+    got = sht.forward_triangular(to_dev(fmap, "fp64"), L, s).cpu().numpy()
+    assert rel(ref, got) < 1e-10, rel(ref, got)
+    assert rel(flm, got) < 1e-9
+
+
+def test_triangular_forward_instability_on_the_gpu():
+    """Section 4.2 on the GPU: real spin-0 U[-1, 1] test functions; the
+    paper's forward is exact at L = 8 and loses accuracy by L = 64, while the
+    quadrature forward stays exact."""
+    sht = _sht()
+    errs = {}
+    for L in (8, 32, 64):
+        f = sht_synth.uniform_flm(L, 0, 21 + L)
+        # real signal: f_{l,-m} = (-1)^m conj(f_lm)
+        for l in range(L):
+            for m in range(1, l + 1):
+                f[l * l + l - m] = (-1) ** m * np.conj(f[l * l + l + m])
+            f[l * l + l] = f[l * l + l].real
+        fmap = sht.inverse(to_dev(f, "fp64"), L, 0, "fp64")
+        g = sht.forward_triangular(fmap, L, 0).cpu().numpy()
+        q = sht.forward(fmap, L, 0, "fp64").cpu().numpy()
+        errs[L] = rel(f, g)
+        assert rel(f, q) < 1e-12
+    print(f"[triangular] rel rms error by L: {errs}", flush=True)
+    assert errs[8] < 1e-12
+    assert errs[64] > 1e-3
