@@ -187,6 +187,8 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--tables", action="store_true",
+                    help="also time the cached-table design (an L^3 table per spin, 4 GiB each in FP32 at L=1024)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rates", default="0.7", help="comma-separated fractions of the saturation rate")
     args = ap.parse_args()
@@ -317,6 +319,21 @@ def main() -> int:
                   for s in wl.spins)
         out["bf16x3_path"] = {"value": round(per_step / (ms3 / 1e3), 2), "ms_per_step": round(ms3, 4),
                               "steps": n3, "round_trip_rel_l2": rt3}
+    if args.tables:
+        # the precomputed-table design: M streamed from a cached L^3 table
+        for s in wl.spins:
+            sht.plan_tables(L, s, prec, True)
+        n_t = max(2, min(args.steps, 10))
+        ms_t, st_t, back_t = run_steps(sht, torch, wl, prec, flm, n_t, 1, trace=True)
+        rt_t = max(float(torch.linalg.vector_norm(back_t[s] - flm[s]) / torch.linalg.vector_norm(flm[s]))
+                   for s in wl.spins)
+        for s in wl.spins:
+            sht.plan_tables(L, s, prec, False)
+        out["table_mode_path"] = {
+            "value": round(per_step / (ms_t / 1e3), 2), "ms_per_step": round(ms_t, 4), "steps": n_t,
+            "round_trip_rel_l2": rt_t, "table_GiB_per_spin": round(L ** 3 * cbytes / 2 / 2 ** 30, 2),
+            "contract_inv_ms": round(st_t["contract_inv"][0] / st_t["contract_inv"][1], 4),
+            "contract_fwd_ms": round(st_t["contract_fwd"][0] / st_t["contract_fwd"][1], 4)}
     rates = [float(f) for f in args.serve_rates.split(",") if f.strip()]
     if not args.no_serve and rates:
         out["serving"] = serving(args.serve_requests, rates)

@@ -133,6 +133,19 @@ size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precisi
  * first use.  Returns SHT_OK or an error code. */
 int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream);
 
+/*
+ * Cached contraction tables (a measured alternative to generating the Wigner
+ * factors on the fly).  enable = 1 builds, for (L, spin) on the current
+ * device, the table of M_m(m', l) = sqrt((2l+1)/4pi) d^l_{m'm}(pi/2)
+ * d^l_{m',-s}(pi/2) for all 0 <= m, m', l < L -- L^3 entries in FP64 for
+ * SHT_FP64, in FP32 for SHT_FP32 and SHT_BF16X3 (4 GiB at L = 1024 in FP32)
+ * -- the precomputation Section 4.1 describes; from then on the transforms at
+ * that (L, spin) and precision class stream M from the table instead of
+ * running the recursions.  enable = 0 frees the table.  Synchronises the
+ * stream.  SHT_ERR_OOM if the table does not fit.
+ */
+int sht_plan_tables(int L, int spin, int precision, int enable, void *stream);
+
 /* Free every cached plan on every device.  The caller must make sure no
  * enqueued transform still uses them (e.g. synchronise first). */
 int sht_release_all(void);

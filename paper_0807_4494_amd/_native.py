@@ -26,6 +26,7 @@ SHT_TRI_L_MAX = 128
 
 #: every symbol include/sht.h declares
 EXPORTS = ("sht_inverse", "sht_forward", "sht_forward_triangular", "sht_workspace_bytes", "sht_plan_warmup",
+           "sht_plan_tables",
            "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error",
            "sht_trace_enable", "sht_trace_read")
 
@@ -64,6 +65,8 @@ def load() -> ctypes.CDLL:
     lib.sht_workspace_bytes.restype = sz
     lib.sht_plan_warmup.argtypes = [i, i, i, i, vp]
     lib.sht_plan_warmup.restype = i
+    lib.sht_plan_tables.argtypes = [i, i, i, i, vp]
+    lib.sht_plan_tables.restype = i
     lib.sht_release_all.argtypes = []
     lib.sht_release_all.restype = i
     lib.sht_status_string.argtypes = [i]

@@ -355,6 +355,37 @@ int sht_forward_triangular(int L, int spin, int batch, int sampling, int precisi
     return SHT_OK;
 }
 
+int sht_plan_tables(int L, int spin, int precision, int enable, void *stream) {
+    int rc = check_args(L, spin, 1, SHT_SAMPLING_MW, precision);
+    if (rc != SHT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    if (rc != SHT_OK) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    const bool f64 = precision == SHT_FP64;
+    void **slot = f64 ? (void **)&sp->mtab64 : (void **)&sp->mtab32;
+    if (!enable) {
+        if (*slot) {
+            SHT_HIP(hipStreamSynchronize(st), "table release sync");
+            SHT_HIP(hipFree(*slot), "table free");
+            *slot = nullptr;
+        }
+        return SHT_OK;
+    }
+    if (*slot) return SHT_OK;
+    const size_t bytes = (size_t)L * L * L * (f64 ? sizeof(double) : sizeof(float));
+    if (hipMalloc(slot, bytes) != hipSuccess) {
+        *slot = nullptr;
+        return SHT_ERR_OOM;
+    }
+    SHT_HIP(launch_mtable(L, f64 ? 1 : 0, ds->E, plan->rec, *sp, st), "contraction table");
+    SHT_HIP(hipStreamSynchronize(st), "contraction table sync");
+    return SHT_OK;
+}
+
 int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) {
     int rc = check_args(L, spin, 1, sampling, precision);
     if (rc != SHT_OK) return rc;
@@ -372,6 +403,8 @@ int sht_release_all(void) {
     for (auto &kv : g_spin) {
         (void)hipSetDevice(kv.second->device);
         if (hipFree(kv.second->wi) != hipSuccess) rc = SHT_ERR_HIP;
+        if (kv.second->mtab64 && hipFree(kv.second->mtab64) != hipSuccess) rc = SHT_ERR_HIP;
+        if (kv.second->mtab32 && hipFree(kv.second->mtab32) != hipSuccess) rc = SHT_ERR_HIP;
         delete kv.second;
     }
     g_spin.clear();

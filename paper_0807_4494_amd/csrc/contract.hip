@@ -111,9 +111,13 @@ template <typename T> struct Args {
     const T *wtab;        // [L][L] spin factor at [k][j] (wi or wf)
     const double2 *fab;   // [L][L] order-side l-recursion factors
     const double *cl;     // [L] sqrt((2l+1)/4pi)
+    const T *mtab;        // table mode: M_m(m', l) at [m][l][m'] (plan's cached table)
 };
 
-template <int P, int MODE, int CTILE>
+// TAB: the producers copy the slab of M from the plan's cached table instead
+// of running the Wigner chains (the measured comparison of a precomputed-Delta
+// design with on-the-fly generation).
+template <int P, int MODE, int CTILE, bool TAB>
 __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
     using T = typename Prec<P>::T;
     constexpr bool BF = P == kPBF;
@@ -164,6 +168,66 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
     auto kbase_of = [&](int chunk) {
         return MODE == kInverse ? kfirst + chunk * TK : kfirst - (chunk + 1) * TK + 1;
     };
+
+    if (TAB && producer) {
+        // ================= producers, table mode: copy M slabs =================
+        const int ptid = tid - NC;
+        const int jl = ptid % TJ, sub = ptid / TJ;
+        const int j = j0 + jl;
+        T vc[NCH][TK], vn[NCH][TK];
+        auto load_slab = [&](int chunk, T (&dst)[NCH][TK]) {
+            const int kbase = kbase_of(chunk);
+#pragma unroll
+            for (int g = 0; g < NCH; ++g) {
+                const int m = m0 + sub * NCH + g;
+#pragma unroll
+                for (int kk = 0; kk < TK; ++kk) {
+                    const int k = kbase + kk;
+                    const bool ok = chunk < nchunks && j < L && m < L && k >= 0 && k < L;
+                    size_t idx = 0;
+                    if (ok) idx = MODE == kInverse ? ((size_t)m * L + k) * L + j : ((size_t)m * L + j) * L + k;
+                    dst[g][kk] = ok ? a.mtab[idx] : T(0);
+                }
+            }
+        };
+        auto emit_t = [&](int buf, int gi, int kk, T v) {
+            if constexpr (BF) {
+                unsigned short hi, lo;
+                bf16_split(v, hi, lo);
+                sm.Mh[buf][gi][kk >> 2][jl][kk & 3] = hi;
+                sm.Ml[buf][gi][kk >> 2][jl][kk & 3] = lo;
+            } else {
+                sm.M[buf][gi][kk][jl] = v;
+            }
+        };
+        auto store_slab = [&](int buf) {
+#pragma unroll
+            for (int g = 0; g < NCH; ++g)
+#pragma unroll
+                for (int kk = 0; kk < TK; ++kk) emit_t(buf, sub * NCH + g, kk, vc[g][kk]);
+        };
+        auto advance = [&]() {
+#pragma unroll
+            for (int g = 0; g < NCH; ++g)
+#pragma unroll
+                for (int kk = 0; kk < TK; ++kk) vc[g][kk] = vn[g][kk];
+        };
+        // same barrier sequence as the chain producers below
+        load_slab(0, vc);
+        __syncthreads();
+        load_slab(1, vn);
+        store_slab(0);
+        __syncthreads();
+        for (int chunk = 1; chunk <= nchunks; ++chunk) {
+            if (chunk < nchunks) {
+                advance();
+                load_slab(chunk + 1, vn);
+                store_slab(chunk & 1);
+            }
+            __syncthreads();
+        }
+        return;
+    }
 
     if (producer) {
         // ================= producers: FP64 Wigner chains =================
@@ -513,8 +577,49 @@ template <int P, int MODE, int CTILE>
 hipError_t launch_one(Args<typename Prec<P>::T> a, hipStream_t st) {
     const int nmg = (a.L + GM - 1) / GM;
     const dim3 grid(8 * ((nmg + 7) / 8) * a.njt * a.ncb);  // 8 XCDs x groups per XCD x tiles
-    hipLaunchKernelGGL((k_contract<P, MODE, CTILE>), grid, dim3(NT), 0, st, a);
+    if (a.mtab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true>), grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
+}
+
+// Table of M_m(m', l) = sqrt((2l+1)/4pi) d^l_{m'm}(pi/2) d^l_{m',-s}(pi/2),
+// rounded to T as the chain producers round it, at [m][l][m'] (zero for
+// l < max(m, m')).  One thread per (m, m'): the l-chain of the inverse
+// producers run over the whole degree range.
+template <typename T>
+__global__ void k_mtable(int L, EdgeTable E, const double *ri, const double2 *fab, const T *w, T *tab) {
+    const int mp = blockIdx.x * blockDim.x + threadIdx.x, m = blockIdx.y;
+    if (mp >= L) return;
+    const int l0 = mp > m ? mp : m;
+    const Seed sd = edge_seed(E, mp, m);
+    Chain c;
+    c.d = 0.0;
+    c.dp = 0.0;
+    c.k = sd.k;
+    c.es = emit_scale(sd.k);
+    double q = 0.0;
+    for (int l = 0; l < L; ++l) {
+        const size_t o = ((size_t)m * L + l) * L + mp;
+        if (l < l0) {
+            tab[o] = T(0);
+            continue;
+        }
+        if (l == l0) c.d = sd.v;
+        tab[o] = (T)(c.d * c.es) * w[(size_t)l * L + mp];
+        const double r = ri[(size_t)l * L + mp];
+        const double ap = (double)mp * r, bp = q * r;
+        q = ((double)(l + 1) * (l + 1) - (double)mp * mp) * r;
+        const double2 f = fab[(size_t)m * L + l];
+        const double dn = -(ap * f.x * c.d + bp * f.y * c.dp);
+        c.dp = c.d;
+        c.d = dn;
+        if (((l - l0) & 15) == 15 && c.k > 1 && fabs(c.d) > kBig) {
+            c.d *= kSmall;
+            c.dp *= kSmall;
+            --c.k;
+            c.es = emit_scale(c.k);
+        }
+    }
 }
 
 template <int P>
@@ -535,6 +640,8 @@ hipError_t launch_prec(int mode, int L, int s, int B, const typename Prec<P>::T 
     else a.wtab = mode == kInverse ? sp.wi32 : sp.wf32;
     a.fab = rt.fab;
     a.cl = rt.cl;
+    if constexpr (P == kP64) a.mtab = sp.mtab64;
+    else a.mtab = sp.mtab32;
     if (a.C <= 16) {
         a.ncb = 1;
         return mode == kInverse ? launch_one<P, kInverse, 16>(a, st) : launch_one<P, kForward, 16>(a, st);
@@ -556,6 +663,16 @@ template hipError_t launch_contract<double>(int, int, int, int, const double *, 
                                             const SpinPlan &, const RecTables &, hipStream_t);
 template hipError_t launch_contract<float>(int, int, int, int, const float *, float *, const EdgeTable &,
                                            const SpinPlan &, const RecTables &, hipStream_t);
+
+hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const RecTables &rt, SpinPlan &sp,
+                         hipStream_t st) {
+    const dim3 grid((L + 63) / 64, L);
+    if (precision_fp64)
+        hipLaunchKernelGGL(k_mtable<double>, grid, dim3(64), 0, st, L, E, rt.ri, rt.fab, sp.wi, sp.mtab64);
+    else
+        hipLaunchKernelGGL(k_mtable<float>, grid, dim3(64), 0, st, L, E, rt.ri, rt.fab, sp.wi32, sp.mtab32);
+    return hipGetLastError();
+}
 
 hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y, const EdgeTable &E,
                                   const SpinPlan &sp, const RecTables &rt, hipStream_t st) {

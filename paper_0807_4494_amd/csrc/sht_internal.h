@@ -86,6 +86,10 @@ struct SpinPlan {
     int device = 0, L = 0, spin = 0;
     double *wi = nullptr, *wf = nullptr;
     float *wi32 = nullptr, *wf32 = nullptr;
+    // optional cached tables of the full contraction factor M_m(m', l) at
+    // [m][l][m'] (L^3 entries), FP64 and FP32 (the latter also feeds BF16x3)
+    double *mtab64 = nullptr;
+    float *mtab32 = nullptr;
 };
 
 // -------------------------------------------------------- kernel launches ---
@@ -126,6 +130,8 @@ enum ContractMode { kInverse = 0, kForward = 1 };
 template <typename T>
 hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
                            const SpinPlan &sp, const RecTables &rt, hipStream_t st);
+hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const RecTables &rt, SpinPlan &sp,
+                         hipStream_t st);
 hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y,
                                   const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 

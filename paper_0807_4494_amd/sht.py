@@ -123,6 +123,14 @@ def plan_warmup(L: int, spin: int = 0, precision="fp64", device=None) -> None:
             "sht_plan_warmup")
 
 
+def plan_tables(L: int, spin: int = 0, precision="fp32", enable: bool = True, device=None) -> None:
+    """Build (or, with enable=False, free) the cached L^3 contraction table of
+    (L, spin) for this precision class; transforms then stream it."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    N.check(N.load().sht_plan_tables(L, spin, _prec(precision), 1 if enable else 0, _stream_handle(dev)),
+            "sht_plan_tables")
+
+
 def release_all() -> None:
     N.check(N.load().sht_release_all(), "sht_release_all")
 

@@ -186,3 +186,22 @@ def test_triangular_forward_instability_on_the_gpu():
     print(f"[triangular] rel rms error by L: {errs}", flush=True)
     assert errs[8] < 1e-12
     assert errs[64] > 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("L,s,B", [(33, -1, 2), (100, 2, 3), (257, 0, 1)])
+def test_cached_table_mode_matches_oracle(L, s, B, prec):
+    """With the plan's cached L^3 contraction table the transforms stream M
+    instead of running the recursions; the results keep the same bars."""
+    sht = _sht()
+    print(f"[table mode] L={L} s={s} B={B} {prec}", flush=True)
+    flm = np.stack([sht_synth.gaussian_flm(L, s, 800 + 31 * L + b) for b in range(B)])
+    ref_map = oracle.inverse_batch(flm, L, s)
+    sht.plan_tables(L, s, prec, True)
+    try:
+        got_map = sht.inverse(to_dev(flm, prec), L, s, prec).cpu().numpy()
+        got_f = sht.forward(to_dev(ref_map, prec), L, s, prec).cpu().numpy()
+    finally:
+        sht.plan_tables(L, s, prec, False)
+    assert rel(ref_map, got_map) < TOL[prec], rel(ref_map, got_map)
+    assert rel(flm, got_f) < TOL[prec], rel(flm, got_f)
