@@ -162,6 +162,10 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
         return SHT_ERR_OOM;
     }
     SHT_HIP(launch_rec_tables(L, p->rec, st), "recursion tables");
+    if (build_contract_schedules(L, p->rec) != 0) {
+        delete p;
+        return SHT_ERR_OOM;
+    }
     SHT_HIP(launch_fft_tables<double>(p->f64, nullptr, st), "fft tables f64");
     SHT_HIP(launch_fft_tables<float>(p->f32, &p->f64, st), "fft tables f32");
     SHT_HIP(hipStreamSynchronize(st), "plan sync");
@@ -416,6 +420,9 @@ int sht_release_all(void) {
         if (hipFree(kv.second->rec.rf) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.fab) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.cl) != hipSuccess) rc = SHT_ERR_HIP;
+        for (int md = 0; md < 2; ++md)
+            for (int c = 0; c < 2; ++c)
+                if (kv.second->rec.sched[md][c] && hipFree(kv.second->rec.sched[md][c]) != hipSuccess) rc = SHT_ERR_HIP;
         delete kv.second;
     }
     g_plans.clear();

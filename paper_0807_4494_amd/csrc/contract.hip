@@ -25,7 +25,10 @@
 //   BF16x3  M and X split into BF16 pairs hi + lo, three v_mfma_f32_16x16x16
 //           BF16 products hi*hi + hi*lo + lo*hi accumulated in FP32 (the
 //           lo*lo term, ~2^-16 relative, is dropped).
+#include <algorithm>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "chain.h"
 
@@ -112,6 +115,7 @@ template <typename T> struct Args {
     const double2 *fab;   // [L][L] order-side l-recursion factors
     const double *cl;     // [L] sqrt((2l+1)/4pi)
     const T *mtab;        // table mode: M_m(m', l) at [m][l][m'] (plan's cached table)
+    const int *sched;     // workgroup order: (group << 8) | j tile, longest K loop first
 };
 
 // TAB: the producers copy the slab of M from the plan's cached table instead
@@ -133,16 +137,11 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 
     const int L = a.L, s = a.s, Cn = a.C;
     const int asg = s < 0 ? -s : s;
-    // Hardware workgroup b runs on XCD b mod 8.  Order group mg goes to XCD
-    // mg mod 8 with all its j tiles and column blocks (they stream the same X
-    // panel through that XCD's L2); each XCD takes its groups in ascending
-    // order, which for the inverse is heaviest first.
-    const int tiles = a.njt * a.ncb;
-    const int xcd = (int)(blockIdx.x % 8), slot = (int)(blockIdx.x / 8);
-    const int mg = (slot / tiles) * 8 + xcd;
-    if (mg * GM >= L) return;
-    const int cb = (slot % tiles) % a.ncb;
-    const int jt = (slot % tiles) / a.ncb;
+    // Workgroup x takes the x-th (order group, j tile) pair of the plan's
+    // schedule, longest K loop first, so the short ones fill the tail; the
+    // column block is blockIdx.y.
+    const int code = a.sched[blockIdx.x];
+    const int mg = code >> 8, jt = code & 255, cb = (int)blockIdx.y;
     const int m0 = mg * GM, j0 = jt * TJ, c0 = cb * CTILE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool producer = tid >= NC;
@@ -574,9 +573,9 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 }
 
 template <int P, int MODE, int CTILE>
-hipError_t launch_one(Args<typename Prec<P>::T> a, hipStream_t st) {
-    const int nmg = (a.L + GM - 1) / GM;
-    const dim3 grid(8 * ((nmg + 7) / 8) * a.njt * a.ncb);  // 8 XCDs x groups per XCD x tiles
+hipError_t launch_one(Args<typename Prec<P>::T> a, int nsched, hipStream_t st) {
+    if (nsched == 0) return hipSuccess;
+    const dim3 grid(nsched, a.ncb);
     if (a.mtab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true>), grid, dim3(NT), 0, st, a);
     else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
@@ -642,12 +641,15 @@ hipError_t launch_prec(int mode, int L, int s, int B, const typename Prec<P>::T 
     a.cl = rt.cl;
     if constexpr (P == kP64) a.mtab = sp.mtab64;
     else a.mtab = sp.mtab32;
+    const int cls = Prec<P>::TJ == 64 ? 0 : 1;
+    a.sched = rt.sched[mode][cls];
+    const int ns = rt.nsched[mode][cls];
     if (a.C <= 16) {
         a.ncb = 1;
-        return mode == kInverse ? launch_one<P, kInverse, 16>(a, st) : launch_one<P, kForward, 16>(a, st);
+        return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, st) : launch_one<P, kForward, 16>(a, ns, st);
     }
     a.ncb = (a.C + 63) / 64;
-    return mode == kInverse ? launch_one<P, kInverse, 64>(a, st) : launch_one<P, kForward, 64>(a, st);
+    return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, st) : launch_one<P, kForward, 64>(a, ns, st);
 }
 
 }  // namespace
@@ -663,6 +665,41 @@ template hipError_t launch_contract<double>(int, int, int, int, const double *, 
                                             const SpinPlan &, const RecTables &, hipStream_t);
 template hipError_t launch_contract<float>(int, int, int, int, const float *, float *, const EdgeTable &,
                                            const SpinPlan &, const RecTables &, hipStream_t);
+
+int build_contract_schedules(int L, RecTables &rt) {
+    static_assert(Prec<kP64>::TJ == 64 && Prec<kP32>::TJ == 128 && Prec<kPBF>::TJ == 128, "tile classes");
+    const int tjs[2] = {64, 128};
+    for (int mode = 0; mode < 2; ++mode)
+        for (int cls = 0; cls < 2; ++cls) {
+            const int TJ = tjs[cls];
+            const int nmg = (L + GM - 1) / GM, njt = (L + TJ - 1) / TJ;
+            std::vector<std::pair<int, int>> items;  // (K slabs, code)
+            for (int mg = 0; mg < nmg; ++mg)
+                for (int jt = 0; jt < njt; ++jt) {
+                    const int m0 = mg * GM, j0 = jt * TJ;
+                    int cost;
+                    if (mode == kInverse) {
+                        const int lo = m0 > j0 ? m0 : j0;
+                        cost = (L - (lo / TK) * TK + TK - 1) / TK;
+                    } else {
+                        if (j0 + TJ - 1 < m0) continue;  // outputs l < m are never read
+                        const int top = j0 + TJ - 1 < L - 1 ? j0 + TJ - 1 : L - 1;
+                        cost = (top + TK) / TK;
+                    }
+                    items.push_back({cost, (mg << 8) | jt});
+                }
+            std::stable_sort(items.begin(), items.end(),
+                             [](const std::pair<int, int> &x, const std::pair<int, int> &y) { return x.first > y.first; });
+            std::vector<int> codes(items.size());
+            for (size_t i = 0; i < items.size(); ++i) codes[i] = items[i].second;
+            if (hipMalloc(&rt.sched[mode][cls], codes.size() * sizeof(int)) != hipSuccess) return -1;
+            if (hipMemcpy(rt.sched[mode][cls], codes.data(), codes.size() * sizeof(int), hipMemcpyHostToDevice) !=
+                hipSuccess)
+                return -1;
+            rt.nsched[mode][cls] = (int)codes.size();
+        }
+    return 0;
+}
 
 hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const RecTables &rt, SpinPlan &sp,
                          hipStream_t st) {

@@ -64,11 +64,18 @@ template <typename T> struct FftTables {
 //   fab[a*L + l] = { a (2l+1) / (l sqrt((l+1)^2 - a^2)),
 //                    sqrt(l^2 - a^2) (l+1) / (l sqrt((l+1)^2 - a^2)) }  (0 at l = 0 or a > l)
 //   cl[l] = sqrt((2l+1)/(4 pi))
+//
+// and the contraction's workgroup order: for each mode (inverse, forward) and
+// tile width class (TJ = 64: FP64, TJ = 128: FP32 / BF16x3), the
+// (order group, j tile) pairs that have work, as (group << 8) | tile, sorted
+// by the length of their K loop, longest first (nsched entries each).
 struct RecTables {
     double *ri = nullptr;
     double *rf = nullptr;
     double2 *fab = nullptr;
     double *cl = nullptr;
+    int *sched[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int nsched[2][2] = {{0, 0}, {0, 0}};
 };
 
 struct Plan {
@@ -132,6 +139,8 @@ hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, cons
                            const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const RecTables &rt, SpinPlan &sp,
                          hipStream_t st);
+// fills rt.sched / rt.nsched for L (host sort, synchronous copy); 0 on success
+int build_contract_schedules(int L, RecTables &rt);
 hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y,
                                   const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 
