@@ -230,8 +230,12 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 
     if (producer) {
         // ================= producers: FP64 Wigner chains =================
+        // (FP32 / BF16x3: the producers issue ahead of the matrix-core waves)
+        if constexpr (P != kP64) __builtin_amdgcn_s_setprio(2);
         const int ptid = tid - NC;
-        const int jl = ptid % TJ, sub = ptid / TJ;
+        // sub (the order rows of this thread) is uniform across a wave, which
+        // lets the order-side recursion factors come in through scalar loads
+        const int jl = ptid % TJ, sub = __builtin_amdgcn_readfirstlane(ptid / TJ);
         const int j = j0 + jl;
         const bool jvalid = j < L;
         const double jd = (double)j;
@@ -287,9 +291,10 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                 dw[kk] = ok ? wtab[k * L] : T(0);
             }
         };
-        // order-side factors of the l-recursion for one slab (inverse)
+        // order-side factors of the l-recursion for one slab (inverse, FP64:
+        // staged through LDS; the FP32 paths read them with scalar loads)
         auto fill_factors = [&](int chunk, int buf) {
-            if (MODE == kInverse && ptid < GM * TK && chunk < nchunks) {
+            if (P == kP64 && MODE == kInverse && ptid < GM * TK && chunk < nchunks) {
                 const int gi = ptid / TK, kk = ptid % TK;
                 const int l = kbase_of(chunk) + kk;
                 const int idx = m0 + gi;
@@ -345,7 +350,16 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
                         const int gi = sub * NCH + g;
-                        double dn = -(ap * fam[buf][gi][kk] * ch[g].d + bp * fbm[buf][gi][kk] * ch[g].dp);
+                        double am, bm;
+                        if constexpr (P == kP64) {
+                            am = fam[buf][gi][kk];
+                            bm = fbm[buf][gi][kk];
+                        } else {
+                            const double2 f = a.fab[(size_t)(m0 + gi) * L + l];
+                            am = f.x;
+                            bm = f.y;
+                        }
+                        double dn = -(ap * am * ch[g].d + bp * bm * ch[g].dp);
                         if constexpr (INJ) dn += (l + 1 == l0[g]) ? sv[g] : 0.0;
                         ch[g].dp = ch[g].d;
                         ch[g].d = dn;
