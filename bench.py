@@ -187,6 +187,7 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-real", action="store_true")
     ap.add_argument("--tables", action="store_true",
                     help="also time the cached-table design (an L^3 table per spin, 4 GiB each in FP32 at L=1024)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -319,6 +320,34 @@ def main() -> int:
                   for s in wl.spins)
         out["bf16x3_path"] = {"value": round(per_step / (ms3 / 1e3), 2), "ms_per_step": round(ms3, 4),
                               "steps": n3, "round_trip_rel_l2": rt3}
+    if not args.no_real and prec != "fp64":
+        # real spin-0 maps (only m >= 0 transformed): the same L and batch
+        # coefficients of real signals: the spin-0 maps with f_{l0} made real
+        # (entries with m < 0 follow from f_{l,-m} = (-1)^m conj(f_lm) and are not read)
+        f0 = (flm[0] if 0 in flm else flm[wl.spins[0]]).clone()
+        l_of = torch.repeat_interleave(torch.arange(L, device=dev), 2 * torch.arange(L, device=dev) + 1)
+        m_of = torch.arange(L * L, device=dev) - l_of * l_of - l_of
+        f0[:, m_of == 0] = f0[:, m_of == 0].real.to(f0.dtype)
+        rmap = torch.empty((B, L, 2 * L - 1), dtype=sht.real_dtype(prec), device=dev)
+        rback = torch.empty_like(f0)
+        wsr = torch.empty(sht.workspace_bytes(L, 0, B, prec), dtype=torch.uint8, device=dev)
+        sht.plan_warmup(L, 0, prec)
+        for _ in range(2):
+            sht.inverse_real(f0, L, prec, out=rmap, workspace=wsr)
+            sht.forward_real(rmap, L, prec, out=rback, workspace=wsr)
+        torch.cuda.synchronize()
+        n_r = max(2, min(args.steps, 10))
+        t0 = time.perf_counter()
+        for _ in range(n_r):
+            sht.inverse_real(f0, L, prec, out=rmap, workspace=wsr)
+            sht.forward_real(rmap, L, prec, out=rback, workspace=wsr)
+        torch.cuda.synchronize()
+        ms_r = (time.perf_counter() - t0) / n_r * 1e3
+        pos = m_of >= 0
+        rt_r = float(torch.linalg.vector_norm((rback - f0)[:, pos]) / torch.linalg.vector_norm(f0[:, pos]))
+        out["real_signal_path"] = {"workload": f"L={L}, spin 0, {B} real maps, inverse + forward",
+                                   "value": round(B / (ms_r / 1e3), 2), "unit": "transforms/s",
+                                   "ms_per_batch": round(ms_r, 4), "round_trip_rel_l2_m_ge_0": rt_r}
     if args.tables:
         # the precomputed-table design: M streamed from a cached L^3 table
         for s in wl.spins:

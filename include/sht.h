@@ -106,6 +106,26 @@ int sht_forward(int L, int spin, int batch, int sampling, int precision,
                 void *stream);
 
 /*
+ * Real spin-0 signals (Section 3.3): for a real map f, f_{l,-m} =
+ * (-1)^m conj(f_lm), and only the orders m >= 0 are transformed (half the
+ * contraction columns and half the theta-stage rows of the complex path).
+ *   sht_inverse_real: flm in [batch][L*L] complex (entries with m < 0 are not
+ *                     read), map out [batch][L][2L-1] REAL (double for
+ *                     SHT_FP64, float otherwise).
+ *   sht_forward_real: map in (real, as above), flm out [batch][L*L] complex
+ *                     with every m written (m < 0 from the symmetry).
+ * The map needs element alignment (8 or 4 bytes), flm complex alignment; the
+ * workspace size is sht_workspace_bytes(L, 0, batch, sampling, precision).
+ * Precisions and errors as for sht_inverse / sht_forward.
+ */
+int sht_inverse_real(int L, int batch, int sampling, int precision,
+                     const void *flm, void *map, void *workspace, size_t ws_bytes,
+                     void *stream);
+int sht_forward_real(int L, int batch, int sampling, int precision,
+                     const void *map, void *flm, void *workspace, size_t ws_bytes,
+                     void *stream);
+
+/*
  * The paper's own forward transform (Section 3.4.2): phi DFT, the per-order
  * extension and theta DFT of Section 3.2 (Eq. (fourier_series)), then for
  * each order m0 the triangular system of Eq. (matrix_fwd),

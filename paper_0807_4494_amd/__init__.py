@@ -4,9 +4,10 @@ The transform runs in hand-written HIP kernels for gfx950 behind the C ABI of
 ``include/sht.h`` (``libsht.so``); this package is its thin Python binding.
 """
 
-from .sht import (PRECISIONS, forward, forward_triangular, inverse, io_dtype, plan_tables, plan_warmup,
-                  release_all, trace_enable, trace_read, version, workspace_bytes)
+from .sht import (PRECISIONS, forward, forward_real, forward_triangular, inverse, inverse_real, io_dtype,
+                  plan_tables, plan_warmup, real_dtype, release_all, trace_enable, trace_read, version,
+                  workspace_bytes)
 
-__all__ = ["PRECISIONS", "forward", "forward_triangular", "inverse", "io_dtype", "plan_tables", "plan_warmup",
-           "release_all",
+__all__ = ["PRECISIONS", "forward", "forward_real", "forward_triangular", "inverse", "inverse_real", "io_dtype",
+           "plan_tables", "plan_warmup", "real_dtype", "release_all",
            "trace_enable", "trace_read", "version", "workspace_bytes"]

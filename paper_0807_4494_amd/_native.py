@@ -25,7 +25,8 @@ SHT_FP64, SHT_FP32, SHT_BF16X3 = 0, 1, 2
 SHT_TRI_L_MAX = 128
 
 #: every symbol include/sht.h declares
-EXPORTS = ("sht_inverse", "sht_forward", "sht_forward_triangular", "sht_workspace_bytes", "sht_plan_warmup",
+EXPORTS = ("sht_inverse", "sht_forward", "sht_inverse_real", "sht_forward_real", "sht_forward_triangular",
+           "sht_workspace_bytes", "sht_plan_warmup",
            "sht_plan_tables",
            "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error",
            "sht_trace_enable", "sht_trace_read")
@@ -60,6 +61,10 @@ def load() -> ctypes.CDLL:
     for name in ("sht_inverse", "sht_forward", "sht_forward_triangular"):
         f = getattr(lib, name)
         f.argtypes = [i, i, i, i, i, vp, vp, vp, sz, vp]
+        f.restype = i
+    for name in ("sht_inverse_real", "sht_forward_real"):
+        f = getattr(lib, name)
+        f.argtypes = [i, i, i, i, vp, vp, vp, sz, vp]
         f.restype = i
     lib.sht_workspace_bytes.argtypes = [i, i, i, i, i]
     lib.sht_workspace_bytes.restype = sz

@@ -222,45 +222,68 @@ int check_buffers(int L, int batch, int precision, const void *in, const void *o
     return SHT_OK;
 }
 
-// The contraction in the path's own precision, or as BF16x3 on FP32 data.
-template <typename T>
-hipError_t contract(int mode, bool bf16x3, int L, int spin, int batch, const T *X, T *Y, const DeviceState *ds,
-                    const SpinPlan *sp, const RecTables &rec, hipStream_t st) {
-    if constexpr (sizeof(T) == 4) {
-        if (bf16x3) return launch_contract_bf16x3(mode, L, spin, batch, X, Y, ds->E, *sp, rec, st);
-    }
-    return launch_contract<T>(mode, L, spin, batch, X, Y, ds->E, *sp, rec, st);
+// Real maps: the map is real (element-aligned), the coefficients complex.
+int check_buffers_real(bool inverse, int L, int batch, int precision, const void *in, const void *out,
+                       const void *ws, size_t ws_bytes) {
+    if (!in || !out || !ws) return SHT_ERR_INVALID_ARG;
+    const size_t e = elem_bytes(precision);
+    const void *flm = inverse ? in : out, *map = inverse ? out : in;
+    if (misaligned(flm, 2 * e) || misaligned(map, e) || misaligned(ws, 256)) return SHT_ERR_ALIGNMENT;
+    size_t ra, rb;
+    regions(L, batch, precision, ra, rb);
+    if (ws_bytes < ra + rb) return SHT_ERR_WORKSPACE;
+    return SHT_OK;
 }
 
+// The contraction in the path's own precision, or as BF16x3 on FP32 data,
+// over C columns.
 template <typename T>
-int run_inverse(int L, int spin, int batch, bool bf16x3, const FftTables<T> &ft, const RecTables &rec,
+hipError_t contract(int mode, bool bf16x3, int L, int spin, int C, const T *X, T *Y, const DeviceState *ds,
+                    const SpinPlan *sp, const RecTables &rec, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        if (bf16x3) return launch_contract_bf16x3(mode, L, spin, C, X, Y, ds->E, *sp, rec, st);
+    }
+    return launch_contract<T>(mode, L, spin, C, X, Y, ds->E, *sp, rec, st);
+}
+
+// real: spin-0 real maps; only the orders m >= 0 are carried (2 columns per
+// map, L theta rows), and the phi stages read / write real rings.
+template <typename T>
+int run_inverse(int L, int spin, int batch, bool bf16x3, bool real, const FftTables<T> &ft, const RecTables &rec,
                 const DeviceState *ds, const SpinPlan *sp, const void *flm, void *map, void *ws, hipStream_t st) {
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
     T *P = (T *)w;            // region A: layout panels, later the theta-stage output
     T *R = (T *)(w + ra);     // region B: contraction output
-    SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st, [&] { return launch_layout_in<T>(L, spin, batch, flm, P, st); }),
+    const int C = (real ? 2 : 4) * batch;
+    const int rows = real ? L : ft.N;  // theta rows per map
+    SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st,
+                   [&] { return launch_layout_in<T>(L, spin, batch, real, flm, P, st); }),
             "layout_in");
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
-                   [&] { return contract<T>(kInverse, bf16x3, L, spin, batch, P, R, ds, sp, rec, st); }),
+                   [&] { return contract<T>(kInverse, bf16x3, L, spin, C, P, R, ds, sp, rec, st); }),
             "contract inverse");
     // theta stage writes rows g_mu(theta_t) over t (region A); the transpose
     // makes rings over mu (region B) for the phi stage
     SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
                    [&] {
-                       hipError_t e = launch_theta_inv<T>(ft, spin, batch, R, (void *)P, st);
+                       hipError_t e = launch_theta_inv<T>(ft, spin, batch, real, R, (void *)P, st);
                        if (e != hipSuccess) return e;
-                       return launch_transpose<T>(batch, ft.N, L, (const void *)P, (void *)R, st);
+                       return launch_transpose<T>(batch, rows, L, (const void *)P, (void *)R, st);
                    }),
             "theta inverse");
-    SHT_HIP(traced(SHT_STAGE_PHI_INV, st, [&] { return launch_phi_inv<T>(ft, batch, (const void *)R, map, st); }),
+    SHT_HIP(traced(SHT_STAGE_PHI_INV, st,
+                   [&] {
+                       return real ? launch_phi_inv_real<T>(ft, batch, (const void *)R, (T *)map, st)
+                                   : launch_phi_inv<T>(ft, batch, (const void *)R, map, st);
+                   }),
             "phi inverse");
     return SHT_OK;
 }
 
 template <typename T>
-int run_forward(int L, int spin, int batch, bool bf16x3, const FftTables<T> &ft, const RecTables &rec,
+int run_forward(int L, int spin, int batch, bool bf16x3, bool real, const FftTables<T> &ft, const RecTables &rec,
                 const DeviceState *ds, const SpinPlan *sp, const void *map, void *flm, void *ws, hipStream_t st) {
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
@@ -268,22 +291,56 @@ int run_forward(int L, int spin, int batch, bool bf16x3, const FftTables<T> &ft,
     void *Q = (void *)w;          // region A: phi-stage output (rings over mu)
     void *Qt = (void *)(w + ra);  // region B: the same as rows over t
     T *X = (T *)w;                // region A: weighted theta coefficients
-    SHT_HIP(traced(SHT_STAGE_PHI_FWD, st, [&] { return launch_phi_fwd<T>(ft, batch, map, Q, st); }),
+    const int C = (real ? 2 : 4) * batch;
+    const int cols = real ? L : ft.N;  // orders per ring
+    SHT_HIP(traced(SHT_STAGE_PHI_FWD, st,
+                   [&] {
+                       return real ? launch_phi_fwd_real<T>(ft, batch, (const T *)map, Q, st)
+                                   : launch_phi_fwd<T>(ft, batch, map, Q, st);
+                   }),
             "phi forward");
     SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
                    [&] {
-                       hipError_t e = launch_transpose<T>(batch, L, ft.N, Q, Qt, st);
+                       hipError_t e = launch_transpose<T>(batch, L, cols, Q, Qt, st);
                        if (e != hipSuccess) return e;
-                       return launch_theta_fwd<T>(ft, spin, batch, (const void *)Qt, X, st);
+                       return launch_theta_fwd<T>(ft, spin, batch, real, (const void *)Qt, X, st);
                    }),
             "theta forward");
     T *R = (T *)(w + ra);
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
-                   [&] { return contract<T>(kForward, bf16x3, L, spin, batch, X, R, ds, sp, rec, st); }),
+                   [&] { return contract<T>(kForward, bf16x3, L, spin, C, X, R, ds, sp, rec, st); }),
             "contract forward");
-    SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st, [&] { return launch_layout_out<T>(L, spin, batch, R, flm, st); }),
+    SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st,
+                   [&] { return launch_layout_out<T>(L, spin, batch, real, R, flm, st); }),
             "layout_out");
     return SHT_OK;
+}
+
+int transform(bool inverse, bool real, int L, int spin, int batch, int sampling, int precision, const void *in,
+              void *out, void *workspace, size_t ws_bytes, void *stream) {
+    int rc = check_args(L, spin, batch, sampling, precision);
+    if (rc != SHT_OK) return rc;
+    if (real && spin != 0) return SHT_ERR_INVALID_ARG;
+    rc = real ? check_buffers_real(inverse, L, batch, precision, in, out, workspace, ws_bytes)
+              : check_buffers(L, batch, precision, in, out, workspace, ws_bytes);
+    if (rc != SHT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    if (rc != SHT_OK) return rc;
+    const bool bf = precision == SHT_BF16X3;
+    if (precision == SHT_FP64) {
+        return inverse ? run_inverse<double>(L, spin, batch, false, real, plan->f64, plan->rec, ds, sp, in, out,
+                                             workspace, st)
+                       : run_forward<double>(L, spin, batch, false, real, plan->f64, plan->rec, ds, sp, in, out,
+                                             workspace, st);
+    }
+    return inverse ? run_inverse<float>(L, spin, batch, bf, real, plan->f32, plan->rec, ds, sp, in, out, workspace,
+                                        st)
+                   : run_forward<float>(L, spin, batch, bf, real, plan->f32, plan->rec, ds, sp, in, out, workspace,
+                                        st);
 }
 
 }  // namespace
@@ -299,38 +356,22 @@ size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precisi
 
 int sht_inverse(int L, int spin, int batch, int sampling, int precision, const void *flm, void *map,
                 void *workspace, size_t ws_bytes, void *stream) {
-    int rc = check_args(L, spin, batch, sampling, precision);
-    if (rc != SHT_OK) return rc;
-    rc = check_buffers(L, batch, precision, flm, map, workspace, ws_bytes);
-    if (rc != SHT_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    DeviceState *ds;
-    Plan *plan;
-    SpinPlan *sp;
-    rc = prepare(L, spin, st, &ds, &plan, &sp);
-    if (rc != SHT_OK) return rc;
-    if (precision == SHT_FP64)
-        return run_inverse<double>(L, spin, batch, false, plan->f64, plan->rec, ds, sp, flm, map, workspace, st);
-    return run_inverse<float>(L, spin, batch, precision == SHT_BF16X3, plan->f32, plan->rec, ds, sp, flm, map,
-                              workspace, st);
+    return transform(true, false, L, spin, batch, sampling, precision, flm, map, workspace, ws_bytes, stream);
 }
 
 int sht_forward(int L, int spin, int batch, int sampling, int precision, const void *map, void *flm,
                 void *workspace, size_t ws_bytes, void *stream) {
-    int rc = check_args(L, spin, batch, sampling, precision);
-    if (rc != SHT_OK) return rc;
-    rc = check_buffers(L, batch, precision, map, flm, workspace, ws_bytes);
-    if (rc != SHT_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    DeviceState *ds;
-    Plan *plan;
-    SpinPlan *sp;
-    rc = prepare(L, spin, st, &ds, &plan, &sp);
-    if (rc != SHT_OK) return rc;
-    if (precision == SHT_FP64)
-        return run_forward<double>(L, spin, batch, false, plan->f64, plan->rec, ds, sp, map, flm, workspace, st);
-    return run_forward<float>(L, spin, batch, precision == SHT_BF16X3, plan->f32, plan->rec, ds, sp, map, flm,
-                              workspace, st);
+    return transform(false, false, L, spin, batch, sampling, precision, map, flm, workspace, ws_bytes, stream);
+}
+
+int sht_inverse_real(int L, int batch, int sampling, int precision, const void *flm, void *map, void *workspace,
+                     size_t ws_bytes, void *stream) {
+    return transform(true, true, L, 0, batch, sampling, precision, flm, map, workspace, ws_bytes, stream);
+}
+
+int sht_forward_real(int L, int batch, int sampling, int precision, const void *map, void *flm, void *workspace,
+                     size_t ws_bytes, void *stream) {
+    return transform(false, true, L, 0, batch, sampling, precision, map, flm, workspace, ws_bytes, stream);
 }
 
 int sht_forward_triangular(int L, int spin, int batch, int sampling, int precision, const void *map, void *flm,

@@ -105,7 +105,7 @@ template <int CTILE> struct Slabs<kPBF, CTILE> {
 };
 
 template <typename T> struct Args {
-    int L, s, B, C;       // C = 4B columns
+    int L, s, C;          // C columns (4 per map; 2 per map for real signals)
     int njt, ncb;         // j tiles, column blocks
     const T *X;           // [L][C][L]
     T *Y;                 // [L][C][L]
@@ -636,14 +636,13 @@ __global__ void k_mtable(int L, EdgeTable E, const double *ri, const double2 *fa
 }
 
 template <int P>
-hipError_t launch_prec(int mode, int L, int s, int B, const typename Prec<P>::T *X, typename Prec<P>::T *Y,
+hipError_t launch_prec(int mode, int L, int s, int C, const typename Prec<P>::T *X, typename Prec<P>::T *Y,
                        const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
     using T = typename Prec<P>::T;
     Args<T> a;
     a.L = L;
     a.s = s;
-    a.B = B;
-    a.C = 4 * B;
+    a.C = C;
     a.njt = (L + Prec<P>::TJ - 1) / Prec<P>::TJ;
     a.X = X;
     a.Y = Y;
@@ -669,10 +668,10 @@ hipError_t launch_prec(int mode, int L, int s, int B, const typename Prec<P>::T 
 }  // namespace
 
 template <typename T>
-hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
+hipError_t launch_contract(int mode, int L, int s, int C, const T *X, T *Y, const EdgeTable &E,
                            const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
     constexpr int P = sizeof(T) == 8 ? kP64 : kP32;
-    return launch_prec<P>(mode, L, s, B, X, Y, E, sp, rt, st);
+    return launch_prec<P>(mode, L, s, C, X, Y, E, sp, rt, st);
 }
 
 template hipError_t launch_contract<double>(int, int, int, int, const double *, double *, const EdgeTable &,
@@ -725,9 +724,9 @@ hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const Re
     return hipGetLastError();
 }
 
-hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y, const EdgeTable &E,
+hipError_t launch_contract_bf16x3(int mode, int L, int s, int C, const float *X, float *Y, const EdgeTable &E,
                                   const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
-    return launch_prec<kPBF>(mode, L, s, B, X, Y, E, sp, rt, st);
+    return launch_prec<kPBF>(mode, L, s, C, X, Y, E, sp, rt, st);
 }
 
 }  // namespace sht

@@ -209,8 +209,9 @@ __device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typena
 //   g_mu(theta_t) = (Z(theta_t) + sigma_mu Z(theta_{N-1-t})) / 2.
 // Block (b, i) takes mu = 2i - (L-1) and mu + 1 (the last block of a map
 // takes mu = L-1 alone).  Output G'[b][mu + L - 1][t] (rows; transposed for
-// the phi stage afterwards).
-template <typename T, int LOGM>
+// the phi stage afterwards).  HALF (real spin-0 signals): only mu >= 0, from
+// the 2-column panels, pairs (2i, 2i+1), output G'[b][mu][t].
+template <typename T, int LOGM, bool HALF>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B,
                                                            const T *__restrict__ R,
                                                            typename CT<T>::type *__restrict__ G) {
@@ -218,8 +219,9 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const int pair = blockIdx.x % L, b = blockIdx.x / L;
-    const int Cn = 4 * B;
+    const int npair = HALF ? (L + 1) / 2 : L;
+    const int pair = blockIdx.x % npair, b = blockIdx.x / npair;
+    const int Cn = (HALF ? 2 : 4) * B;
     const T sgn_s = (s & 1) ? T(-1) : T(1);
     struct Row {
         const T *re, *im;
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
         r.odd = parity((long long)mu + s);
         return r;
     };
-    const int mua = 2 * pair - h;
+    const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
     const Row ra = row_of(mua), rb = row_of(two ? mua + 1 : mua);
     auto coef = [&](const Row &r, int n) -> C {
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
         if (t < N) buf[pad(t)] = cmul(y, chb[t]);
     };
     convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
-    C *Ga = G + ((size_t)b * N + (mua + h)) * L;
+    C *Ga = G + ((size_t)b * (HALF ? L : N) + (HALF ? mua : mua + h)) * L;
     C *Gb = Ga + L;
     const T sa = ra.odd ? T(-0.5) : T(0.5);
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
@@ -337,7 +339,9 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
 // Written as X[|mu|][c][m'] with c = q*B + b (q = 0,1 for mu >= 0, 2,3 for
 // mu < 0), times (-1)^{m'} for mu < 0 (the d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
 // symmetry; the (-1)^l part is applied on output).
-template <typename T, int LOGM>
+// HALF (real spin-0 signals): only mu >= 0, rows Q'[b][mu][t], pairs
+// (2i, 2i+1), 2-column panels.
+template <typename T, int LOGM, bool HALF>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B,
                                                            const typename CT<T>::type *__restrict__ Q,
                                                            T *__restrict__ X) {
@@ -345,11 +349,12 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const int pair = blockIdx.x % L, b = blockIdx.x / L;
-    const int mua = 2 * pair - h;
+    const int npair = HALF ? (L + 1) / 2 : L;
+    const int pair = blockIdx.x % npair, b = blockIdx.x / npair;
+    const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
     const int oddA = parity((long long)mua + s);
-    const C *Qa = Q + ((size_t)b * N + (mua + h)) * L;  // rows over t < L
+    const C *Qa = Q + ((size_t)b * (HALF ? L : N) + (HALF ? mua : mua + h)) * L;  // rows over t < L
     const C *Qb = Qa + L;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     // Y(m') at buf[m' + h], |m'| <= h
     convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, [buf](int n) { return buf[pad(n)]; },
                       [buf, N](int k, C y) { if (k < N) buf[pad(k)] = y; });
-    const int Cn = 4 * B;
+    const int Cn = (HALF ? 2 : 4) * B;
     const T twopi = T(6.283185307179586476925286766559);
     const T pi2 = T(9.8696044010893586188344909998762);
     auto store = [&](int mu, int odd, const C *Qr) {
@@ -405,6 +410,59 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     };
     store(mua, oddA, Qa);
     if (two) store(mua + 1, !oddA, Qb);
+}
+
+// Real spin-0 maps.  Inverse phi stage from the orders m >= 0: row (b, t) of
+// G'[b][t][m] (L entries), g_{-m} = conj(g_m) (Section 3.3), real output.
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft,
+                                                              const typename CT<T>::type *__restrict__ G,
+                                                              T *__restrict__ map) {
+    using C = typename CT<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int L = ft.L, N = ft.N, h = L - 1;
+    const size_t row = blockIdx.x;
+    const C *in = G + row * L;
+    T *out = map + row * N;
+    const C *cha = ft.cha, *chb = ft.chb;
+    auto ld = [&](int n) -> C {
+        if (n >= N) return C{T(0), T(0)};
+        const int mu = n - h;
+        const C v = mu >= 0 ? in[mu] : conj(in[-mu]);
+        return cmul(v, cha[n]);
+    };
+    auto st = [&](int p, C y) {
+        if (p < N) out[p] = y.x * chb[p].x - y.y * chb[p].y;
+    };
+    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
+}
+
+// Forward phi stage of a real ring, keeping the orders m >= 0:
+// Q[b][t][m] = N^-1 sum_p f(theta_t, phi_p) e^{-i m phi_p}, m < L.
+template <typename T, int LOGM>
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft, const T *__restrict__ map,
+                                                              typename CT<T>::type *__restrict__ Q) {
+    using C = typename CT<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *buf = reinterpret_cast<C *>(smem_raw);
+    const int L = ft.L, N = ft.N, h = L - 1;
+    const size_t row = blockIdx.x;
+    const T *in = map + row * N;
+    C *out = Q + row * L;
+    const C *cha = ft.cha, *chb = ft.chb;
+    const T invN = T(1) / T(N);
+    auto ld = [&](int n) -> C {
+        if (n >= N) return C{T(0), T(0)};
+        return cmulc(C{in[n], T(0)}, chb[n]);
+    };
+    auto st = [&](int k, C y) {
+        if (k >= h && k < N) {
+            const C z = cmulc(y, cha[k]);
+            out[k - h] = C{z.x * invN, z.y * invN};
+        }
+    };
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
 }
 
 // Theta DFT alone, for the paper's own forward transform (per-order
@@ -511,14 +569,22 @@ template <typename F> hipError_t with_logm(int logM, F f) {
 }
 
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, const T *R, void *G, hipStream_t st) {
+hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, bool half, const T *R, void *G, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
-        hipError_t e = set_lds(k_theta_inv<T, LM>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_theta_inv<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft, s, B, R,
-                           (typename CT<T>::type *)G);
+        typename CT<T>::type *g = (typename CT<T>::type *)G;
+        if (half) {
+            hipError_t e = set_lds(k_theta_inv<T, LM, true>, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_theta_inv<T, LM, true>), dim3((ft.L + 1) / 2 * B), dim3(row_threads(ft.M)), lds,
+                               st, ft, s, B, R, g);
+        } else {
+            hipError_t e = set_lds(k_theta_inv<T, LM, false>, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_theta_inv<T, LM, false>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
+                               s, B, R, g);
+        }
         return hipGetLastError();
     });
 }
@@ -550,14 +616,48 @@ hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *
 }
 
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q, T *X, hipStream_t st) {
+hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, bool half, const void *Q, T *X, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
-        hipError_t e = set_lds(k_theta_fwd<T, LM>, lds);
+        const typename CT<T>::type *q = (const typename CT<T>::type *)Q;
+        if (half) {
+            hipError_t e = set_lds(k_theta_fwd<T, LM, true>, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_theta_fwd<T, LM, true>), dim3((ft.L + 1) / 2 * B), dim3(row_threads(ft.M)), lds,
+                               st, ft, s, B, q, X);
+        } else {
+            hipError_t e = set_lds(k_theta_fwd<T, LM, false>, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_theta_fwd<T, LM, false>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
+                               s, B, q, X);
+        }
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, hipStream_t st) {
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_phi_inv_real<T, LM>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_theta_fwd<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft, s, B,
-                           (const typename CT<T>::type *)Q, X);
+        hipLaunchKernelGGL((k_phi_inv_real<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
+                           (const typename CT<T>::type *)G, map);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+hipError_t launch_phi_fwd_real(const FftTables<T> &ft, int B, const T *map, void *Q, hipStream_t st) {
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_phi_fwd_real<T, LM>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_phi_fwd_real<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft, map,
+                           (typename CT<T>::type *)Q);
         return hipGetLastError();
     });
 }
@@ -597,11 +697,13 @@ hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out
 }
 
 #define SHT_INST(T)                                                                                      \
-    template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, const T *, void *, hipStream_t); \
+    template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, bool, const T *, void *, hipStream_t); \
+    template hipError_t launch_phi_inv_real<T>(const FftTables<T> &, int, const void *, T *, hipStream_t);  \
+    template hipError_t launch_phi_fwd_real<T>(const FftTables<T> &, int, const T *, void *, hipStream_t);  \
     template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
     template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
     template hipError_t launch_theta_dft<T>(const FftTables<T> &, int, int, const void *, void *, hipStream_t); \
-    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, const void *, T *, hipStream_t); \
+    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, bool, const void *, T *, hipStream_t); \
     template hipError_t launch_transpose<T>(int, int, int, const void *, void *, hipStream_t);                \
     template hipError_t launch_fft_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \
                                                   hipStream_t);

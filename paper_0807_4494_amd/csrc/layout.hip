@@ -11,6 +11,10 @@
 // Both kernels transpose 32 x 32 (l, m) tiles through LDS so that the
 // coefficient rows (contiguous in m) and the panels (contiguous in l) are
 // both accessed with unit stride.
+//
+// HALF (real spin-0 signals, f_{l,-m} = (-1)^m conj(f_lm), Section 3.3):
+// only q = 0, 1 are kept (c = q*B + b, 2B columns); the output side writes
+// the negative orders from the symmetry.
 #include "sht_internal.h"
 
 namespace sht {
@@ -19,7 +23,7 @@ namespace {
 
 constexpr int TL = 32;  // tile edge
 
-template <typename T>
+template <typename T, bool HALF>
 __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, const typename CT<T>::type *__restrict__ flm,
                                                   T *__restrict__ P) {
     using C = typename CT<T>::type;
@@ -38,7 +42,7 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, const ty
             const C p = fb[base + m];
             v0 = p.x;
             v1 = p.y;
-            if (m > 0) {
+            if (!HALF && m > 0) {
                 const C q = fb[base - m];
                 const T sg = (l & 1) ? T(-1) : T(1);
                 v2 = q.x * sg;
@@ -52,11 +56,12 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, const ty
     }
     __syncthreads();
     // write: x runs over l (contiguous in the panel)
-    const int Cn = 4 * B;
+    constexpr int NQ = HALF ? 2 : 4;
+    const int Cn = NQ * B;
     for (int mi = ty; mi < TL; mi += 8) {
         const int m = m0 + mi, l = l0 + tx;
         if (m >= L || l >= L || l < m) continue;
-        for (int q = 0; q < 4; ++q) P[((size_t)m * Cn + (size_t)q * B + b) * L + l] = tile[q][tx][mi];
+        for (int q = 0; q < NQ; ++q) P[((size_t)m * Cn + (size_t)q * B + b) * L + l] = tile[q][tx][mi];
     }
 }
 
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, const ty
 // R[m][c][l], applying the remaining factors of the conjugated Eq. (shf_exp):
 //   f_{l, m}  = (-1)^s i^{m+s}              (R0 + i R1)
 //   f_{l,-m}  = (-1)^s i^{s-m} (-1)^l       (R2 + i R3)      (m > 0)
-template <typename T>
+template <typename T, bool HALF>
 __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, const T *__restrict__ R,
                                                    typename CT<T>::type *__restrict__ flm) {
     using C = typename CT<T>::type;
@@ -72,14 +77,15 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, const T
     const int l0 = blockIdx.x * TL, m0 = blockIdx.y * TL, b = blockIdx.z;
     if (l0 + TL - 1 < m0) return;
     const int as = s < 0 ? -s : s;
-    const int Cn = 4 * B;
+    constexpr int NQ = HALF ? 2 : 4;
+    const int Cn = NQ * B;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // read: x runs over l
     for (int mi = ty; mi < TL; mi += 8) {
         const int m = m0 + mi, l = l0 + tx;
         T v[4] = {0, 0, 0, 0};
         if (m < L && l < L && l >= m && l >= as) {
-            for (int q = 0; q < 4; ++q) v[q] = R[((size_t)m * Cn + (size_t)q * B + b) * L + l];
+            for (int q = 0; q < NQ; ++q) v[q] = R[((size_t)m * Cn + (size_t)q * B + b) * L + l];
         }
         for (int q = 0; q < 4; ++q) tile[q][mi][tx] = v[q];
     }
@@ -100,7 +106,10 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, const T
             default: p = C{p.y, -p.x}; break;
         }
         fb[base + m] = p;
-        if (m > 0) {
+        if (HALF && m > 0) {
+            // f_{l,-m} = (-1)^m conj(f_lm)
+            fb[base - m] = (m & 1) ? C{-p.x, p.y} : C{p.x, -p.y};
+        } else if (m > 0) {
             const T sl = (l & 1) ? -sgn_s : sgn_s;
             C q{tile[2][tx][li] * sl, tile[3][tx][li] * sl};
             switch ((s - m) & 3) {
@@ -117,22 +126,26 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, const T
 }  // namespace
 
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, const void *flm, T *P, hipStream_t st) {
+hipError_t launch_layout_in(int L, int s, int B, bool half, const void *flm, T *P, hipStream_t st) {
     dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
-    hipLaunchKernelGGL(k_layout_in<T>, grid, dim3(256), 0, st, L, s, B, (const typename CT<T>::type *)flm, P);
+    const typename CT<T>::type *f = (const typename CT<T>::type *)flm;
+    if (half) hipLaunchKernelGGL((k_layout_in<T, true>), grid, dim3(256), 0, st, L, s, B, f, P);
+    else hipLaunchKernelGGL((k_layout_in<T, false>), grid, dim3(256), 0, st, L, s, B, f, P);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, const T *R, void *flm, hipStream_t st) {
+hipError_t launch_layout_out(int L, int s, int B, bool half, const T *R, void *flm, hipStream_t st) {
     dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
-    hipLaunchKernelGGL(k_layout_out<T>, grid, dim3(256), 0, st, L, s, B, R, (typename CT<T>::type *)flm);
+    typename CT<T>::type *f = (typename CT<T>::type *)flm;
+    if (half) hipLaunchKernelGGL((k_layout_out<T, true>), grid, dim3(256), 0, st, L, s, B, R, f);
+    else hipLaunchKernelGGL((k_layout_out<T, false>), grid, dim3(256), 0, st, L, s, B, R, f);
     return hipGetLastError();
 }
 
-template hipError_t launch_layout_in<double>(int, int, int, const void *, double *, hipStream_t);
-template hipError_t launch_layout_in<float>(int, int, int, const void *, float *, hipStream_t);
-template hipError_t launch_layout_out<double>(int, int, int, const double *, void *, hipStream_t);
-template hipError_t launch_layout_out<float>(int, int, int, const float *, void *, hipStream_t);
+template hipError_t launch_layout_in<double>(int, int, int, bool, const void *, double *, hipStream_t);
+template hipError_t launch_layout_in<float>(int, int, int, bool, const void *, float *, hipStream_t);
+template hipError_t launch_layout_out<double>(int, int, int, bool, const double *, void *, hipStream_t);
+template hipError_t launch_layout_out<float>(int, int, int, bool, const float *, void *, hipStream_t);
 
 }  // namespace sht

@@ -107,20 +107,26 @@ hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
 // layout.hip
+// half: real spin-0 signals, orders m >= 0 only (2 columns per map)
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, const void *flm, T *P, hipStream_t st);
+hipError_t launch_layout_in(int L, int s, int B, bool half, const void *flm, T *P, hipStream_t st);
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, const T *R, void *flm, hipStream_t st);
+hipError_t launch_layout_out(int L, int s, int B, bool half, const T *R, void *flm, hipStream_t st);
 
 // fft.hip: row transforms
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, const T *R, void *G, hipStream_t st);
+hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, bool half, const T *R, void *G, hipStream_t st);
 template <typename T>
 hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, hipStream_t st);
 template <typename T>
 hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st);
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, const void *Q, T *X, hipStream_t st);
+hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, bool half, const void *Q, T *X, hipStream_t st);
+// real maps (spin 0): phi synthesis from orders m >= 0, phi analysis keeping m >= 0
+template <typename T>
+hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, hipStream_t st);
+template <typename T>
+hipError_t launch_phi_fwd_real(const FftTables<T> &ft, int B, const T *map, void *Q, hipStream_t st);
 // theta DFT of the extended rows alone, F[b][mu][m'] for m' in [0, L)
 template <typename T>
 hipError_t launch_theta_dft(const FftTables<T> &ft, int s, int B, const void *Q, void *F, hipStream_t st);
@@ -134,14 +140,16 @@ hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf,
 
 // contract.hip
 enum ContractMode { kInverse = 0, kForward = 1 };
+// C columns: 4 per map for complex signals (Re, Im of f_{l,m} and of
+// (-1)^l f_{l,-m}), 2 per map for real spin-0 signals (m >= 0 only)
 template <typename T>
-hipError_t launch_contract(int mode, int L, int s, int B, const T *X, T *Y, const EdgeTable &E,
+hipError_t launch_contract(int mode, int L, int s, int C, const T *X, T *Y, const EdgeTable &E,
                            const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const RecTables &rt, SpinPlan &sp,
                          hipStream_t st);
 // fills rt.sched / rt.nsched for L (host sort, synchronous copy); 0 on success
 int build_contract_schedules(int L, RecTables &rt);
-hipError_t launch_contract_bf16x3(int mode, int L, int s, int B, const float *X, float *Y,
+hipError_t launch_contract_bf16x3(int mode, int L, int s, int C, const float *X, float *Y,
                                   const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 
 // tri.hip: the paper's per-order triangular systems (FP64, L <= SHT_TRI_L_MAX)

@@ -94,6 +94,54 @@ def forward(fmap: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Op
     return out[0] if single else out
 
 
+def real_dtype(precision) -> torch.dtype:
+    return torch.float64 if _prec(precision) == N.SHT_FP64 else torch.float32
+
+
+def inverse_real(flm: torch.Tensor, L: int, precision="fp64", out: Optional[torch.Tensor] = None,
+                 workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Inverse transform of a real spin-0 signal: f_lm (m >= 0 read) -> real samples."""
+    p = _prec(precision)
+    single = flm.dim() == 1
+    f = flm.reshape(1, -1) if single else flm
+    if f.shape[-1] != L * L:
+        raise ValueError(f"flm has {f.shape[-1]} coefficients per map, expected L*L = {L * L}")
+    if not f.is_cuda:
+        raise ValueError("flm must be a GPU tensor")
+    f = f.to(io_dtype(p)).contiguous()
+    B = f.shape[0]
+    if out is None:
+        out = torch.empty((B, L, 2 * L - 1), dtype=real_dtype(p), device=f.device)
+    ws, nbytes = _workspace(L, 0, B, p, f.device, workspace)
+    rc = N.load().sht_inverse_real(L, B, N.SHT_SAMPLING_MW, p, f.data_ptr(), out.data_ptr(),
+                                   ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(f.device))
+    N.check(rc, "sht_inverse_real")
+    return out[0] if single else out
+
+
+def forward_real(fmap: torch.Tensor, L: int, precision="fp64", out: Optional[torch.Tensor] = None,
+                 workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Forward transform of a real spin-0 map -> f_lm (all m)."""
+    p = _prec(precision)
+    single = fmap.dim() == 2
+    g = fmap.reshape(1, *fmap.shape) if single else fmap
+    if tuple(g.shape[-2:]) != (L, 2 * L - 1):
+        raise ValueError(f"map shape {tuple(g.shape[-2:])}, expected ({L}, {2 * L - 1})")
+    if not g.is_cuda:
+        raise ValueError("map must be a GPU tensor")
+    if g.is_complex():
+        raise ValueError("forward_real takes a real map")
+    g = g.to(real_dtype(p)).contiguous()
+    B = g.shape[0]
+    if out is None:
+        out = torch.empty((B, L * L), dtype=io_dtype(p), device=g.device)
+    ws, nbytes = _workspace(L, 0, B, p, g.device, workspace)
+    rc = N.load().sht_forward_real(L, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
+                                   ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(g.device))
+    N.check(rc, "sht_forward_real")
+    return out[0] if single else out
+
+
 def forward_triangular(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch.Tensor] = None,
                        workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The paper's own forward transform (per-order triangular systems), FP64,

@@ -66,6 +66,13 @@ def test_argument_checks_run_before_any_hip_call():
     need = lib.sht_workspace_bytes(8, 0, 1, 0, 0)
     assert call(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
     assert lib.sht_forward(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
+    # real-signal entry points: map element-aligned, flm complex-aligned
+    assert lib.sht_inverse_real(8, 1, 0, 0, ctypes.c_void_p((1 << 20) + 8), fake, fake, big, None) == \
+        N.SHT_ERR_ALIGNMENT
+    assert lib.sht_forward_real(8, 1, 0, 1, ctypes.c_void_p((1 << 20) + 2), fake, fake, big, None) == \
+        N.SHT_ERR_ALIGNMENT
+    assert lib.sht_forward_real(0, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_forward_real(8, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
     # the triangular forward: FP64 only, L <= SHT_TRI_L_MAX
     tri = lib.sht_forward_triangular
     assert tri(8, 0, 1, 0, 1, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
