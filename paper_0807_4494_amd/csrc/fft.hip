@@ -412,57 +412,79 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     if (two) store(mua + 1, !oddA, Qb);
 }
 
-// Real spin-0 maps.  Inverse phi stage from the orders m >= 0: row (b, t) of
-// G'[b][t][m] (L entries), g_{-m} = conj(g_m) (Section 3.3), real output.
+// Real spin-0 maps, two rings per transform (rows r and r+1 of the [B*L]
+// rings).  Inverse phi stage from the orders m >= 0 of G'[r][m] (L entries),
+// g_{-m} = conj(g_m) (Section 3.3): each ring's samples are real, so the
+// spectrum g_r + i g_{r+1} gives ring r in the real part and ring r+1 in the
+// imaginary part of one synthesis.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft,
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft, int rows,
                                                               const typename CT<T>::type *__restrict__ G,
                                                               T *__restrict__ map) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const size_t row = blockIdx.x;
-    const C *in = G + row * L;
-    T *out = map + row * N;
+    const size_t r0 = 2 * (size_t)blockIdx.x;
+    const bool two = r0 + 1 < (size_t)rows;
+    const C *ina = G + r0 * L, *inb = ina + L;
+    T *outa = map + r0 * N, *outb = outa + N;
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
-        const int mu = n - h;
-        const C v = mu >= 0 ? in[mu] : conj(in[-mu]);
-        return cmul(v, cha[n]);
+        const int mu = n - h, am = mu < 0 ? -mu : mu;
+        C a = ina[am], b = two ? inb[am] : C{T(0), T(0)};
+        if (mu < 0) {
+            a = conj(a);
+            b = conj(b);
+        }
+        return cmul(C{a.x - b.y, a.y + b.x}, cha[n]);  // a + i b
     };
     auto st = [&](int p, C y) {
-        if (p < N) out[p] = y.x * chb[p].x - y.y * chb[p].y;
+        if (p < N) {
+            const C z = cmul(y, chb[p]);
+            outa[p] = z.x;
+            if (two) outb[p] = z.y;
+        }
     };
     convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
 }
 
-// Forward phi stage of a real ring, keeping the orders m >= 0:
-// Q[b][t][m] = N^-1 sum_p f(theta_t, phi_p) e^{-i m phi_p}, m < L.
+// Forward phi stage of two real rings r, r+1 at once, keeping the orders
+// m >= 0: the DFT Z of x_r + i x_{r+1} gives
+//   Q_r(m) = (Z_m + conj(Z_{-m})) / 2,  Q_{r+1}(m) = (Z_m - conj(Z_{-m})) / (2i),
+// with Q(m) = N^-1 sum_p x(phi_p) e^{-i m phi_p}.  Output Q[r][m], m < L.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft, const T *__restrict__ map,
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft, int rows,
+                                                              const T *__restrict__ map,
                                                               typename CT<T>::type *__restrict__ Q) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const size_t row = blockIdx.x;
-    const T *in = map + row * N;
-    C *out = Q + row * L;
+    const size_t r0 = 2 * (size_t)blockIdx.x;
+    const bool two = r0 + 1 < (size_t)rows;
+    const T *ina = map + r0 * N, *inb = ina + N;
+    C *outa = Q + r0 * L, *outb = outa + L;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
         if (n >= N) return C{T(0), T(0)};
-        return cmulc(C{in[n], T(0)}, chb[n]);
+        return cmulc(C{ina[n], two ? inb[n] : T(0)}, chb[n]);
     };
+    // Z_{k-h}, k < N, lands in LDS
     auto st = [&](int k, C y) {
-        if (k >= h && k < N) {
+        if (k < N) {
             const C z = cmulc(y, cha[k]);
-            out[k - h] = C{z.x * invN, z.y * invN};
+            buf[pad(k)] = C{z.x * invN, z.y * invN};
         }
     };
     convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
+    for (int m = threadIdx.x; m < L; m += blockDim.x) {
+        const C zp = buf[pad(h + m)], zm = buf[pad(h - m)];
+        outa[m] = C{T(0.5) * (zp.x + zm.x), T(0.5) * (zp.y - zm.y)};
+        if (two) outb[m] = C{T(0.5) * (zp.y + zm.y), T(0.5) * (zm.x - zp.x)};
+    }
 }
 
 // Theta DFT alone, for the paper's own forward transform (per-order
@@ -643,8 +665,9 @@ hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_inv_real<T, LM>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_phi_inv_real<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
-                           (const typename CT<T>::type *)G, map);
+        const int rows = ft.L * B;
+        hipLaunchKernelGGL((k_phi_inv_real<T, LM>), dim3((rows + 1) / 2), dim3(row_threads(ft.M)), lds, st, ft,
+                           rows, (const typename CT<T>::type *)G, map);
         return hipGetLastError();
     });
 }
@@ -656,8 +679,9 @@ hipError_t launch_phi_fwd_real(const FftTables<T> &ft, int B, const T *map, void
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_fwd_real<T, LM>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_phi_fwd_real<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft, map,
-                           (typename CT<T>::type *)Q);
+        const int rows = ft.L * B;
+        hipLaunchKernelGGL((k_phi_fwd_real<T, LM>), dim3((rows + 1) / 2), dim3(row_threads(ft.M)), lds, st, ft,
+                           rows, map, (typename CT<T>::type *)Q);
         return hipGetLastError();
     });
 }
