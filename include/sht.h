@@ -126,6 +126,18 @@ int sht_forward_real(int L, int batch, int sampling, int precision,
                      void *stream);
 
 /*
+ * Spin pairs (Section 3.3): when the spin -s field is the conjugate of the
+ * spin s field (e.g. Q + iU and Q - iU), one transform serves both:
+ *   {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m}),
+ * and the spin -s map is the conjugate of the spin s map.  This call writes
+ * the spin -s coefficients flm_ms [batch][L*L] from the spin s ones flm_s
+ * (distinct buffers, complex of the precision's type; zero for l < |s|),
+ * enqueued on `stream`.
+ */
+int sht_spin_pair(int L, int spin, int batch, int precision, const void *flm_s, void *flm_ms,
+                  void *stream);
+
+/*
  * The paper's own forward transform (Section 3.4.2): phi DFT, the per-order
  * extension and theta DFT of Section 3.2 (Eq. (fourier_series)), then for
  * each order m0 the triangular system of Eq. (matrix_fwd),

@@ -26,7 +26,7 @@ SHT_TRI_L_MAX = 128
 
 #: every symbol include/sht.h declares
 EXPORTS = ("sht_inverse", "sht_forward", "sht_inverse_real", "sht_forward_real", "sht_forward_triangular",
-           "sht_workspace_bytes", "sht_plan_warmup",
+           "sht_spin_pair", "sht_workspace_bytes", "sht_plan_warmup",
            "sht_plan_tables",
            "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error",
            "sht_trace_enable", "sht_trace_read")
@@ -66,6 +66,8 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = [i, i, i, i, vp, vp, vp, sz, vp]
         f.restype = i
+    lib.sht_spin_pair.argtypes = [i, i, i, i, vp, vp, vp]
+    lib.sht_spin_pair.restype = i
     lib.sht_workspace_bytes.argtypes = [i, i, i, i, i]
     lib.sht_workspace_bytes.restype = sz
     lib.sht_plan_warmup.argtypes = [i, i, i, i, vp]

@@ -400,6 +400,19 @@ int sht_forward_triangular(int L, int spin, int batch, int sampling, int precisi
     return SHT_OK;
 }
 
+int sht_spin_pair(int L, int spin, int batch, int precision, const void *flm_s, void *flm_ms, void *stream) {
+    int rc = check_args(L, spin, batch, SHT_SAMPLING_MW, precision);
+    if (rc != SHT_OK) return rc;
+    if (!flm_s || !flm_ms) return SHT_ERR_INVALID_ARG;
+    if (flm_s == flm_ms) return SHT_ERR_INVALID_ARG;
+    const size_t ca = 2 * elem_bytes(precision);
+    if (misaligned(flm_s, ca) || misaligned(flm_ms, ca)) return SHT_ERR_ALIGNMENT;
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == SHT_FP64) SHT_HIP(launch_spin_pair<double>(L, spin, batch, flm_s, flm_ms, st), "spin pair");
+    else SHT_HIP(launch_spin_pair<float>(L, spin, batch, flm_s, flm_ms, st), "spin pair");
+    return SHT_OK;
+}
+
 int sht_plan_tables(int L, int spin, int precision, int enable, void *stream) {
     int rc = check_args(L, spin, 1, SHT_SAMPLING_MW, precision);
     if (rc != SHT_OK) return rc;

@@ -123,7 +123,43 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, const T
     }
 }
 
+// Spin pairs (Section 3.3): for f_{-s} = conj(f_s),
+//   {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m}).
+template <typename T>
+__global__ void k_spin_pair(int L, int s, size_t total, const typename CT<T>::type *__restrict__ in,
+                            typename CT<T>::type *__restrict__ out) {
+    using C = typename CT<T>::type;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const size_t per = (size_t)L * L;
+    const size_t b = i / per;
+    const int idx = (int)(i % per);
+    int l = (int)sqrt((double)idx);
+    while (l * l > idx) --l;
+    while ((l + 1) * (l + 1) <= idx) ++l;
+    const int m = idx - l * l - l;
+    const int as = s < 0 ? -s : s;
+    C v{T(0), T(0)};
+    if (l >= as) {
+        const C x = in[b * per + (size_t)(l * l + l - m)];
+        const T sg = ((s + m) & 1) ? T(-1) : T(1);
+        v = C{sg * x.x, -sg * x.y};
+    }
+    out[i] = v;
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_spin_pair(int L, int s, int B, const void *in, void *out, hipStream_t st) {
+    const size_t total = (size_t)B * L * L;
+    hipLaunchKernelGGL(k_spin_pair<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, L, s, total,
+                       (const typename CT<T>::type *)in, (typename CT<T>::type *)out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_spin_pair<double>(int, int, int, const void *, void *, hipStream_t);
+template hipError_t launch_spin_pair<float>(int, int, int, const void *, void *, hipStream_t);
 
 template <typename T>
 hipError_t launch_layout_in(int L, int s, int B, bool half, const void *flm, T *P, hipStream_t st) {

@@ -113,6 +113,10 @@ hipError_t launch_layout_in(int L, int s, int B, bool half, const void *flm, T *
 template <typename T>
 hipError_t launch_layout_out(int L, int s, int B, bool half, const T *R, void *flm, hipStream_t st);
 
+// {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m}) for spin pairs f_{-s} = conj(f_s)
+template <typename T>
+hipError_t launch_spin_pair(int L, int s, int B, const void *in, void *out, hipStream_t st);
+
 // fft.hip: row transforms
 template <typename T>
 hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, bool half, const T *R, void *G, hipStream_t st);

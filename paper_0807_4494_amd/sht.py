@@ -142,6 +142,21 @@ def forward_real(fmap: torch.Tensor, L: int, precision="fp64", out: Optional[tor
     return out[0] if single else out
 
 
+def spin_pair(flm_s: torch.Tensor, L: int, spin: int, precision="fp64",
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Coefficients of the spin -s field f_{-s} = conj(f_s) from those of f_s."""
+    p = _prec(precision)
+    single = flm_s.dim() == 1
+    f = (flm_s.reshape(1, -1) if single else flm_s).to(io_dtype(p)).contiguous()
+    if f.shape[-1] != L * L or not f.is_cuda:
+        raise ValueError("flm_s must be a GPU tensor [batch, L*L]")
+    if out is None:
+        out = torch.empty_like(f)
+    N.check(N.load().sht_spin_pair(L, spin, f.shape[0], p, f.data_ptr(), out.data_ptr(),
+                                   _stream_handle(f.device)), "sht_spin_pair")
+    return out[0] if single else out
+
+
 def forward_triangular(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch.Tensor] = None,
                        workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The paper's own forward transform (per-order triangular systems), FP64,

@@ -73,6 +73,11 @@ def test_argument_checks_run_before_any_hip_call():
         N.SHT_ERR_ALIGNMENT
     assert lib.sht_forward_real(0, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
     assert lib.sht_forward_real(8, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
+    # spin pairs: distinct, aligned buffers
+    assert lib.sht_spin_pair(8, 2, 1, 0, fake, fake, None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_spin_pair(8, 2, 1, 0, ctypes.c_void_p((1 << 20) + 8), ctypes.c_void_p(1 << 21), None) == \
+        N.SHT_ERR_ALIGNMENT
+    assert lib.sht_spin_pair(8, 9, 1, 0, fake, ctypes.c_void_p(1 << 21), None) == N.SHT_ERR_INVALID_ARG
     # the triangular forward: FP64 only, L <= SHT_TRI_L_MAX
     tri = lib.sht_forward_triangular
     assert tri(8, 0, 1, 0, 1, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED

@@ -238,3 +238,19 @@ def test_real_signal_path_matches_oracle(L, B, prec):
     ref_f = oracle.forward_batch(raw.astype(np.complex128), L, 0)
     got_f = sht.forward_real(torch.from_numpy(raw).to(_dev()), L, prec).cpu().numpy()
     assert rel(ref_f, got_f) < TOL[prec], rel(ref_f, got_f)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("L,s,B", [(8, 2, 1), (33, -1, 2), (100, 2, 3)])
+def test_spin_pair_coefficients(L, s, B, prec):
+    """One transform serves a conjugate spin pair (Section 3.3)."""
+    sht = _sht()
+    flm = np.stack([sht_synth.gaussian_flm(L, s, 1200 + L + b) for b in range(B)])
+    fmap = oracle.inverse_batch(flm, L, s)
+    ref = oracle.forward_batch(np.conj(fmap), L, -s)
+    got = sht.spin_pair(to_dev(flm, prec), L, s, prec).cpu().numpy()
+    assert rel(ref, got) < TOL[prec]
+    # and through the transforms: the spin -s forward of the conjugate map
+    fm = sht.inverse(to_dev(flm, prec), L, s, prec)
+    g2 = sht.forward(torch.conj(fm).resolve_conj().contiguous(), L, -s, prec).cpu().numpy()
+    assert rel(ref, g2) < TOL[prec]

@@ -238,3 +238,16 @@ def test_imaginary_weights_cancel_in_the_forward(monkeypatch, s):
 
     monkeypatch.setattr(T, "quadrature_weight", w_real)
     assert oracle.rel_l2(f, T.forward(fmap, L, s)) < 1e-13
+
+
+@pytest.mark.parametrize("L,s", [(6, 1), (8, 2), (9, -3)])
+def test_spin_pair_relation(L, s):
+    """Section 3.3: for f_{-s} = conj(f_s), {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m})."""
+    f = sht_synth.gaussian_flm(L, s, 31 + L)
+    fmap = oracle.inverse(f, L, s)
+    g = oracle.forward(np.conj(fmap), L, -s)
+    want = np.zeros_like(f)
+    for l in range(abs(s), L):
+        for m in range(-l, l + 1):
+            want[l * l + l + m] = (-1) ** (s + m) * np.conj(f[l * l + l - m])
+    assert oracle.rel_l2(want, g) < 1e-12
