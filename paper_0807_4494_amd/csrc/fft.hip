@@ -144,9 +144,29 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
         if (j < nb) {
             const int k = j & ((1 << logNs) - 1);
             if constexpr (LOGNS > 0) {
-                const C *w = ptw + k * R;  // w^{r k}, r < R, contiguous
+                // w^{r k}, r < R, contiguous in the table; for radix 16 only
+                // w^{k}, w^{2k}, w^{4k}, w^{8k} are loaded and the rest formed
+                // as products of at most four table values (the loads, not
+                // the multiplies, limit these passes)
+                const C *w = ptw + k * R;
+                if constexpr (R == 16) {
+                    C t[16];
+                    t[1] = w[1];
+                    t[2] = w[2];
+                    t[4] = w[4];
+                    t[8] = w[8];
+                    t[3] = cmul(t[1], t[2]);
+                    t[5] = cmul(t[1], t[4]);
+                    t[6] = cmul(t[2], t[4]);
+                    t[7] = cmul(t[3], t[4]);
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
+                    for (int r = 9; r < 16; ++r) t[r] = cmul(t[r - 8], t[8]);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], t[r]);
+                } else {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
+                }
             }
             dft_r<R, C, T>(v[q]);
             const int base = ((j >> logNs) << (logNs + LOGR)) + k;
