@@ -30,6 +30,14 @@ inline int row_threads(int M) { return M / 16 < 64 ? 64 : M / 16; }
 // stride-16 accesses of the Stockham passes spread over the banks.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
+// f(std::integral_constant<int, i>) for i = 0 .. n-1, unrolled at compile time.
+template <int n, int i = 0, typename F> __device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (i < n) {
+        f(std::integral_constant<int, i>{});
+        static_for<n, i + 1>(f);
+    }
+}
+
 template <typename C>
 __device__ inline C rot_ipow(C v, int k) {  // v * i^k
     switch (k & 3) {
@@ -78,10 +86,22 @@ template <typename C, typename T> __device__ inline void dft8(C *v) {
     for (int i = 0; i < 8; ++i) v[i] = o[i];
 }
 
-// 16 = 4 x 4: x[n1 + 4 n2] -> DFT4 over n2 -> W16^{n1 k1} -> DFT4 over n1 -> X[k1 + 4 k2]
-template <typename C, typename T> __device__ inline void dft16(C *v) {
+// 16 = 4 x 4: x[n1 + 4 n2] -> DFT4 over n2 -> W16^{n1 k1} -> DFT4 over n1 -> X[k1 + 4 k2].
+// HIN: the inputs x[8..15] are zero (the first DFT4s see two zero inputs).
+// HOUT: only X[0..7] are wanted (the last DFT4s form two outputs each).
+template <typename C, typename T, bool HIN = false, bool HOUT = false> __device__ inline void dft16(C *v) {
 #pragma unroll
-    for (int n1 = 0; n1 < 4; ++n1) dft4(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
+    for (int n1 = 0; n1 < 4; ++n1) {
+        if constexpr (HIN) {
+            const C a = v[n1], b = v[n1 + 4], mb = mul_mi(b);
+            v[n1] = cadd(a, b);
+            v[n1 + 4] = cadd(a, mb);
+            v[n1 + 8] = csub(a, b);
+            v[n1 + 12] = csub(a, mb);
+        } else {
+            dft4(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
+        }
+    }
     // v[n1 + 4 k1] now holds Y[n1][k1]
     const T c1 = T(0.92387953251128675612818318939679), s1 = T(0.38268343236508977172845998403040);
     const T h = T(0.70710678118654752440084436210485);
@@ -96,45 +116,127 @@ template <typename C, typename T> __device__ inline void dft16(C *v) {
     v[11] = tw(v[11], -h, h);    // W16^6
     v[15] = tw(v[15], -c1, -s1); // W16^9
 #pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C *x = v + 4 * k1;
+        if constexpr (HOUT) {
+            const C t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+            const C t2 = cadd(x[1], x[3]), t3 = mul_mi(csub(x[1], x[3]));
+            x[0] = cadd(t0, t2);
+            x[1] = cadd(t1, t3);
+        } else {
+            dft4(x[0], x[1], x[2], x[3]);
+        }
+    }
     // v[4 k1 + k2] holds X[k1 + 4 k2]; transpose to natural order
+    constexpr int K2 = HOUT ? 2 : 4;
     C o[16];
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1)
 #pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+        for (int k2 = 0; k2 < K2; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = o[i];
+    for (int i = 0; i < 4 * K2; ++i) v[i] = o[i];
 }
 
-template <int R, typename C, typename T> __device__ inline void dft_r(C *v) {
-    if constexpr (R == 2) dft2(v[0], v[1]);
-    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
-    else if constexpr (R == 8) dft8<C, T>(v);
-    else dft16<C, T>(v);
+// R-point DFT in place; HIN / HOUT as for dft16 (the smaller radices take the
+// zero inputs as they are and form every output).
+template <int R, typename C, typename T, bool HIN = false, bool HOUT = false> __device__ inline void dft_r(C *v) {
+    if constexpr (R == 16) {
+        dft16<C, T, HIN, HOUT>(v);
+    } else {
+        if constexpr (HIN) {
+#pragma unroll
+            for (int r = R / 2; r < R; ++r) v[r] = C{T(0), T(0)};
+        }
+        if constexpr (R == 2) dft2(v[0], v[1]);
+        else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+        else dft8<C, T>(v);
+    }
 }
 
 // One Stockham radix-R pass over M points, in place in LDS or from/to the
 // caller's functors.  Butterfly j < M/R reads src[j + r M/R], multiplies by
 // w^{r (j mod Ns)} with w = e^{-2 pi i / (Ns R)}, takes the R-point DFT and
-// writes dst[(j div Ns) Ns R + (j mod Ns) + r Ns].  All reads finish (barrier)
-// before any write, so src and dst may be the same LDS buffer.
-template <int R, int LOGM, int LOGNS, typename T, typename Ld, typename St>
-__device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, Ld ld, St st) {
+// writes dst[(j div Ns) Ns R + (j mod Ns) + r Ns].  Every load of the pass
+// (inputs, twiddles, and pre(k) for each output k, a per-output value the
+// store needs, such as a chirp factor) is issued before the barrier that
+// separates the reads from the writes, so that src and dst may be the same
+// LDS buffer and no load waits inside the compute phase.
+// HIN (first pass only, Ns = 1): the points from M/2 on are zero, so only
+// r < R/2 is read.  HOUT (last pass only, Ns = M/R): only the outputs below
+// M/2 are formed and handed on.
+struct NoAux {};
+struct NoPre {
+    __host__ __device__ NoAux operator()(int) const { return NoAux{}; }
+};
+
+// Reads / writes of point n at LDS slot pad(n).  For the accesses of a
+// Stockham pass, pad(b + c) = pad(b) + c + (c >> 4) for the butterfly's base
+// index b and its constant offsets c = r M/R (reads) or r Ns (writes): the
+// low four bits of b plus those of c never carry (b mod 16 is below
+// 16 - (c mod 16) for power-of-two M, R, Ns).  The pass therefore forms
+// pad(b) once and addresses every point with a constant offset.
+template <typename C> struct LdsLd {
+    C *buf;
+    __device__ C operator()(int n) const { return buf[pad(n)]; }
+};
+template <typename C> struct LdsSt {
+    C *buf;
+    __device__ void operator()(int k, C x, NoAux) const { buf[pad(k)] = x; }
+};
+template <typename F> struct IsLds : std::false_type {};
+template <typename C> struct IsLds<LdsLd<C>> : std::true_type {};
+template <typename C> struct IsLds<LdsSt<C>> : std::true_type {};
+template <int c> constexpr int padc = c + (c >> 4);
+
+template <int R, int LOGM, int LOGNS, typename T, bool HIN, bool HOUT, typename Ld, typename Pre, typename St>
+__device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, Ld ld, Pre pre, St st) {
     using C = typename CT<T>::type;
+    using A = decltype(pre(0));
     constexpr int LOGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
     constexpr int M = 1 << LOGM;
     constexpr int nb = M >> LOGR;
     constexpr int nt = (M / 16) < 64 ? 64 : (M / 16);  // threads per row
     constexpr int NP = (nb + nt - 1) / nt;               // butterflies per thread
     constexpr int logNs = LOGNS;
+    constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
+    // w^{r k}, r < R, is contiguous in the table; for radix 16 only w^{k},
+    // w^{2k}, w^{4k}, w^{8k} are loaded and the rest formed as products of
+    // at most four table values (the loads, not the multiplies, limit these
+    // passes)
+    constexpr int NW = LOGNS == 0 ? 1 : R == 16 ? 4 : R;
+    static_assert(!HIN || LOGNS == 0, "zero upper half only on the first pass");
+    static_assert(!HOUT || LOGNS + LOGR == LOGM, "half output only on the last pass");
     C v[NP][R];
+    C w[NP][NW];
+    A aux[NP][ROUT];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         const int j = threadIdx.x + q * nt;
         if (j < nb) {
+            const int k = j & ((1 << logNs) - 1);
+            const int base = ((j >> logNs) << (logNs + LOGR)) + k;
+            if constexpr (IsLds<Ld>::value) {
+                const C *p = ld.buf + pad(j);
+                static_for<RIN>([&](auto rr) { v[q][rr.value] = p[padc<rr.value * nb>]; });
+            } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = ld(j + r * nb);
+                for (int r = 0; r < RIN; ++r) v[q][r] = ld(j + r * nb);
+            }
+            if constexpr (LOGNS > 0) {
+                const C *wk = ptw + k * R;
+                if constexpr (R == 16) {
+                    w[q][0] = wk[1];
+                    w[q][1] = wk[2];
+                    w[q][2] = wk[4];
+                    w[q][3] = wk[8];
+                } else {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) w[q][r] = wk[r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < ROUT; ++r) aux[q][r] = pre(base + (r << logNs));
         }
     }
     __syncthreads();
@@ -144,17 +246,12 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
         if (j < nb) {
             const int k = j & ((1 << logNs) - 1);
             if constexpr (LOGNS > 0) {
-                // w^{r k}, r < R, contiguous in the table; for radix 16 only
-                // w^{k}, w^{2k}, w^{4k}, w^{8k} are loaded and the rest formed
-                // as products of at most four table values (the loads, not
-                // the multiplies, limit these passes)
-                const C *w = ptw + k * R;
                 if constexpr (R == 16) {
                     C t[16];
-                    t[1] = w[1];
-                    t[2] = w[2];
-                    t[4] = w[4];
-                    t[8] = w[8];
+                    t[1] = w[q][0];
+                    t[2] = w[q][1];
+                    t[4] = w[q][2];
+                    t[8] = w[q][3];
                     t[3] = cmul(t[1], t[2]);
                     t[5] = cmul(t[1], t[4]);
                     t[6] = cmul(t[2], t[4]);
@@ -165,55 +262,76 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
                     for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], t[r]);
                 } else {
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r]);
                 }
             }
-            dft_r<R, C, T>(v[q]);
+            dft_r<R, C, T, HIN, HOUT>(v[q]);
             const int base = ((j >> logNs) << (logNs + LOGR)) + k;
+            if constexpr (IsLds<St>::value) {
+                C *p = st.buf + pad(base);
+                static_for<ROUT>([&](auto rr) { p[padc<(rr.value << logNs)>] = v[q][rr.value]; });
+            } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) st(base + (r << logNs), v[q][r]);
+                for (int r = 0; r < ROUT; ++r) st(base + (r << logNs), v[q][r], aux[q][r]);
+            }
         }
     }
     __syncthreads();
 }
 
 // Forward DFT of M = 2^LOGM points: the first pass reads ld(n), the last pass
-// hands output k to st(k, X_k); intermediate passes live in buf (LDS).  The
-// first pass has radix 2^(LOGM mod 4) when LOGM is not a multiple of 4, all
-// others radix 16.
-template <int LOGM, int P, int LOGNS, typename T, typename Ld, typename St>
+// hands output k to st(k, X_k, pre(k)); intermediate passes live in buf
+// (LDS).  The first pass has radix 2^(LOGM mod 4) when LOGM is not a
+// multiple of 4, all others radix 16.  HIN: ld(n) is zero for n >= M/2 and is
+// not called there.  HOUT: st is called for k < M/2 only.
+template <int LOGM, int P, int LOGNS, typename T, bool HIN, bool HOUT, typename Ld, typename Pre, typename St>
 __device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const typename CT<T>::type *ptw, Ld ld,
-                                           St st) {
+                                           Pre pre, St st) {
     using C = typename CT<T>::type;
     constexpr int NPASS = fft_npass(LOGM);
     constexpr int LR = fft_pass_lr(LOGM, P);
     constexpr int RR = 1 << LR;
     constexpr bool FIRST = P == 0, LAST = P == NPASS - 1;
+    constexpr bool PIN = HIN && FIRST, POUT = HOUT && LAST;
     const C *tp = ptw + fft_pass_offset(LOGM, P);
-    auto lbuf = [buf](int n) { return buf[pad(n)]; };
-    auto sbuf = [buf](int k, C x) { buf[pad(k)] = x; };
-    if constexpr (FIRST && LAST) stockham_pass<RR, LOGM, LOGNS, T>(tp, ld, st);
-    else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T>(tp, ld, sbuf);
-    else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T>(tp, lbuf, st);
-    else stockham_pass<RR, LOGM, LOGNS, T>(tp, lbuf, sbuf);
-    if constexpr (!LAST) fft_passes<LOGM, P + 1, LOGNS + LR, T>(buf, ptw, ld, st);
+    const LdsLd<C> lbuf{buf};
+    const LdsSt<C> sbuf{buf};
+    if constexpr (FIRST && LAST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, ld, pre, st);
+    else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, ld, NoPre{}, sbuf);
+    else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, lbuf, pre, st);
+    else stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, lbuf, NoPre{}, sbuf);
+    if constexpr (!LAST) fft_passes<LOGM, P + 1, LOGNS + LR, T, HIN, HOUT>(buf, ptw, ld, pre, st);
 }
 
 template <int LOGM, typename T, typename Ld, typename St>
 __device__ __forceinline__ void fft_run(typename CT<T>::type *buf, const typename CT<T>::type *ptw, Ld ld, St st) {
-    fft_passes<LOGM, 0, 0, T>(buf, ptw, ld, st);
+    fft_passes<LOGM, 0, 0, T, false, false>(buf, ptw, ld, NoPre{}, st);
 }
 
 // Cyclic convolution with a plan kernel of spectrum H (natural order, 1/M
 // folded in): y = IFFT(FFT(x) H), the inverse taken as conj(FFT(conj(.))).
-// x is read through ld(n); y_k is handed to st(k, y_k).
-template <int LOGM, typename T, typename Ld, typename St>
+// x is read through ld(n) for n < M/2 (the input must vanish from M/2 on);
+// y_k is handed to st(k, y_k, pre(k)) for k < M/2, pre(k) being loaded ahead
+// of the last pass's compute phase.  Every chirp-z use satisfies both:
+// M >= 2N - 1 is even, so the N inputs and the (at most N) wanted outputs lie
+// below M/2.
+template <int LOGM, typename T, typename Ld, typename Pre, typename St>
 __device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typename CT<T>::type *H,
-                                         const typename CT<T>::type *tw, Ld ld, St st) {
+                                         const typename CT<T>::type *tw, Ld ld, Pre pre, St st) {
     using C = typename CT<T>::type;
-    fft_run<LOGM, T>(buf, tw, ld, [buf, H](int k, C x) { buf[pad(k)] = conj(cmul(x, H[k])); });
-    fft_run<LOGM, T>(buf, tw, [buf](int n) { return buf[pad(n)]; }, [&st](int k, C x) { st(k, conj(x)); });
+    using A = decltype(pre(0));
+    fft_passes<LOGM, 0, 0, T, true, false>(
+        buf, tw, ld, [H](int k) { return H[k]; },
+        [buf](int k, C x, C hk) { buf[pad(k)] = conj(cmul(x, hk)); });
+    fft_passes<LOGM, 0, 0, T, false, true>(
+        buf, tw, LdsLd<C>{buf}, pre,
+        [&st](int k, C x, A a) { st(k, conj(x), a); });
 }
+
+// Clamped load p[min(n, N-1)]: the chirp-z functors read unconditionally and
+// select zero afterwards, so that the loads of a pass issue together instead
+// of one branch (and one wait) per point.
+template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N) { return p[n < N ? n : N - 1]; }
 
 // ---------------------------------------------------------------- kernels --
 
@@ -269,16 +387,17 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     };
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
-        if (n >= N) return C{T(0), T(0)};
-        C F = coef(ra, n);
-        if (two) F = cadd(F, coef(rb, n));
-        return cmul(F, cha[n]);
+        const int nc = n < N ? n : N - 1;
+        const C Fa = coef(ra, nc), Fb = coef(rb, nc), c = cha[nc];
+        const C x = cmul(two ? cadd(Fa, Fb) : Fa, c);
+        return n < N ? x : C{T(0), T(0)};
     };
     // Z(theta_t), t < N, lands in LDS
-    auto st = [&](int t, C y) {
-        if (t < N) buf[pad(t)] = cmul(y, chb[t]);
+    auto pre = [&](int t) { return ldc(chb, t, N); };
+    auto st = [&](int t, C y, C c) {
+        if (t < N) buf[pad(t)] = cmul(y, c);
     };
-    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, pre, st);
     C *Ga = G + ((size_t)b * (HALF ? L : N) + (HALF ? mua : mua + h)) * L;
     C *Gb = Ga + L;
     const T sa = ra.odd ? T(-0.5) : T(0.5);
@@ -303,13 +422,14 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft,
     C *out = map + row * N;
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
-        if (n >= N) return C{T(0), T(0)};
-        return cmul(in[n], cha[n]);
+        const C x = cmul(ldc(in, n, N), ldc(cha, n, N));
+        return n < N ? x : C{T(0), T(0)};
     };
-    auto st = [&](int p, C y) {
-        if (p < N) out[p] = cmul(y, chb[p]);
+    auto pre = [&](int p) { return ldc(chb, p, N); };
+    auto st = [&](int p, C y, C c) {
+        if (p < N) out[p] = cmul(y, c);
     };
-    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, pre, st);
 }
 
 // Forward phi stage.  Row (b, t): Q_mu(t) = N^-1 sum_p f(theta_t, phi_p) e^{-i mu phi_p}.
@@ -327,16 +447,17 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
-        if (n >= N) return C{T(0), T(0)};
-        return cmulc(in[n], chb[n]);
+        const C x = cmulc(ldc(in, n, N), ldc(chb, n, N));
+        return n < N ? x : C{T(0), T(0)};
     };
-    auto st = [&](int k, C y) {
+    auto pre = [&](int k) { return ldc(cha, k, N); };
+    auto st = [&](int k, C y, C c) {
         if (k < N) {
-            const C z = cmulc(y, cha[k]);
+            const C z = cmulc(y, c);
             out[k] = C{z.x * invN, z.y * invN};
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st);
 }
 
 // Forward theta stage, two rows per block.  Row (b, mu) of Q'[b][mu][t] (the
@@ -375,34 +496,32 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     const bool two = mua < h;
     const int oddA = parity((long long)mua + s);
     const C *Qa = Q + ((size_t)b * (HALF ? L : N) + (HALF ? mua : mua + h)) * L;  // rows over t < L
-    const C *Qb = Qa + L;
+    const C *Qb = two ? Qa + L : Qa;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
-    // extension of one row; the theta = pi sample (t = L-1) of an odd row is left out
+    // extension of one row at n < N; the theta = pi sample (t = L-1) of an
+    // odd row is left out
     auto ext = [&](const C *Qr, int odd, int n) -> C {
-        if (n < L) return (odd && n == h) ? C{T(0), T(0)} : Qr[n];
-        const C x = Qr[2 * L - 2 - n];
-        return odd ? C{-x.x, -x.y} : x;
+        const C x = Qr[n < L ? n : 2 * L - 2 - n];
+        if (odd && n == h) return C{T(0), T(0)};
+        return (odd && n >= L) ? C{-x.x, -x.y} : x;
     };
     auto ld = [&](int n) -> C {
-        if (n >= N) return C{T(0), T(0)};
-        C x = ext(Qa, oddA, n);
-        if (two) x = cadd(x, ext(Qb, !oddA, n));
-        return cmulc(x, chb[n]);
+        const int nc = n < N ? n : N - 1;
+        const C xa = ext(Qa, oddA, nc), xb = ext(Qb, !oddA, nc), c = chb[nc];
+        const C x = cmulc(two ? cadd(xa, xb) : xa, c);
+        return n < N ? x : C{T(0), T(0)};
     };
-    // the theta DFT lands in LDS (zero beyond N) as the input of the correlation
-    auto st_mid = [&](int k, C y) {
-        C z{T(0), T(0)};
-        if (k < N) {
-            z = cmulc(y, cha[k]);
-            z = C{z.x * invN, z.y * invN};
-        }
-        buf[pad(k)] = z;
+    // the theta DFT lands in LDS (zero from N to M/2) as the input of the correlation
+    auto pre = [&](int k) { return ldc(cha, k, N); };
+    auto st_mid = [&](int k, C y, C c) {
+        const C z = cmulc(y, c);
+        buf[pad(k)] = k < N ? C{z.x * invN, z.y * invN} : C{T(0), T(0)};
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st_mid);
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st_mid);
     // Y(m') at buf[m' + h], |m'| <= h
-    convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, [buf](int n) { return buf[pad(n)]; },
-                      [buf, N](int k, C y) { if (k < N) buf[pad(k)] = y; });
+    convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, LdsLd<C>{buf}, NoPre{},
+                      [buf, N](int k, C y, NoAux) { if (k < N) buf[pad(k)] = y; });
     const int Cn = (HALF ? 2 : 4) * B;
     const T twopi = T(6.283185307179586476925286766559);
     const T pi2 = T(9.8696044010893586188344909998762);
@@ -447,27 +566,31 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft
     const int L = ft.L, N = ft.N, h = L - 1;
     const size_t r0 = 2 * (size_t)blockIdx.x;
     const bool two = r0 + 1 < (size_t)rows;
-    const C *ina = G + r0 * L, *inb = ina + L;
+    const C *ina = G + r0 * L, *inb = two ? ina + L : ina;
     T *outa = map + r0 * N, *outb = outa + N;
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
-        if (n >= N) return C{T(0), T(0)};
-        const int mu = n - h, am = mu < 0 ? -mu : mu;
-        C a = ina[am], b = two ? inb[am] : C{T(0), T(0)};
+        const int nc = n < N ? n : N - 1;
+        const int mu = nc - h, am = mu < 0 ? -mu : mu;
+        C a = ina[am], b = inb[am];
+        const C c = cha[nc];
+        if (!two) b = C{T(0), T(0)};
         if (mu < 0) {
             a = conj(a);
             b = conj(b);
         }
-        return cmul(C{a.x - b.y, a.y + b.x}, cha[n]);  // a + i b
+        const C x = cmul(C{a.x - b.y, a.y + b.x}, c);  // a + i b
+        return n < N ? x : C{T(0), T(0)};
     };
-    auto st = [&](int p, C y) {
+    auto pre = [&](int p) { return ldc(chb, p, N); };
+    auto st = [&](int p, C y, C c) {
         if (p < N) {
-            const C z = cmul(y, chb[p]);
+            const C z = cmul(y, c);
             outa[p] = z.x;
             if (two) outb[p] = z.y;
         }
     };
-    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, pre, st);
 }
 
 // Forward phi stage of two real rings r, r+1 at once, keeping the orders
@@ -484,22 +607,25 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft
     const int L = ft.L, N = ft.N, h = L - 1;
     const size_t r0 = 2 * (size_t)blockIdx.x;
     const bool two = r0 + 1 < (size_t)rows;
-    const T *ina = map + r0 * N, *inb = ina + N;
+    const T *ina = map + r0 * N, *inb = two ? ina + N : ina;
     C *outa = Q + r0 * L, *outb = outa + L;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
-        if (n >= N) return C{T(0), T(0)};
-        return cmulc(C{ina[n], two ? inb[n] : T(0)}, chb[n]);
+        const int nc = n < N ? n : N - 1;
+        const T a = ina[nc], b = inb[nc];
+        const C x = cmulc(C{a, two ? b : T(0)}, chb[nc]);
+        return n < N ? x : C{T(0), T(0)};
     };
     // Z_{k-h}, k < N, lands in LDS
-    auto st = [&](int k, C y) {
+    auto pre = [&](int k) { return ldc(cha, k, N); };
+    auto st = [&](int k, C y, C c) {
         if (k < N) {
-            const C z = cmulc(y, cha[k]);
+            const C z = cmulc(y, c);
             buf[pad(k)] = C{z.x * invN, z.y * invN};
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st);
     for (int m = threadIdx.x; m < L; m += blockDim.x) {
         const C zp = buf[pad(h + m)], zm = buf[pad(h - m)];
         outa[m] = C{T(0.5) * (zp.x + zm.x), T(0.5) * (zp.y - zm.y)};
@@ -528,23 +654,20 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_dft(FftTables<T> ft, i
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
-        if (n >= N) return C{T(0), T(0)};
-        C x;
-        if (n < L) {
-            x = Qr[n];
-        } else {
-            x = Qr[2 * L - 2 - n];
-            if (odd) x = C{-x.x, -x.y};
-        }
-        return cmulc(x, chb[n]);
+        const int nc = n < N ? n : N - 1;
+        C x = Qr[nc < L ? nc : 2 * L - 2 - nc];
+        if (odd && nc >= L) x = C{-x.x, -x.y};
+        const C y = cmulc(x, chb[nc]);
+        return n < N ? y : C{T(0), T(0)};
     };
-    auto st = [&](int k, C y) {
+    auto pre = [&](int k) { return ldc(cha, k, N); };
+    auto st = [&](int k, C y, C c) {
         if (k >= h && k < N) {
-            const C z = cmulc(y, cha[k]);
+            const C z = cmulc(y, c);
             Fr[k - h] = C{z.x * invN, z.y * invN};
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, st);
+    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st);
 }
 
 // out[b][c][r] = in[b][r][c], 32 x 32 tiles through LDS.
@@ -577,7 +700,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_fft_rows(FftTables<T> ft, ty
     C *buf = reinterpret_cast<C *>(smem_raw);
     C *row = data + (size_t)blockIdx.x * ft.M;
     fft_run<LOGM, T>(buf, ft.ptw, [row](int n) { return row[n]; },
-                     [row, scale](int k, C x) { row[k] = C{x.x * scale, x.y * scale}; });
+                     [row, scale](int k, C x, NoAux) { row[k] = C{x.x * scale, x.y * scale}; });
 }
 
 template <typename T> size_t lds_bytes(const FftTables<T> &ft) {
