@@ -157,6 +157,8 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     if (hipMalloc(&p->rec.ri, (size_t)L * L * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->rec.rf, (size_t)L * L * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->rec.fab, (size_t)L * L * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->rec.jti, (size_t)L * L * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->rec.jtf, (size_t)L * L * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->rec.cl, (size_t)L * sizeof(double)) != hipSuccess) {
         delete p;
         return SHT_ERR_OOM;
@@ -473,6 +475,8 @@ int sht_release_all(void) {
         if (hipFree(kv.second->rec.ri) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.rf) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.fab) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.jti) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.jtf) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.cl) != hipSuccess) rc = SHT_ERR_HIP;
         for (int md = 0; md < 2; ++md)
             for (int c = 0; c < 2; ++c)

@@ -110,7 +110,7 @@ template <typename T> struct Args {
     const T *X;           // [L][C][L]
     T *Y;                 // [L][C][L]
     EdgeTable E;
-    const double *rtab;   // [L][L] recursion rsqrt at [k][j] (ri or rf)
+    const double2 *jtab;  // [L][L] j-side step factors at [k][j] (jti or jtf)
     const T *wtab;        // [L][L] spin factor at [k][j] (wi or wf)
     const double2 *fab;   // [L][L] order-side l-recursion factors
     const double *cl;     // [L] sqrt((2l+1)/4pi)
@@ -233,12 +233,10 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         // (FP32 / BF16x3: the producers issue ahead of the matrix-core waves)
         if constexpr (P != kP64) __builtin_amdgcn_s_setprio(2);
         const int ptid = tid - NC;
-        // sub (the order rows of this thread) is uniform across a wave, which
-        // lets the order-side recursion factors come in through scalar loads
+        // sub (the order rows of this thread) is uniform across a wave
         const int jl = ptid % TJ, sub = __builtin_amdgcn_readfirstlane(ptid / TJ);
         const int j = j0 + jl;
         const bool jvalid = j < L;
-        const double jd = (double)j;
         Chain ch[NCH];
         int l0[NCH];
         double sv[NCH], twom[NCH];
@@ -259,53 +257,53 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             l0[g] = !vch[g] ? -2 : (MODE == kInverse ? (j > m ? j : m) : j);
             twom[g] = 2.0 * m;
         }
-        double q = 0.0;      // inverse: sqrt(l^2 - j^2) at the current l
         double gprev = 0.0;  // forward: sqrt((l+m'+1)(l-m')) of the previous m'
-        if (MODE == kInverse) {
 #pragma unroll
-            for (int g = 0; g < NCH; ++g)
-                if (l0[g] == kfirst) ch[g].d = sv[g];
-            const double Y = (double)kfirst * kfirst - jd * jd;
-            q = Y > 0.0 ? sqrt(Y) : 0.0;
-        } else {
-#pragma unroll
-            for (int g = 0; g < NCH; ++g)
-                if (l0[g] == kfirst) ch[g].d = sv[g];
-        }
+        for (int g = 0; g < NCH; ++g)
+            if (l0[g] == kfirst) ch[g].d = sv[g];
 
-        // per-step recursion rsqrt and spin factor sqrt((2l+1)/4pi) d^l_{.,-s}
-        // for this j, one slab ahead: rr/wr hold slab `chunk`, rn/wn are
-        // loaded for `chunk + 1` (the spin factor is held in the output
-        // precision: it multiplies a value rounded to T on emission anyway)
-        const double *rtab = a.rtab + (jvalid ? j : 0);
-        const T *wtab = a.wtab + (jvalid ? j : 0);
-        double rr[TK], rn[TK];
-        T wr[TK], wn[TK];
-        auto load_steps = [&](int chunk, double *dr, T *dw) {
-            const int kbase = kbase_of(chunk);
-#pragma unroll
-            for (int kk = 0; kk < TK; ++kk) {
-                const int k = kbase + kk;
-                const bool ok = jvalid && chunk < nchunks && k >= 0 && k < L;
-                dr[kk] = ok ? rtab[k * L] : 0.0;
-                dw[kk] = ok ? wtab[k * L] : T(0);
+        // j-side step factors (plan table: (ap, bp) of the l-recursion for the
+        // inverse, (y, g) of the m'-recursion for the forward) and the spin
+        // factor sqrt((2l+1)/4pi) d^l_{.,-s}, PD steps ahead: set kk % PD
+        // holds step kk of the slab until it is consumed and is then refilled
+        // with step kk + PD (in this slab or the next), so no register copies.
+        // Rows outside [0, L) are clamped; they only reach steps whose chains
+        // are zero or whose emissions meet zero rows of X.  (The spin factor
+        // is held in the output precision: it multiplies a value rounded to T
+        // on emission anyway.)
+        constexpr int PD = TK / 2;
+        const unsigned jo = (unsigned)(jvalid ? j : 0);
+        double2 tj[PD];
+        T wj[PD];
+        auto load_step = [&](int chunk, int kk, double2 &t, T &w) {
+            if (kk >= TK) {
+                ++chunk;
+                kk -= TK;
+            } else if (kk < 0) {
+                ++chunk;
+                kk += TK;
+            }
+            int k = kbase_of(chunk) + kk;
+            k = k < 0 ? 0 : (k > L - 1 ? L - 1 : k);
+            t = (a.jtab + (size_t)k * L)[jo];
+            w = (a.wtab + (size_t)k * L)[jo];
+        };
+        // order-side factors of the l-recursion (inverse), staged through LDS
+        // one slab ahead: loaded at the start of a slab, stored at its end
+        double2 fnext = make_double2(0.0, 0.0);
+        const int fgi = ptid / TK, fkk = ptid % TK;
+        auto fetch_factors = [&](int chunk) {
+            if (MODE == kInverse && ptid < GM * TK) {
+                const int l = kbase_of(chunk) + fkk, idx = m0 + fgi;
+                const bool ok = chunk < nchunks && l < L && idx < L;
+                fnext = a.fab[ok ? (size_t)idx * L + l : 0];
+                if (!ok) fnext = make_double2(0.0, 0.0);
             }
         };
-        // order-side factors of the l-recursion for one slab (inverse, FP64:
-        // staged through LDS; the FP32 paths read them with scalar loads)
-        auto fill_factors = [&](int chunk, int buf) {
-            if (P == kP64 && MODE == kInverse && ptid < GM * TK && chunk < nchunks) {
-                const int gi = ptid / TK, kk = ptid % TK;
-                const int l = kbase_of(chunk) + kk;
-                const int idx = m0 + gi;
-                double am = 0.0, bm = 0.0;
-                if (l < L && idx < L) {
-                    const double2 f = a.fab[idx * L + l];
-                    am = f.x;
-                    bm = f.y;
-                }
-                fam[buf][gi][kk] = am;
-                fbm[buf][gi][kk] = bm;
+        auto store_factors = [&](int buf) {
+            if (MODE == kInverse && ptid < GM * TK) {
+                fam[buf][fgi][fkk] = fnext.x;
+                fbm[buf][fgi][fkk] = fnext.y;
             }
         };
         // one entry of M, rounded to the MFMA precision, into LDS
@@ -329,101 +327,115 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                 c.es = emit_scale(c.k);
             }
         };
-        // one slab; INJ = some lane of the wave reaches a chain edge in it
-        auto steps = [&](int chunk, int buf, auto inj_tag) {
-            constexpr bool INJ = decltype(inj_tag)::value;
+        // one slab.  INJ: some lane of the wave reaches a chain edge in it.
+        // ES1: every chain of the wave is at scale level 0 (emission needs no
+        // unscaling).
+        auto steps = [&](int chunk, int buf, auto inj_tag, auto es_tag) {
+            constexpr bool INJ = decltype(inj_tag)::value, ES1 = decltype(es_tag)::value;
             const int kbase = kbase_of(chunk);
             if (MODE == kInverse) {
-                double Xl = (double)(kbase + 1) * (kbase + 1) - jd * jd;
+                // order-side factors of step kk are read from LDS during step
+                // kk-1; a scheduling barrier closes every step, so the reads
+                // neither wait inside their own step nor all move to the slab
+                // start (which needs more registers than the wave has)
+                double fa[NCH], fb[NCH];
+#pragma unroll
+                for (int g = 0; g < NCH; ++g) {
+                    fa[g] = fam[buf][sub * NCH + g][0];
+                    fb[g] = fbm[buf][sub * NCH + g][0];
+                }
 #pragma unroll
                 for (int kk = 0; kk < TK; ++kk) {
                     const int l = kbase + kk;
-                    const T W = wr[kk];
-#pragma unroll
-                    for (int g = 0; g < NCH; ++g)
-                        emit(buf, sub * NCH + g, kk, ch[g].d * ch[g].es, W);
-                    // step l -> l+1
-                    const double r = rr[kk];
-                    const double ap = jd * r, bp = q * r;
-                    q = Xl * r;
-                    Xl += 2.0 * l + 3.0;
+                    const double2 t = tj[kk % PD];
+                    const T W = wj[kk % PD];
+                    double am[NCH], bm[NCH];
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
-                        const int gi = sub * NCH + g;
-                        double am, bm;
-                        if constexpr (P == kP64) {
-                            am = fam[buf][gi][kk];
-                            bm = fbm[buf][gi][kk];
-                        } else {
-                            const double2 f = a.fab[(size_t)(m0 + gi) * L + l];
-                            am = f.x;
-                            bm = f.y;
+                        am[g] = fa[g];
+                        bm[g] = fb[g];
+                        if (kk + 1 < TK) {
+                            fa[g] = fam[buf][sub * NCH + g][kk + 1];
+                            fb[g] = fbm[buf][sub * NCH + g][kk + 1];
                         }
-                        double dn = -(ap * am * ch[g].d + bp * bm * ch[g].dp);
+                    }
+                    load_step(chunk, kk + PD, tj[kk % PD], wj[kk % PD]);
+#pragma unroll
+                    for (int g = 0; g < NCH; ++g)
+                        emit(buf, sub * NCH + g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
+                    // step l -> l+1
+#pragma unroll
+                    for (int g = 0; g < NCH; ++g) {
+                        double dn = -(t.x * am[g] * ch[g].d + t.y * bm[g] * ch[g].dp);
                         if constexpr (INJ) dn += (l + 1 == l0[g]) ? sv[g] : 0.0;
                         ch[g].dp = ch[g].d;
                         ch[g].d = dn;
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
 #pragma unroll
                 for (int kk = TK - 1; kk >= 0; --kk) {
                     const int k = kbase + kk;  // m'
-                    const T W = wr[kk];
+                    const double2 t = tj[kk % PD];
+                    const T W = wj[kk % PD];
+                    load_step(chunk, kk - PD, tj[kk % PD], wj[kk % PD]);
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        emit(buf, sub * NCH + g, kk, ch[g].d * ch[g].es, W);
+                        emit(buf, sub * NCH + g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
                     // step m' -> m'-1
-                    const double y = rr[kk];
-                    const double gcur = (double)(j + k) * (double)(j - k + 1) * y;
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
-                        double dn = (twom[g] * ch[g].d - gprev * ch[g].dp) * y;
+                        double dn = (twom[g] * ch[g].d - gprev * ch[g].dp) * t.x;
                         if constexpr (INJ) dn += (k - 1 == l0[g]) ? sv[g] : 0.0;
                         ch[g].dp = ch[g].d;
                         ch[g].d = dn;
                     }
-                    gprev = gcur;
+                    gprev = t.y;
                 }
             }
         };
         auto generate = [&](int chunk, int buf) {
             const int kbase = kbase_of(chunk);
-            load_steps(chunk + 1, rn, wn);
+            fetch_factors(chunk + 1);
             // edges reached in this slab: inverse l+1 in (kbase, kbase+TK],
             // forward m'-1 in [kbase-1, kbase+TK-2]
-            bool mine = false;
+            bool mine = false, lvl0 = true;
 #pragma unroll
             for (int g = 0; g < NCH; ++g) {
                 const int e = l0[g];
                 mine |= MODE == kInverse ? (e > kbase && e <= kbase + TK) : (e >= kbase - 1 && e <= kbase + TK - 2);
+                lvl0 = lvl0 && ch[g].k == 0;
             }
-            if (__any(mine)) steps(chunk, buf, std::true_type{});
-            else steps(chunk, buf, std::false_type{});
+            const bool inj = __any(mine), es1 = __all(lvl0);
+            if (inj) {
+                if (es1) steps(chunk, buf, std::true_type{}, std::true_type{});
+                else steps(chunk, buf, std::true_type{}, std::false_type{});
+            } else {
+                if (es1) steps(chunk, buf, std::false_type{}, std::true_type{});
+                else steps(chunk, buf, std::false_type{}, std::false_type{});
+            }
 #pragma unroll
             for (int g = 0; g < NCH; ++g) renorm(ch[g]);
-#pragma unroll
-            for (int kk = 0; kk < TK; ++kk) {
-                rr[kk] = rn[kk];
-                wr[kk] = wn[kk];
-            }
+            store_factors(buf ^ 1);
         };
 
         // ---- pipeline: producers run one slab ahead of the consumers.  Each
         // role has its own loop (disjoint register live ranges); both execute
         // the same number of workgroup barriers, and every wave takes one role.
-        load_steps(0, rr, wr);
-        fill_factors(0, 0);
+        // the first PD steps of slab 0 in processing order
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+            const int kk = MODE == kInverse ? i : TK - 1 - i;
+            load_step(0, kk, tj[kk % PD], wj[kk % PD]);
+        }
+        fetch_factors(0);
+        store_factors(0);
         __syncthreads();
         generate(0, 0);
-        fill_factors(1, 1);
         __syncthreads();
         for (int chunk = 1; chunk <= nchunks; ++chunk) {
-            const int cur = chunk & 1, prev = cur ^ 1;
-            if (chunk < nchunks) {
-                generate(chunk, cur);
-                fill_factors(chunk + 1, prev);
-            }
+            if (chunk < nchunks) generate(chunk, chunk & 1);
             __syncthreads();
         }
         return;
@@ -647,7 +659,7 @@ hipError_t launch_prec(int mode, int L, int s, int C, const typename Prec<P>::T 
     a.X = X;
     a.Y = Y;
     a.E = E;
-    a.rtab = mode == kInverse ? rt.ri : rt.rf;
+    a.jtab = mode == kInverse ? rt.jti : rt.jtf;
     if constexpr (P == kP64) a.wtab = mode == kInverse ? sp.wi : sp.wf;
     else a.wtab = mode == kInverse ? sp.wi32 : sp.wf32;
     a.fab = rt.fab;

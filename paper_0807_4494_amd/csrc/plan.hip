@@ -101,7 +101,7 @@ hipError_t launch_spin_tables(const EdgeTable &E, const RecTables &rt, SpinPlan 
 // ------------------------------------------------ recursion factors ------
 // The arguments are exact integers in double precision; the reciprocal square
 // roots are taken once per L here instead of once per chain step.
-__global__ void k_rec_tables(int L, double *ri, double *rf, double2 *fab, double *cl) {
+__global__ void k_rec_tables(int L, double *ri, double *rf, double2 *fab, double *cl, double2 *jti, double2 *jtf) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)L * L) return;
     const int a = (int)(idx / L), b = (int)(idx % L);
@@ -111,13 +111,21 @@ __global__ void k_rec_tables(int L, double *ri, double *rf, double2 *fab, double
         fab[idx] = make_double2(am, bm);
         if (a == 0) cl[b] = sqrt((2.0 * b + 1.0) / (4.0 * 3.14159265358979323846));
     }
-    {   // ri[l][j], l = a, j = b
+    {   // ri[l][j], l = a, j = b, and the j-side factors of the l-recursion
+        // step l -> l+1: ap = j r, bp = sqrt(l^2 - j^2) r
         const double X = (double)(a + 1) * (a + 1) - (double)b * b;
-        ri[idx] = (b <= a) ? 1.0 / sqrt(X) : 0.0;
+        const double r = (b <= a) ? 1.0 / sqrt(X) : 0.0;
+        ri[idx] = r;
+        const double Y = (double)a * a - (double)b * b;
+        const double q = (b < a) ? Y * (1.0 / sqrt(Y)) : 0.0;
+        jti[idx] = make_double2((double)b * r, q * r);
     }
-    {   // rf[k][l], k = a, l = b
+    {   // rf[k][l], k = a, l = b, and the factors of the m'-recursion step
+        // m' = k -> k-1: y = rf[k][l], g = (l+k)(l-k+1) y
         const double X = (double)(b + a) * (double)(b - a + 1);
-        rf[idx] = (a <= b && X > 0.0) ? 1.0 / sqrt(X) : 0.0;
+        const double y = (a <= b && X > 0.0) ? 1.0 / sqrt(X) : 0.0;
+        rf[idx] = y;
+        jtf[idx] = make_double2(y, X * y);
     }
 }
 
@@ -125,7 +133,7 @@ hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st) {
     const size_t n = (size_t)L * L;
     const int th = 256;
     hipLaunchKernelGGL(k_rec_tables, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, L, rt.ri, rt.rf,
-                       rt.fab, rt.cl);
+                       rt.fab, rt.cl, rt.jti, rt.jtf);
     return hipGetLastError();
 }
 

@@ -73,6 +73,8 @@ struct RecTables {
     double *ri = nullptr;
     double *rf = nullptr;
     double2 *fab = nullptr;
+    double2 *jti = nullptr;  // [l][j]: (j r, sqrt(l^2 - j^2) r), r = ri[l][j] (l-recursion, j side)
+    double2 *jtf = nullptr;  // [k][j]: (y, (j+k)(j-k+1) y), y = rf[k][j] (m'-recursion)
     double *cl = nullptr;
     int *sched[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int nsched[2][2] = {{0, 0}, {0, 0}};
