@@ -59,6 +59,17 @@ template <> struct Mfma<double> {
     }
 };
 
+// Raw buffer loads (gfx9 resource word 3; offsets past the resource's size
+// read zero).
+constexpr int kBufWord3 = 0x00020000;
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
 // BF16 pair of an FP32 value: hi = v rounded to BF16 (nearest, ties to
 // even), lo = the remainder v - hi rounded the same way; hi + lo carries
 // about 16 significant bits.  Finite inputs only.
@@ -456,17 +467,46 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         xsl[i] = (g * CTILE + c) * (BF ? TK + 4 : TK + 1) + kk;
     }
     const T *xbase = a.X + (size_t)m0 * Cn * L;
+    bool xall = true;
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) xall = xall && xok[i];
+    xall = __all(xall);  // every (order, column) of the tile exists
+    // the group's panel rows as a buffer resource (used only when xall: then
+    // the GM rows of Cn x L entries all exist)
+    const __amdgpu_buffer_rsrc_t xrsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)xbase, (short)0, xall ? GM * Cn * L * (int)sizeof(T) : 0, kBufWord3);
+    unsigned xvo[P != kP64 ? XPT : 1];
+    if constexpr (P != kP64) {
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) xvo[i] = (unsigned)xoff[i] * (unsigned)sizeof(T);
+    }
     T xr[XPT];
     auto load_x = [&](int chunk) {
         const int kbase = kbase_of(chunk);
+        // whole slab inside the panel rows that exist (inverse: l >= m for
+        // every order of the group): plain loads from a uniform base
+        // (FP64 tiles keep the masked loads: their accumulators leave no
+        // room for the buffer offsets)
+        const bool full = P != kP64 && xall && kbase >= 0 && kbase + TK <= L && (MODE != kInverse || kbase >= m0 + GM - 1);
+        if (full) {
+            // buffer loads: the tile's panel as a resource, the lane offset
+            // (fixed for the whole K loop) and the slab offset (uniform) both
+            // added by the memory unit
+            const unsigned so = (unsigned)kbase * (unsigned)sizeof(T);
+            if constexpr (P != kP64) {
 #pragma unroll
-        for (int i = 0; i < XPT; ++i) {
-            const int e = tid + i * NC;
-            const int g = e / (CTILE * TK), kk = e % TK;
-            const int k = kbase + kk;
-            bool ok = xok[i] && k >= 0 && k < L;
-            if (MODE == kInverse) ok = ok && k >= m0 + g;
-            xr[i] = ok ? xbase[xoff[i] + kbase] : T(0);
+                for (int i = 0; i < XPT; ++i) xr[i] = buffer_load<T>(xrsrc, xvo[i], so);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < XPT; ++i) {
+                const int e = tid + i * NC;
+                const int g = e / (CTILE * TK), kk = e % TK;
+                const int k = kbase + kk;
+                bool ok = xok[i] && k >= 0 && k < L;
+                if (MODE == kInverse) ok = ok && k >= m0 + g;
+                xr[i] = ok ? xbase[xoff[i] + kbase] : T(0);
+            }
         }
     };
     auto store_x = [&](int buf) {
@@ -545,13 +585,17 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             // while the MFMAs of group idx run
             constexpr int NKS = TK / 4, NGRP = GM * NKS;
             T av[2][NCI], bv[2][NJI];
+            // this lane's fragment bases in the slab; every fragment is a
+            // constant offset from them
+            const T *xl = &sm.X[buf][0][lane & 15][lane >> 4];
+            const T *ml = &sm.M[buf][0][lane >> 4][wave * WJ + (lane & 15)];
+            constexpr int XR = TK + 1, MR = TJ + 16;
             auto ldfrag = [&](int idx, int slot) {
                 const int g = idx / NKS, ks = idx % NKS;
-                const int kr = ks * 4 + (lane >> 4);
 #pragma unroll
-                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = sm.X[buf][g][ci * 16 + (lane & 15)][kr];
+                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = xl[(g * CTILE + ci * 16) * XR + ks * 4];
 #pragma unroll
-                for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = sm.M[buf][g][kr][wave * WJ + ji * 16 + (lane & 15)];
+                for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = ml[(g * TK + ks * 4) * MR + ji * 16];
             };
             ldfrag(0, 0);
 #pragma unroll
