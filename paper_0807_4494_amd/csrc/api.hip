@@ -259,26 +259,21 @@ int run_inverse(int L, int spin, int batch, bool bf16x3, bool real, const FftTab
     T *P = (T *)w;            // region A: layout panels, later the theta-stage output
     T *R = (T *)(w + ra);     // region B: contraction output
     const int C = (real ? 2 : 4) * batch;
-    const int rows = real ? L : ft.N;  // theta rows per map
     SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st,
                    [&] { return launch_layout_in<T>(L, spin, batch, real, flm, P, st); }),
             "layout_in");
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
                    [&] { return contract<T>(kInverse, bf16x3, L, spin, C, P, R, ds, sp, rec, st); }),
             "contract inverse");
-    // theta stage writes rows g_mu(theta_t) over t (region A); the transpose
-    // makes rings over mu (region B) for the phi stage
+    // theta stage writes g_mu(theta_t) straight into the rings over mu that
+    // the phi stage reads (region A; the panels are no longer needed)
     SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
-                   [&] {
-                       hipError_t e = launch_theta_inv<T>(ft, spin, batch, real, R, (void *)P, st);
-                       if (e != hipSuccess) return e;
-                       return launch_transpose<T>(batch, rows, L, (const void *)P, (void *)R, st);
-                   }),
+                   [&] { return launch_theta_inv<T>(ft, spin, batch, real, R, (void *)P, st); }),
             "theta inverse");
     SHT_HIP(traced(SHT_STAGE_PHI_INV, st,
                    [&] {
-                       return real ? launch_phi_inv_real<T>(ft, batch, (const void *)R, (T *)map, st)
-                                   : launch_phi_inv<T>(ft, batch, (const void *)R, map, st);
+                       return real ? launch_phi_inv_real<T>(ft, batch, (const void *)P, (T *)map, st)
+                                   : launch_phi_inv<T>(ft, batch, (const void *)P, map, st);
                    }),
             "phi inverse");
     return SHT_OK;
@@ -290,23 +285,18 @@ int run_forward(int L, int spin, int batch, bool bf16x3, bool real, const FftTab
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
-    void *Q = (void *)w;          // region A: phi-stage output (rings over mu)
-    void *Qt = (void *)(w + ra);  // region B: the same as rows over t
+    void *Q = (void *)(w + ra);   // region B: phi-stage output (rings over mu)
     T *X = (T *)w;                // region A: weighted theta coefficients
     const int C = (real ? 2 : 4) * batch;
-    const int cols = real ? L : ft.N;  // orders per ring
     SHT_HIP(traced(SHT_STAGE_PHI_FWD, st,
                    [&] {
                        return real ? launch_phi_fwd_real<T>(ft, batch, (const T *)map, Q, st)
                                    : launch_phi_fwd<T>(ft, batch, map, Q, st);
                    }),
             "phi forward");
+    // the theta stage reads its two orders as columns of the rings in place
     SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
-                   [&] {
-                       hipError_t e = launch_transpose<T>(batch, L, cols, Q, Qt, st);
-                       if (e != hipSuccess) return e;
-                       return launch_theta_fwd<T>(ft, spin, batch, real, (const void *)Qt, X, st);
-                   }),
+                   [&] { return launch_theta_fwd<T>(ft, spin, batch, real, (const void *)Q, X, st); }),
             "theta forward");
     T *R = (T *)(w + ra);
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,

@@ -26,6 +26,16 @@ constexpr int kMaxRowThreads = 512;  // M / 16 threads per row, M <= 8192
 // Threads per row: each thread owns 16 of the M points in every pass.
 inline int row_threads(int M) { return M / 16 < 64 ? 64 : M / 16; }
 
+// Workgroups are dealt to the 8 XCDs round-robin; this maps workgroup i to
+// the work item it takes so that each XCD runs one contiguous range of items
+// in order (the tail n mod 8 keeps its own index).  Neighbouring items share
+// cache lines of the strided rows the theta stages read or write, and then
+// meet in one L2.
+__device__ __forceinline__ int xcd_item(int i, int n) {
+    const int per = n >> 3;
+    return i < (per << 3) ? (i & 7) * per + (i >> 3) : i;
+}
+
 // LDS slot of point i: one pad slot after every 16 points, so that the
 // stride-16 accesses of the Stockham passes spread over the banks.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
@@ -346,9 +356,10 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N)
 // sigma, so one length-N transform of their sum Z gives both:
 //   g_mu(theta_t) = (Z(theta_t) + sigma_mu Z(theta_{N-1-t})) / 2.
 // Block (b, i) takes mu = 2i - (L-1) and mu + 1 (the last block of a map
-// takes mu = L-1 alone).  Output G'[b][mu + L - 1][t] (rows; transposed for
-// the phi stage afterwards).  HALF (real spin-0 signals): only mu >= 0, from
-// the 2-column panels, pairs (2i, 2i+1), output G'[b][mu][t].
+// takes mu = L-1 alone).  Output: columns mu + L - 1 and mu + L of the rings
+// G[b][t][.] that the phi stage reads (one 16-byte or 32-byte piece per t).
+// HALF (real spin-0 signals): only mu >= 0, from the 2-column panels, pairs
+// (2i, 2i+1), rings of L orders.
 template <typename T, int LOGM, bool HALF>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B,
                                                            const T *__restrict__ R,
@@ -358,7 +369,8 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
     const int npair = HALF ? (L + 1) / 2 : L;
-    const int pair = blockIdx.x % npair, b = blockIdx.x / npair;
+    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+    const int pair = item % npair, b = item / npair;
     const int Cn = (HALF ? 2 : 4) * B;
     const T sgn_s = (s & 1) ? T(-1) : T(1);
     struct Row {
@@ -398,13 +410,15 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
         if (t < N) buf[pad(t)] = cmul(y, c);
     };
     convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, pre, st);
-    C *Ga = G + ((size_t)b * (HALF ? L : N) + (HALF ? mua : mua + h)) * L;
-    C *Gb = Ga + L;
+    // columns mu and mu+1 of the rings G[b][t][.] (row length N, or L for HALF)
+    const int rl = HALF ? L : N;
+    C *Ga = G + (size_t)b * L * rl + (HALF ? mua : mua + h);
     const T sa = ra.odd ? T(-0.5) : T(0.5);
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const C z = buf[pad(t)], zr = buf[pad(N - 1 - t)];
-        Ga[t] = C{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
-        if (two) Gb[t] = C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y};
+        C *g = Ga + (size_t)t * rl;
+        g[0] = C{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
+        if (two) g[1] = C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y};
     }
 }
 
@@ -460,8 +474,8 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
     convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st);
 }
 
-// Forward theta stage, two rows per block.  Row (b, mu) of Q'[b][mu][t] (the
-// phi-stage output transposed): parity extension of Q_mu to the torus rings
+// Forward theta stage, two orders per block.  Column mu of the phi-stage rings
+// Q[b][t][.] (read in place, stride one ring): parity extension of Q_mu to the torus rings
 // t < N (Section 3.2: Q~(t) = sigma Q(2L-2-t) for t >= L, sigma = (-1)^{mu+s}),
 // the theta DFT
 //   F_{mu m''} = N^-1 sum_t Q~_mu(t) e^{-i m'' theta_t},
@@ -480,7 +494,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
 // Written as X[|mu|][c][m'] with c = q*B + b (q = 0,1 for mu >= 0, 2,3 for
 // mu < 0), times (-1)^{m'} for mu < 0 (the d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
 // symmetry; the (-1)^l part is applied on output).
-// HALF (real spin-0 signals): only mu >= 0, rows Q'[b][mu][t], pairs
+// HALF (real spin-0 signals): only mu >= 0, rings of L orders, pairs
 // (2i, 2i+1), 2-column panels.
 template <typename T, int LOGM, bool HALF>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B,
@@ -491,18 +505,21 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
     const int npair = HALF ? (L + 1) / 2 : L;
-    const int pair = blockIdx.x % npair, b = blockIdx.x / npair;
+    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+    const int pair = item % npair, b = item / npair;
     const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
     const int oddA = parity((long long)mua + s);
-    const C *Qa = Q + ((size_t)b * (HALF ? L : N) + (HALF ? mua : mua + h)) * L;  // rows over t < L
-    const C *Qb = two ? Qa + L : Qa;
+    // columns mu and mu+1 of the rings Q[b][t][.] (row length rl), t < L
+    const int rl = HALF ? L : N;
+    const C *Qa = Q + (size_t)b * L * rl + (HALF ? mua : mua + h);
+    const C *Qb = two ? Qa + 1 : Qa;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     // extension of one row at n < N; the theta = pi sample (t = L-1) of an
     // odd row is left out
     auto ext = [&](const C *Qr, int odd, int n) -> C {
-        const C x = Qr[n < L ? n : 2 * L - 2 - n];
+        const C x = Qr[(size_t)(n < L ? n : 2 * L - 2 - n) * rl];
         if (odd && n == h) return C{T(0), T(0)};
         return (odd && n >= L) ? C{-x.x, -x.y} : x;
     };
@@ -533,7 +550,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
         // top-order term of an odd row: -2 i pi^2 (-1)^{h-1} Q(L-1) / N
         C top{T(0), T(0)};
         if (odd && h >= 1) {
-            const C q = Qr[h];
+            const C q = Qr[(size_t)h * rl];
             const T f = T(2) * pi2 * invN * ((h - 1) & 1 ? T(-1) : T(1));
             top = C{f * q.y, -f * q.x};
         }
