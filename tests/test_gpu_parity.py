@@ -44,7 +44,10 @@ def rel(ref, got):
 
 
 CASES = [(1, 0, 1), (2, 0, 1), (2, 1, 2), (3, -2, 1), (5, 1, 3), (8, 0, 2), (8, -3, 1), (16, 2, 1),
-         (32, 0, 1), (33, -1, 2), (64, 2, 1), (100, -2, 3), (129, 0, 1), (256, 2, 1), (257, -1, 2)]
+         (32, 0, 1), (33, -1, 2), (64, 2, 1), (100, -2, 3), (129, 0, 1), (256, 2, 1), (257, -1, 2),
+         # whole column tiles (4B = 16, 64, and 64 + a partial tile): the
+         # contraction's full-slab load path
+         (96, 1, 4), (160, -2, 16), (200, 0, 20)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
@@ -218,7 +221,7 @@ def _real_signal_flm(L, seed):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("L,B", [(1, 1), (2, 2), (7, 3), (33, 1), (100, 20), (257, 2)])
+@pytest.mark.parametrize("L,B", [(1, 1), (2, 2), (7, 3), (33, 1), (96, 8), (100, 20), (257, 2)])
 def test_real_signal_path_matches_oracle(L, B, prec):
     """Real spin-0 maps: only m >= 0 is transformed (Section 3.3); the result
     equals the complex transform of the same signal."""
