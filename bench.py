@@ -150,29 +150,88 @@ def cpu_baseline(wl, seconds_hint: float = 30.0) -> dict:
                       f"{dt:.1f} s; oracle round trip rel_l2 {err:.1e}"}
 
 
-def serving(n_requests: int, fractions, precision: str = "fp32", budget_gb: float = 16.0) -> dict:
+def serving(n_requests: int, fractions, precision: str = "fp32", budget_gb: float = 16.0, graphs: int = 32) -> dict:
     """The mixed serving stream: closed-loop replay for the saturation rate X,
     then open-loop Poisson arrivals at each fraction of X."""
     import sht_synth
     from paper_0807_4494_amd.serving import GpuServer
 
-    server = GpuServer(precision, streams=4, budget_bytes=int(budget_gb * (1 << 30)))
+    server = GpuServer(precision, streams=4, budget_bytes=int(budget_gb * (1 << 30)), graphs=graphs)
     base = sht_synth.trace(n_requests=n_requests)
     server.warm((r.L, r.spin) for r in base)
-    _, _, sat = server.run(base, closed_loop=True)
+    mult, pkey = MFMA_COST[precision]
+
+    def contraction_rate(results, makespan_s):
+        """Achieved contraction rate over a run (inverse + forward of every
+        request's maps) and its fraction of the MFMA peak."""
+        f = sum(2 * contraction_flops(r.L, r.spin, r.batch) for r in results)
+        t = mult * f / makespan_s / 1e12
+        return {"contraction_TFLOP_s": round(t, 2), "frac_of_mfma_peak": round(t / PEAK[pkey], 4)}
+
+    res, _, sat = server.run(base, closed_loop=True)
     x = sat["requests_per_s"]
     out = {"requests": n_requests, "precision": precision, "budget_GB": budget_gb, "streams": sat["streams"],
+           "graph_cache": graphs,
            "mix": "L log-uniform [64, 2048] step 32, spin {0, +-1, +-2}, batch 1..32, C_l = 1/(l+1)^2",
            "saturation": {"requests_per_s": round(x, 2), "transforms_per_s": round(sat["transforms_per_s"], 1),
-                          "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3)}}
+                          "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3),
+                          "graph_launches": sat["graph_launches"], "graph_captures": sat["graph_captures"],
+                          **contraction_rate(res, sat["makespan_s"])}}
     for f in fractions:
         tr = sht_synth.trace(n_requests=n_requests, rate_per_s=f * x)
-        _, _, st = server.run(tr)
+        res, _, st = server.run(tr)
         out[f"open_loop_{f:g}X"] = {"rate_per_s": round(f * x, 2), "p50_ms": round(st["p50_ms"], 3),
                                    "p99_ms": round(st["p99_ms"], 3),
                                    "transforms_per_s": round(st["transforms_per_s"], 1),
                                    "mean_group_size": round(st["mean_group_size"], 3),
-                                   "max_inflight_groups": st["max_inflight_groups"]}
+                                   "max_inflight_groups": st["max_inflight_groups"],
+                                   "graph_launches": st["graph_launches"], "graph_captures": st["graph_captures"],
+                                   **contraction_rate(res, st["makespan_s"])}
+    server.close_graphs()
+    return out
+
+
+def graph_replay(prec: str, shapes) -> dict:
+    """Eager launches against replay of the captured inverse + forward
+    (sht_graph_*) for a few shapes: ms per (inverse + forward) pair, timed
+    with events on the current stream over a fixed number of calls."""
+    import numpy as np
+    import torch
+    import paper_0807_4494_amd as sht
+    import sht_synth
+    dev = torch.device("cuda", 0)
+    out = {}
+    for L, s, B, n in shapes:
+        g = sht.Graph(L, s, B, prec, device=dev)
+        try:
+            f = np.stack([sht_synth.gaussian_flm(L, s, 6100 + b) for b in range(B)])
+            g.flm_in.copy_(torch.from_numpy(f).to(dev, sht.io_dtype(prec)))
+            m = torch.empty_like(g.map)
+            back = torch.empty_like(g.flm_out)
+            ws = torch.empty(sht.workspace_bytes(L, s, B, prec), dtype=torch.uint8, device=dev)
+
+            def eager():
+                sht.inverse(g.flm_in, L, s, prec, out=m, workspace=ws)
+                sht.forward(m, L, s, prec, out=back, workspace=ws)
+
+            res = {}
+            for name, fn in (("eager", eager), ("graph", g.launch)):
+                for _ in range(3):
+                    fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(n):
+                    fn()
+                e1.record()
+                e1.synchronize()
+                res[name] = e0.elapsed_time(e1) / n
+            torch.cuda.synchronize()
+            same = bool(torch.equal(m, g.map) and torch.equal(back, g.flm_out))
+            out[f"L{L}_s{s}_b{B}"] = {"eager_ms": round(res["eager"], 4), "graph_ms": round(res["graph"], 4),
+                                      "calls": n, "bitwise_equal": same}
+        finally:
+            g.close()
     return out
 
 
@@ -187,11 +246,15 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the eager-vs-graph-replay leg")
+    ap.add_argument("--serve-graphs", type=int, default=32,
+                    help="captured transforms the serving loop keeps (0: eager launches only)")
     ap.add_argument("--no-real", action="store_true")
     ap.add_argument("--tables", action="store_true",
                     help="also time the cached-table design (an L^3 table per spin, 4 GiB each in FP32 at L=1024)")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-rates", default="0.7", help="comma-separated fractions of the saturation rate")
+    ap.add_argument("--serve-rates", default="0.7,0.5,0.9",
+                    help="comma-separated fractions of the saturation rate (the first is the headline latency)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -363,9 +426,11 @@ def main() -> int:
             "round_trip_rel_l2": rt_t, "table_GiB_per_spin": round(L ** 3 * cbytes / 2 / 2 ** 30, 2),
             "contract_inv_ms": round(st_t["contract_inv"][0] / st_t["contract_inv"][1], 4),
             "contract_fwd_ms": round(st_t["contract_fwd"][0] / st_t["contract_fwd"][1], 4)}
+    if not args.no_graph and prec != "fp64":
+        out["graph_replay"] = graph_replay(prec, [(64, 2, 1, 200), (256, 2, 4, 50), (L, wl.spins[-1], B, 5)])
     rates = [float(f) for f in args.serve_rates.split(",") if f.strip()]
     if not args.no_serve and rates:
-        out["serving"] = serving(args.serve_requests, rates)
+        out["serving"] = serving(args.serve_requests, rates, graphs=args.serve_graphs)
         head = out["serving"][f"open_loop_{rates[0]:g}X"]
         out["latency_mixed_L"] = {"p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
                                   "rate": f"{rates[0]:g} x saturation"}

@@ -178,8 +178,35 @@ int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream);
  */
 int sht_plan_tables(int L, int spin, int precision, int enable, void *stream);
 
-/* Free every cached plan on every device.  The caller must make sure no
- * enqueued transform still uses them (e.g. synchronise first). */
+/*
+ * Captured transforms, for callers that run one shape many times (a serving
+ * loop): the inverse transform of flm_in into map followed by the forward
+ * transform of map into flm_out (both as sht_inverse / sht_forward, with the
+ * same L, spin, batch, sampling and precision), recorded once as a HIP graph
+ * and replayed by sht_graph_launch on any stream of the same device.
+ *   flm_in     in:  [batch][L*L] complex, read when the graph runs
+ *   map        out: [batch][L][2L-1] complex (the inverse's result)
+ *   flm_out    out: [batch][L*L] complex (the forward's result)
+ *   workspace  at least sht_workspace_bytes(...) bytes, used by every launch
+ * The graph binds these device buffers: they stay owned by the caller, must
+ * outlive the graph, and a launch overwrites map, flm_out and the workspace.
+ * Launches of one graph, or of graphs sharing buffers, that overlap on
+ * different streams race.  Creation builds the plan (synchronising `stream`)
+ * and records without executing anything; *out receives the handle (NULL on
+ * error).  Errors as for sht_inverse; SHT_ERR_INVALID_ARG for a NULL out or
+ * an unknown handle, or a launch on another device than the creation's.
+ * sht_release_all destroys every live graph.
+ */
+typedef struct sht_graph_s *sht_graph;
+int sht_graph_create(int L, int spin, int batch, int sampling, int precision,
+                     const void *flm_in, void *map, void *flm_out, void *workspace, size_t ws_bytes,
+                     void *stream, sht_graph *out);
+int sht_graph_launch(sht_graph graph, void *stream);
+int sht_graph_destroy(sht_graph graph);
+
+/* Free every cached plan on every device, after destroying every live graph.
+ * The caller must make sure no enqueued transform still uses them (e.g.
+ * synchronise first). */
 int sht_release_all(void);
 
 /* Static text for a status code (never NULL). */

@@ -27,7 +27,7 @@ SHT_TRI_L_MAX = 128
 #: every symbol include/sht.h declares
 EXPORTS = ("sht_inverse", "sht_forward", "sht_inverse_real", "sht_forward_real", "sht_forward_triangular",
            "sht_spin_pair", "sht_workspace_bytes", "sht_plan_warmup",
-           "sht_plan_tables",
+           "sht_plan_tables", "sht_graph_create", "sht_graph_launch", "sht_graph_destroy",
            "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error",
            "sht_trace_enable", "sht_trace_read")
 
@@ -74,6 +74,12 @@ def load() -> ctypes.CDLL:
     lib.sht_plan_warmup.restype = i
     lib.sht_plan_tables.argtypes = [i, i, i, i, vp]
     lib.sht_plan_tables.restype = i
+    lib.sht_graph_create.argtypes = [i, i, i, i, i, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.sht_graph_create.restype = i
+    lib.sht_graph_launch.argtypes = [vp, vp]
+    lib.sht_graph_launch.restype = i
+    lib.sht_graph_destroy.argtypes = [vp]
+    lib.sht_graph_destroy.restype = i
     lib.sht_release_all.argtypes = []
     lib.sht_release_all.restype = i
     lib.sht_status_string.argtypes = [i]

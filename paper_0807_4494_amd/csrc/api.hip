@@ -4,6 +4,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <tuple>
 #include <vector>
 
@@ -35,12 +36,23 @@ std::map<int, DeviceState> g_devices;
 std::map<std::tuple<int, int>, Plan *> g_plans;              // (device, L)
 std::map<std::tuple<int, int, int>, SpinPlan *> g_spin;      // (device, L, spin)
 
+// ---- captured transforms ----
+}  // namespace
+struct sht_graph_s {
+    int device;
+    hipGraphExec_t exec;
+};
+namespace {
+std::mutex g_graph_mu;
+std::set<sht_graph_s *> g_graphs;
+
 // ---- stage tracing ----
 struct TraceRec {
     int stage;
     hipEvent_t a, b;
 };
 bool g_trace_on = false;
+thread_local bool t_capturing = false;  // inside sht_graph_create's capture
 std::mutex g_trace_mu;
 std::vector<TraceRec> g_trace_pending;
 std::vector<hipEvent_t> g_event_pool;
@@ -58,7 +70,7 @@ hipEvent_t pool_event() {
 
 // Runs `launch` (returns hipError_t), bracketed by events when tracing is on.
 template <typename F> hipError_t traced(int stage, hipStream_t st, F launch) {
-    if (!g_trace_on) return launch();
+    if (!g_trace_on || t_capturing) return launch();
     hipEvent_t a, b;
     {
         std::lock_guard<std::mutex> lk(g_trace_mu);
@@ -445,7 +457,89 @@ int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) 
     return prepare(L, spin, (hipStream_t)stream, &ds, &plan, &sp);
 }
 
+int sht_graph_create(int L, int spin, int batch, int sampling, int precision, const void *flm_in, void *map,
+                     void *flm_out, void *workspace, size_t ws_bytes, void *stream, sht_graph *out) {
+    if (!out) return SHT_ERR_INVALID_ARG;
+    *out = nullptr;
+    int rc = check_args(L, spin, batch, sampling, precision);
+    if (rc != SHT_OK) return rc;
+    rc = check_buffers(L, batch, precision, flm_in, map, workspace, ws_bytes);
+    if (rc == SHT_OK) rc = check_buffers(L, batch, precision, map, flm_out, workspace, ws_bytes);
+    if (rc != SHT_OK) return rc;
+    // the plan is built (and synchronised) before the capture starts, so the
+    // captured sequence is kernel launches only
+    rc = sht_plan_warmup(L, spin, sampling, precision, stream);
+    if (rc != SHT_OK) return rc;
+    int dev = 0;
+    SHT_HIP(hipGetDevice(&dev), "graph device");
+    hipStream_t cs;
+    SHT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph capture stream");
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        t_capturing = true;
+        rc = transform(true, false, L, spin, batch, sampling, precision, flm_in, map, workspace, ws_bytes, cs);
+        if (rc == SHT_OK)
+            rc = transform(false, false, L, spin, batch, sampling, precision, map, flm_out, workspace, ws_bytes, cs);
+        t_capturing = false;
+        e = hipStreamEndCapture(cs, &g);  // always ends the capture
+        if (rc == SHT_OK && e != hipSuccess) {
+            rc = hip_fail(e, "graph end capture");
+        }
+    } else {
+        rc = hip_fail(e, "graph begin capture");
+    }
+    hipGraphExec_t ex = nullptr;
+    if (rc == SHT_OK) {
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "graph instantiate");
+        }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (rc != SHT_OK) return rc;
+    sht_graph_s *h = new sht_graph_s{dev, ex};
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        g_graphs.insert(h);
+    }
+    *out = h;
+    return SHT_OK;
+}
+
+int sht_graph_launch(sht_graph graph, void *stream) {
+    hipGraphExec_t ex;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (!graph || !g_graphs.count(graph)) return SHT_ERR_INVALID_ARG;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev != graph->device) return SHT_ERR_INVALID_ARG;
+        ex = graph->exec;
+    }
+    SHT_HIP(hipGraphLaunch(ex, (hipStream_t)stream), "graph launch");
+    return SHT_OK;
+}
+
+int sht_graph_destroy(sht_graph graph) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (!graph || !g_graphs.count(graph)) return SHT_ERR_INVALID_ARG;
+    g_graphs.erase(graph);
+    const hipError_t e = hipGraphExecDestroy(graph->exec);
+    delete graph;
+    if (e != hipSuccess) return hip_fail(e, "graph destroy");
+    return SHT_OK;
+}
+
 int sht_release_all(void) {
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (sht_graph_s *h : g_graphs) {
+            (void)hipGraphExecDestroy(h->exec);
+            delete h;
+        }
+        g_graphs.clear();
+    }
     std::lock_guard<std::mutex> lock(g_mu);
     int rc = SHT_OK;
     int cur = 0;

@@ -13,6 +13,9 @@
 // The chirps are e^{i pi k / N} with k reduced mod 2N in integer arithmetic.
 // One workgroup of M/16 threads transforms one row; each thread holds 16
 // points in registers during every pass.
+#include <mutex>
+#include <set>
+#include <tuple>
 #include <type_traits>
 
 #include "sht_internal.h"
@@ -724,10 +727,22 @@ template <typename T> size_t lds_bytes(const FftTables<T> &ft) {
     return (size_t)(ft.M + ft.M / 16) * sizeof(typename CT<T>::type);
 }
 
+// Raises a kernel's dynamic-LDS limit once per (device, kernel, size), so a
+// launch sequence after the first one (e.g. under graph capture) is kernel
+// launches only.
 template <typename K> hipError_t set_lds(K kernel, size_t bytes) {
-    if (bytes > 64 * 1024)
-        return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    return hipSuccess;
+    if (bytes <= 64 * 1024) return hipSuccess;
+    static std::mutex mu;
+    static std::set<std::tuple<int, const void *, size_t>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const auto key = std::make_tuple(dev, (const void *)kernel, bytes);
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count(key)) return hipSuccess;
+    e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done.insert(key);
+    return e;
 }
 
 }  // namespace

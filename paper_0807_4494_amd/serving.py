@@ -140,10 +140,19 @@ class GpuServer:
     admission budget.  Inputs are drawn on the device from each request's seed
     (complex Gaussian, variance C_l = 1/(l+1)^2, zero for l < |spin|) inside
     the request's own buffers when its group is admitted.
+
+    ``graphs`` > 0 keeps up to that many captured transforms (``sht.Graph``,
+    one per (L, spin, batch) shape, each at most ``graph_bytes`` of device
+    memory): a shape seen for the ``graph_after``-th time is captured (the
+    least used idle graph makes room), and later groups of a cached shape
+    replay its graph instead of launching the stages one by one, unless that
+    graph is still in flight.  Graph buffers are outside the
+    admission budget (the budget still reserves each request's own
+    footprint).
     """
 
     def __init__(self, precision: str = "fp32", streams: int = 4, budget_bytes: int = 16 << 30,
-                 device: int = 0):
+                 device: int = 0, graphs: int = 0, graph_bytes: int = 1 << 30, graph_after: int = 3):
         import torch
         from . import sht
         self.torch = torch
@@ -156,6 +165,13 @@ class GpuServer:
         self.cbytes = 16 if precision == "fp64" else 8
         self._ws_cache: Dict[Tuple[int, int, int], int] = {}
         self._scale: Dict[Tuple[int, int], "torch.Tensor"] = {}
+        self.graph_cap = graphs
+        self.graph_bytes = graph_bytes
+        self.graph_after = graph_after
+        self._graphs: "Dict[Tuple[int, int, int], list]" = {}   # shape -> [Graph, busy event or None]
+        self._seen: Dict[Tuple[int, int, int], int] = {}
+        self.graph_launches = 0
+        self.graph_captures = 0
 
     def workspace(self, L: int, spin: int, batch: int) -> int:
         key = (L, spin, batch)
@@ -188,9 +204,62 @@ class GpuServer:
         out.copy_(torch.randn(out.shape, generator=g, device=self.dev, dtype=self.cdtype))
         out.mul_(self._spectrum(req.L, req.spin))
 
+    def _graph_for(self, L: int, s: int, B: int):
+        """The cached graph of this shape if it is idle (capturing it on the
+        shape's second sighting), else None."""
+        key = (L, s, B)
+        self._seen[key] = self._seen.get(key, 0) + 1
+        ent = self._graphs.get(key)
+        if ent is not None:
+            if ent[1] is not None and not ent[1].query():
+                return None
+            return ent
+        foot = (2 * B * L * L + B * L * (2 * L - 1)) * self.cbytes + self.workspace(L, s, B)
+        if self._seen[key] < self.graph_after or foot > self.graph_bytes:
+            return None
+        if len(self._graphs) >= self.graph_cap:
+            idle = [k for k, e in self._graphs.items() if e[1] is None or e[1].query()]
+            if not idle:
+                return None
+            victim = min(idle, key=lambda k: self._seen[k])
+            if self._seen[victim] >= self._seen[key]:
+                return None
+            self._graphs.pop(victim)[0].close()
+        ent = [self.sht.Graph(L, s, B, self.precision, device=self.dev), None]
+        self._graphs[key] = ent
+        self.graph_captures += 1
+        return ent
+
+    def close_graphs(self) -> None:
+        for g, _ in self._graphs.values():
+            g.close()
+        self._graphs.clear()
+
     def _launch(self, group: Group, stream, keep: Optional[set]):
         torch = self.torch
         L, s, B = group.L, group.spin, group.batch
+        ent = self._graph_for(L, s, B) if self.graph_cap > 0 else None
+        if ent is not None:
+            g = ent[0]
+            with torch.cuda.stream(stream):
+                off = 0
+                slices = []
+                for req in group.requests:
+                    self.fill_input(req, g.flm_in[off:off + req.batch])
+                    slices.append((req, off))
+                    off += req.batch
+                g.launch(stream)
+                kept = {}
+                if keep:
+                    for req, o in slices:
+                        if req.rid in keep:
+                            sl = slice(o, o + req.batch)
+                            kept[req.rid] = (g.flm_in[sl].clone(), g.map[sl].clone(), g.flm_out[sl].clone())
+                done = torch.cuda.Event(enable_timing=True)
+                done.record(stream)
+            ent[1] = done
+            self.graph_launches += 1
+            return done, (), kept
         with torch.cuda.stream(stream):
             flm = torch.empty((B, L * L), dtype=self.cdtype, device=self.dev)
             fmap = torch.empty((B, L, 2 * L - 1), dtype=self.cdtype, device=self.dev)
@@ -224,6 +293,7 @@ class GpuServer:
         """
         torch = self.torch
         keep = set(keep or ())
+        g_launch0, g_capture0 = self.graph_launches, self.graph_captures
         reqs = sorted(requests, key=lambda r: (0.0 if closed_loop else r.arrival_s, r.rid))
         sched = Scheduler(self.budget, self.workspace, cbytes=self.cbytes)
         free = list(range(len(self.streams)))
@@ -281,5 +351,7 @@ class GpuServer:
                  "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
                  "mean_group_size": sum(r.group_size for r in results) / max(1, len(results)),
                  "peak_admitted_bytes": peak_used, "max_inflight_groups": max_inflight,
-                 "budget_bytes": self.budget, "streams": len(self.streams)}
+                 "budget_bytes": self.budget, "streams": len(self.streams),
+                 "graph_launches": self.graph_launches - g_launch0,
+                 "graph_captures": self.graph_captures - g_capture0}
         return results, kept_all, stats

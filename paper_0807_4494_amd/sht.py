@@ -194,6 +194,41 @@ def plan_tables(L: int, spin: int = 0, precision="fp32", enable: bool = True, de
             "sht_plan_tables")
 
 
+class Graph:
+    """Captured inverse + forward of one shape (``sht_graph_create``): the
+    inverse of ``flm_in`` into ``map`` and the forward of ``map`` into
+    ``flm_out``, replayed by ``launch``.  The buffers are allocated here (torch
+    device memory) and bound to the graph; write the next input into
+    ``flm_in`` before a launch, read the results after it."""
+
+    def __init__(self, L: int, spin: int, batch: int, precision="fp32", device=None):
+        import ctypes
+        self.L, self.spin, self.batch, self.p = L, spin, batch, _prec(precision)
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        dt = io_dtype(self.p)
+        self.flm_in = torch.zeros((batch, L * L), dtype=dt, device=dev)
+        self.map = torch.empty((batch, L, 2 * L - 1), dtype=dt, device=dev)
+        self.flm_out = torch.empty((batch, L * L), dtype=dt, device=dev)
+        self.workspace, nbytes = _workspace(L, spin, batch, self.p, dev, None)
+        h = ctypes.c_void_p()
+        rc = N.load().sht_graph_create(L, spin, batch, N.SHT_SAMPLING_MW, self.p, self.flm_in.data_ptr(),
+                                       self.map.data_ptr(), self.flm_out.data_ptr(),
+                                       self.workspace.data_ptr() if self.workspace is not None else None,
+                                       nbytes, _stream_handle(dev), ctypes.byref(h))
+        N.check(rc, "sht_graph_create")
+        self._h = h.value
+        self.device = dev
+
+    def launch(self, stream: Optional[torch.cuda.Stream] = None) -> None:
+        s = stream.cuda_stream if stream is not None else _stream_handle(self.device)
+        N.check(N.load().sht_graph_launch(self._h, s), "sht_graph_launch")
+
+    def close(self) -> None:
+        if self._h is not None:
+            N.check(N.load().sht_graph_destroy(self._h), "sht_graph_destroy")
+            self._h = None
+
+
 def release_all() -> None:
     N.check(N.load().sht_release_all(), "sht_release_all")
 

@@ -86,6 +86,25 @@ def test_argument_checks_run_before_any_hip_call():
     assert tri(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
 
 
+def test_graph_argument_checks_run_before_any_hip_call():
+    N, lib = _lib()
+    fake = ctypes.c_void_p(1 << 20)     # never dereferenced: checks fail first
+    out = ctypes.c_void_p(123)
+    big = 1 << 40
+    # NULL handle slot, then invalid L / precision (out is cleared first)
+    assert lib.sht_graph_create(8, 0, 1, 0, 1, fake, fake, fake, fake, big, None, None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_graph_create(0, 0, 1, 0, 1, fake, fake, fake, fake, big, None,
+                                ctypes.byref(out)) == N.SHT_ERR_INVALID_ARG
+    assert out.value is None
+    assert lib.sht_graph_create(8, 0, 1, 0, 9, fake, fake, fake, fake, big, None,
+                                ctypes.byref(out)) == N.SHT_ERR_UNSUPPORTED
+    # unknown handles
+    assert lib.sht_graph_launch(None, None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_graph_launch(fake, None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_graph_destroy(None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_graph_destroy(fake) == N.SHT_ERR_INVALID_ARG
+
+
 def test_workspace_size_formula():
     N, lib = _lib()
     for L, B, p in [(32, 1, 0), (1024, 16, 1), (2048, 4, 1), (255, 3, 0)]:

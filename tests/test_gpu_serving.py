@@ -24,15 +24,22 @@ def _rel(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_result_alone_equals_result_in_the_mix(prec):
-    server = _server(precision=prec, streams=4, budget_bytes=2 << 30)
-    reqs = sht_synth.trace(n_requests=150, rate_per_s=4000.0, L_lo=64, L_hi=320, batch_hi=6,
-                           spins=(0, 1, -1, 2, -2), seed=sht_synth.SEED_BASE + 4100)
+@pytest.mark.parametrize("prec,graphs", [("fp32", 0), ("fp64", 0), ("fp32", 8)])
+def test_result_alone_equals_result_in_the_mix(prec, graphs):
+    server = _server(precision=prec, streams=4, budget_bytes=2 << 30, graphs=graphs, graph_after=1)
+    if graphs:
+        # a narrow shape mix, so shapes repeat and the captured transforms replay
+        reqs = sht_synth.trace(n_requests=150, rate_per_s=4000.0, L_lo=64, L_hi=96, batch_hi=1,
+                               spins=(0, 2), seed=sht_synth.SEED_BASE + 4200)
+    else:
+        reqs = sht_synth.trace(n_requests=150, rate_per_s=4000.0, L_lo=64, L_hi=320, batch_hi=6,
+                               spins=(0, 1, -1, 2, -2), seed=sht_synth.SEED_BASE + 4100)
     server.warm((r.L, r.spin) for r in reqs)
     keep = [r.rid for r in reqs[::3]]           # 50 sampled requests
-    print(f"[serving mix] {len(reqs)} requests {prec}", flush=True)
+    print(f"[serving mix] {len(reqs)} requests {prec} graphs={graphs}", flush=True)
     res, kept, stats = server.run(reqs, keep=keep, closed_loop=True)
+    if graphs:
+        assert stats["graph_captures"] > 0 and stats["graph_launches"] > 0, stats
     assert stats["requests"] == len(reqs) and len({r.rid for r in res}) == len(reqs)
     # the mix really mixed: some call served several requests, several calls overlapped
     assert stats["mean_group_size"] > 1.0 and stats["max_inflight_groups"] > 1
@@ -51,3 +58,4 @@ def test_result_alone_equals_result_in_the_mix(prec):
         assert _rel(back_one, back_mix) <= tol
         assert _rel(flm_one, back_mix) <= tol                # inverse then forward returns f_lm
     print(f"[serving mix] {bitwise} of {len(keep)} sampled requests bitwise equal alone and in the mix", flush=True)
+    server.close_graphs()
