@@ -235,6 +235,47 @@ def graph_replay(prec: str, shapes) -> dict:
     return out
 
 
+def tile_autotune(prec: str, shapes) -> dict:
+    """For each shape: ms per (inverse + forward) with each contraction column
+    tile pinned, the default tile, and the autotuner's (sht_tune) pick."""
+    import numpy as np
+    import torch
+    import paper_0807_4494_amd as sht
+    import sht_synth
+    dev = torch.device("cuda", 0)
+    out = {}
+    for L, s, B, n in shapes:
+        f = np.stack([sht_synth.gaussian_flm(L, s, 6300 + b) for b in range(B)])
+        x = torch.from_numpy(f).to(dev, sht.io_dtype(prec))
+        m = torch.empty((B, L, 2 * L - 1), dtype=x.dtype, device=dev)
+        back = torch.empty_like(x)
+        ws = torch.empty(sht.workspace_bytes(L, s, B, prec), dtype=torch.uint8, device=dev)
+        times = {}
+        try:
+            for tile in (16, 32, 64):
+                sht.tile_set(L, 4 * B, prec, tile)
+                for _ in range(2):
+                    sht.inverse(x, L, s, prec, out=m, workspace=ws)
+                    sht.forward(m, L, s, prec, out=back, workspace=ws)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(n):
+                    sht.inverse(x, L, s, prec, out=m, workspace=ws)
+                    sht.forward(m, L, s, prec, out=back, workspace=ws)
+                e1.record()
+                e1.synchronize()
+                times[tile] = round(e0.elapsed_time(e1) / n, 4)
+            sht.tile_set(L, 4 * B, prec, 0)
+            pick = sht.tune(L, s, B, prec)
+        finally:
+            sht.tile_set(L, 4 * B, prec, 0)
+        C = 4 * B
+        default = min((16, 32, 64), key=lambda t: (-(-C // t) * (t + 24), t))
+        out[f"L{L}_s{s}_b{B}"] = {"ms_per_pair_by_tile": times, "default_tile": default,
+                                  "tuned_tile": pick, "best_tile": min(times, key=times.get)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +288,7 @@ def main() -> int:
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the eager-vs-graph-replay leg")
+    ap.add_argument("--no-tune", action="store_true", help="skip the contraction-tile autotuner leg")
     ap.add_argument("--serve-graphs", type=int, default=32,
                     help="captured transforms the serving loop keeps (0: eager launches only)")
     ap.add_argument("--no-real", action="store_true")
@@ -428,6 +470,9 @@ def main() -> int:
             "contract_fwd_ms": round(st_t["contract_fwd"][0] / st_t["contract_fwd"][1], 4)}
     if not args.no_graph and prec != "fp64":
         out["graph_replay"] = graph_replay(prec, [(64, 2, 1, 200), (256, 2, 4, 50), (L, wl.spins[-1], B, 5)])
+    if not args.no_tune:
+        out["tile_autotune"] = tile_autotune(prec, [(L, wl.spins[-1], B, 3), (512, 2, 6, 10), (512, 2, 3, 10),
+                                                    (256, 0, 24, 10)])
     rates = [float(f) for f in args.serve_rates.split(",") if f.strip()]
     if not args.no_serve and rates:
         out["serving"] = serving(args.serve_requests, rates, graphs=args.serve_graphs)

@@ -204,6 +204,31 @@ int sht_graph_create(int L, int spin, int batch, int sampling, int precision,
 int sht_graph_launch(sht_graph graph, void *stream);
 int sht_graph_destroy(sht_graph graph);
 
+/*
+ * Contraction tile shapes.  Each contraction workgroup takes 16, 32 or 64 of
+ * the transform's columns (4 x batch for sht_inverse / sht_forward, 2 x batch
+ * for the real-signal calls); more column blocks mean the Wigner products are
+ * generated once per block, wider blocks waste matrix-core work on empty
+ * columns.  By default a call takes the tile t that minimises
+ * ceil(columns / t) * (t + 24) (the Wigner generation of a block costs about
+ * as much as 24 columns): 16 up to 16 columns, 32 up to 32, 64 up to 64, and
+ * 32 or 64 above.
+ *
+ * sht_tile_set pins the tile (16, 32 or 64; 0 restores the default) for
+ * (current device, L, columns, precision).  SHT_ERR_INVALID_ARG for other
+ * tiles, L outside 1..SHT_L_MAX or columns outside 1..4*SHT_BATCH_MAX.
+ *
+ * sht_tune is the autotuner: it times the contraction kernels of the inverse
+ * and the forward of (L, spin, batch, precision) with each tile, using the
+ * workspace as scratch (its contents are overwritten; at least
+ * sht_workspace_bytes(...) bytes), pins the fastest for those columns, writes
+ * it to *tile_out (if not NULL) and synchronises the stream.  Errors as for
+ * sht_inverse.
+ */
+int sht_tile_set(int L, int columns, int precision, int tile);
+int sht_tune(int L, int spin, int batch, int precision, void *workspace, size_t ws_bytes, void *stream,
+             int *tile_out);
+
 /* Free every cached plan on every device, after destroying every live graph.
  * The caller must make sure no enqueued transform still uses them (e.g.
  * synchronise first). */

@@ -5,9 +5,9 @@ The transform runs in hand-written HIP kernels for gfx950 behind the C ABI of
 """
 
 from .sht import (PRECISIONS, Graph, forward, forward_real, forward_triangular, inverse, inverse_real, io_dtype,
-                  plan_tables, plan_warmup, real_dtype, release_all, spin_pair, trace_enable, trace_read,
-                  version, workspace_bytes)
+                  plan_tables, plan_warmup, real_dtype, release_all, spin_pair, tile_set, trace_enable,
+                  trace_read, tune, version, workspace_bytes)
 
 __all__ = ["PRECISIONS", "Graph", "forward", "forward_real", "forward_triangular", "inverse", "inverse_real", "io_dtype",
-           "plan_tables", "plan_warmup", "real_dtype", "release_all", "spin_pair",
-           "trace_enable", "trace_read", "version", "workspace_bytes"]
+           "plan_tables", "plan_warmup", "real_dtype", "release_all", "spin_pair", "tile_set",
+           "trace_enable", "trace_read", "tune", "version", "workspace_bytes"]

@@ -457,6 +457,78 @@ int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) 
     return prepare(L, spin, (hipStream_t)stream, &ds, &plan, &sp);
 }
 
+int sht_tile_set(int L, int columns, int precision, int tile) {
+    if (L < 1 || L > SHT_L_MAX || columns < 1 || columns > 4 * SHT_BATCH_MAX) return SHT_ERR_INVALID_ARG;
+    if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_ERR_UNSUPPORTED;
+    if (tile != 0 && tile != 16 && tile != 32 && tile != 64) return SHT_ERR_INVALID_ARG;
+    set_contract_tile(L, columns, contract_precision_class(precision == SHT_FP64, precision == SHT_BF16X3), tile);
+    return SHT_OK;
+}
+
+int sht_tune(int L, int spin, int batch, int precision, void *workspace, size_t ws_bytes, void *stream,
+             int *tile_out) {
+    int rc = check_args(L, spin, batch, SHT_SAMPLING_MW, precision);
+    if (rc != SHT_OK) return rc;
+    if (!workspace) return SHT_ERR_INVALID_ARG;
+    if (misaligned(workspace, 256)) return SHT_ERR_ALIGNMENT;
+    size_t ra, rb;
+    regions(L, batch, precision, ra, rb);
+    if (ws_bytes < ra + rb) return SHT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    if (rc != SHT_OK) return rc;
+    const int C = 4 * batch;
+    const bool f64 = precision == SHT_FP64, bf = precision == SHT_BF16X3;
+    const int pc = contract_precision_class(f64, bf);
+    unsigned char *w = (unsigned char *)workspace;
+    // region A as the contraction input (zeroed: the timing does not depend
+    // on the values), region B as its output
+    SHT_HIP(hipMemsetAsync(w, 0, ra, st), "tune clear");
+    hipEvent_t e0, e1;
+    SHT_HIP(hipEventCreate(&e0), "tune event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(hipErrorOutOfMemory, "tune event");
+    }
+    const int tiles[3] = {16, 32, 64};
+    int best = 0;
+    float best_ms = 0.0f;
+    rc = SHT_OK;
+    for (int i = 0; i < 3 && rc == SHT_OK; ++i) {
+        set_contract_tile(L, C, pc, tiles[i]);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3 && rc == SHT_OK; ++rep) {  // rep 0 warms up
+            hipError_t e = hipEventRecord(e0, st);
+            for (int mode = 0; mode < 2 && e == hipSuccess; ++mode) {
+                if (f64)
+                    e = launch_contract<double>(mode, L, spin, C, (const double *)w, (double *)(w + ra), ds->E, *sp,
+                                                plan->rec, st);
+                else
+                    e = contract<float>(mode, bf, L, spin, C, (const float *)w, (float *)(w + ra), ds, sp,
+                                        plan->rec, st);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) rc = hip_fail(e, "tune run");
+            if (rep > 0) ms += t;
+        }
+        if (rc == SHT_OK && (best == 0 || ms < best_ms)) {
+            best = tiles[i];
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_contract_tile(L, C, pc, rc == SHT_OK ? best : 0);
+    if (rc == SHT_OK && tile_out) *tile_out = best;
+    return rc;
+}
+
 int sht_graph_create(int L, int spin, int batch, int sampling, int precision, const void *flm_in, void *map,
                      void *flm_out, void *workspace, size_t ws_bytes, void *stream, sht_graph *out) {
     if (!out) return SHT_ERR_INVALID_ARG;

@@ -26,6 +26,9 @@
 //           BF16 products hi*hi + hi*lo + lo*hi accumulated in FP32 (the
 //           lo*lo term, ~2^-16 relative, is dropped).
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -691,6 +694,34 @@ __global__ void k_mtable(int L, EdgeTable E, const double *ri, const double2 *fa
     }
 }
 
+// Column tile of the contraction for (device, L, columns, precision): the
+// choice recorded by set_contract_tile (pinned, or picked by the timing
+// autotuner), else the tile t in {16, 32, 64} that minimises
+// ceil(C / t) (t + 24): every column block pays its columns on the matrix
+// cores plus the Wigner generation, which costs about as much as 24 columns.
+std::mutex g_tile_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tiles;
+
+int contract_tile(int L, int C, int P) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_tile_mu);
+        auto it = g_tiles.find(std::make_tuple(dev, L, C, P));
+        if (it != g_tiles.end()) return it->second;
+    }
+    int best = 16;
+    long best_cost = -1;
+    for (int t = 16; t <= 64; t *= 2) {
+        const long cost = (long)((C + t - 1) / t) * (t + 24);
+        if (best_cost < 0 || cost < best_cost) {
+            best = t;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 template <int P>
 hipError_t launch_prec(int mode, int L, int s, int C, const typename Prec<P>::T *X, typename Prec<P>::T *Y,
                        const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
@@ -713,11 +744,12 @@ hipError_t launch_prec(int mode, int L, int s, int C, const typename Prec<P>::T 
     const int cls = Prec<P>::TJ == 64 ? 0 : 1;
     a.sched = rt.sched[mode][cls];
     const int ns = rt.nsched[mode][cls];
-    if (a.C <= 16) {
-        a.ncb = 1;
+    const int ct = contract_tile(L, C, P);
+    a.ncb = (a.C + ct - 1) / ct;
+    if (ct == 16)
         return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, st) : launch_one<P, kForward, 16>(a, ns, st);
-    }
-    a.ncb = (a.C + 63) / 64;
+    if (ct == 32)
+        return mode == kInverse ? launch_one<P, kInverse, 32>(a, ns, st) : launch_one<P, kForward, 32>(a, ns, st);
     return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, st) : launch_one<P, kForward, 64>(a, ns, st);
 }
 
@@ -784,5 +816,18 @@ hipError_t launch_contract_bf16x3(int mode, int L, int s, int C, const float *X,
                                   const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
     return launch_prec<kPBF>(mode, L, s, C, X, Y, E, sp, rt, st);
 }
+
+int contract_precision_class(bool fp64, bool bf16x3) { return fp64 ? kP64 : (bf16x3 ? kPBF : kP32); }
+
+void set_contract_tile(int L, int C, int pclass, int ctile) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    const auto key = std::make_tuple(dev, L, C, pclass);
+    if (ctile == 0) g_tiles.erase(key);
+    else g_tiles[key] = ctile;
+}
+
+int get_contract_tile(int L, int C, int pclass) { return contract_tile(L, C, pclass); }
 
 }  // namespace sht

@@ -155,6 +155,13 @@ hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const Re
                          hipStream_t st);
 // fills rt.sched / rt.nsched for L (host sort, synchronous copy); 0 on success
 int build_contract_schedules(int L, RecTables &rt);
+// Column tile of the contraction (16, 32 or 64 columns per workgroup) for
+// (current device, L, columns C, precision class): set_contract_tile pins it
+// (0 restores the default cost model).
+int contract_precision_class(bool fp64, bool bf16x3);
+void set_contract_tile(int L, int C, int pclass, int ctile);
+int get_contract_tile(int L, int C, int pclass);
+
 hipError_t launch_contract_bf16x3(int mode, int L, int s, int C, const float *X, float *Y,
                                   const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 

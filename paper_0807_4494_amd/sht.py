@@ -194,6 +194,25 @@ def plan_tables(L: int, spin: int = 0, precision="fp32", enable: bool = True, de
             "sht_plan_tables")
 
 
+def tile_set(L: int, columns: int, precision="fp32", tile: int = 0) -> None:
+    """Pin the contraction's column tile (16, 32, 64; 0 = default) for
+    (L, columns = 4 x batch, precision) on the current device."""
+    N.check(N.load().sht_tile_set(L, columns, _prec(precision), tile), "sht_tile_set")
+
+
+def tune(L: int, spin: int, batch: int, precision="fp32", device=None) -> int:
+    """Autotuner: time the contraction with each column tile for this shape,
+    pin the fastest and return it (synchronises the current stream)."""
+    import ctypes
+    p = _prec(precision)
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    ws, nbytes = _workspace(L, spin, batch, p, dev, None)
+    out = ctypes.c_int(0)
+    N.check(N.load().sht_tune(L, spin, batch, p, ws.data_ptr() if ws is not None else None, nbytes,
+                              _stream_handle(dev), ctypes.byref(out)), "sht_tune")
+    return int(out.value)
+
+
 class Graph:
     """Captured inverse + forward of one shape (``sht_graph_create``): the
     inverse of ``flm_in`` into ``map`` and the forward of ``map`` into

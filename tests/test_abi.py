@@ -105,6 +105,20 @@ def test_graph_argument_checks_run_before_any_hip_call():
     assert lib.sht_graph_destroy(fake) == N.SHT_ERR_INVALID_ARG
 
 
+def test_tile_and_tune_argument_checks_run_before_any_hip_call():
+    N, lib = _lib()
+    assert lib.sht_tile_set(0, 4, 1, 32) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_tile_set(64, 0, 1, 32) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_tile_set(64, 4 * 64 + 1, 1, 32) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_tile_set(64, 8, 7, 32) == N.SHT_ERR_UNSUPPORTED
+    assert lib.sht_tile_set(64, 8, 1, 48) == N.SHT_ERR_INVALID_ARG
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.sht_tune(0, 0, 1, 1, fake, 1 << 40, None, None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_tune(64, 0, 1, 1, None, 1 << 40, None, None) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_tune(64, 0, 1, 1, ctypes.c_void_p((1 << 20) + 8), 1 << 40, None, None) == N.SHT_ERR_ALIGNMENT
+    assert lib.sht_tune(64, 0, 1, 1, fake, 16, None, None) == N.SHT_ERR_WORKSPACE
+
+
 def test_workspace_size_formula():
     N, lib = _lib()
     for L, B, p in [(32, 1, 0), (1024, 16, 1), (2048, 4, 1), (255, 3, 0)]:
