@@ -169,12 +169,16 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     if (hipMalloc(&p->rec.ri, (size_t)L * L * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->rec.rf, (size_t)L * L * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->rec.fab, (size_t)L * L * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->rec.jti, (size_t)L * L * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&p->rec.jtf, (size_t)L * L * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->rec.jti, (size_t)(L + 2 * kTabPad) * L * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->rec.jtf, (size_t)(L + 2 * kTabPad) * L * sizeof(double2)) != hipSuccess ||
         hipMalloc(&p->rec.cl, (size_t)L * sizeof(double)) != hipSuccess) {
         delete p;
         return SHT_ERR_OOM;
     }
+    SHT_HIP(hipMemsetAsync(p->rec.jti, 0, (size_t)(L + 2 * kTabPad) * L * sizeof(double2), st), "table padding");
+    SHT_HIP(hipMemsetAsync(p->rec.jtf, 0, (size_t)(L + 2 * kTabPad) * L * sizeof(double2), st), "table padding");
+    p->rec.jti += (size_t)kTabPad * L;
+    p->rec.jtf += (size_t)kTabPad * L;
     SHT_HIP(launch_rec_tables(L, p->rec, st), "recursion tables");
     if (build_contract_schedules(L, p->rec) != 0) {
         delete p;
@@ -197,14 +201,17 @@ int get_spin_plan(int dev, int L, int spin, const DeviceState *ds, const Plan *p
     sp->device = dev;
     sp->L = L;
     sp->spin = spin;
-    // one block: wi, wf (FP64) then wi32, wf32 (FP32)
-    const size_t n = (size_t)L * L;
+    // one block: wi, wf (FP64) then wi32, wf32 (FP32), each L rows of L
+    // between kTabPad zero rows
+    const size_t n = (size_t)(L + 2 * kTabPad) * L, pad = (size_t)kTabPad * L;
+    const size_t bytes = n * (2 * sizeof(double) + 2 * sizeof(float));
     char *blk = nullptr;
-    if (hipMalloc(&blk, n * (2 * sizeof(double) + 2 * sizeof(float))) != hipSuccess) { delete sp; return SHT_ERR_OOM; }
-    sp->wi = (double *)blk;
-    sp->wf = sp->wi + n;
-    sp->wi32 = (float *)(sp->wf + n);
-    sp->wf32 = sp->wi32 + n;
+    if (hipMalloc(&blk, bytes) != hipSuccess) { delete sp; return SHT_ERR_OOM; }
+    SHT_HIP(hipMemsetAsync(blk, 0, bytes, st), "table padding");
+    sp->wi = (double *)blk + pad;
+    sp->wf = (double *)blk + n + pad;
+    sp->wi32 = (float *)((double *)blk + 2 * n) + pad;
+    sp->wf32 = (float *)((double *)blk + 2 * n) + n + pad;
     SHT_HIP(launch_spin_tables(ds->E, plan->rec, *sp, st), "spin tables");
     SHT_HIP(hipStreamSynchronize(st), "spin plan sync");
     g_spin[key] = sp;
@@ -618,7 +625,7 @@ int sht_release_all(void) {
     if (hipGetDevice(&cur) != hipSuccess) cur = 0;
     for (auto &kv : g_spin) {
         (void)hipSetDevice(kv.second->device);
-        if (hipFree(kv.second->wi) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->wi - (size_t)kTabPad * kv.second->L) != hipSuccess) rc = SHT_ERR_HIP;
         if (kv.second->mtab64 && hipFree(kv.second->mtab64) != hipSuccess) rc = SHT_ERR_HIP;
         if (kv.second->mtab32 && hipFree(kv.second->mtab32) != hipSuccess) rc = SHT_ERR_HIP;
         delete kv.second;
@@ -631,8 +638,8 @@ int sht_release_all(void) {
         if (hipFree(kv.second->rec.ri) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.rf) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.fab) != hipSuccess) rc = SHT_ERR_HIP;
-        if (hipFree(kv.second->rec.jti) != hipSuccess) rc = SHT_ERR_HIP;
-        if (hipFree(kv.second->rec.jtf) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.jti - (size_t)kTabPad * kv.second->L) != hipSuccess) rc = SHT_ERR_HIP;
+        if (hipFree(kv.second->rec.jtf - (size_t)kTabPad * kv.second->L) != hipSuccess) rc = SHT_ERR_HIP;
         if (hipFree(kv.second->rec.cl) != hipSuccess) rc = SHT_ERR_HIP;
         for (int md = 0; md < 2; ++md)
             for (int c = 0; c < 2; ++c)

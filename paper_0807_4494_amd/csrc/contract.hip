@@ -73,6 +73,12 @@ __device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
+__device__ __forceinline__ double2 buffer_load_d2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v v = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+    return make_double2(v.x, v.y);
+}
+
 // BF16 pair of an FP32 value: hi = v rounded to BF16 (nearest, ties to
 // even), lo = the remainder v - hi rounded the same way; hi + lo carries
 // about 16 significant bits.  Finite inputs only.
@@ -281,26 +287,39 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         // factor sqrt((2l+1)/4pi) d^l_{.,-s}, PD steps ahead: set kk % PD
         // holds step kk of the slab until it is consumed and is then refilled
         // with step kk + PD (in this slab or the next), so no register copies.
-        // Rows outside [0, L) are clamped; they only reach steps whose chains
-        // are zero or whose emissions meet zero rows of X.  (The spin factor
-        // is held in the output precision: it multiplies a value rounded to T
-        // on emission anyway.)
+        // The steps visit table rows one after another (up in l for the
+        // inverse, down in m' for the forward), so each load takes a running
+        // uniform row offset and a fixed lane offset into the table viewed as
+        // a buffer: no address arithmetic per step.  The rows a tile visits
+        // outside [0, L) lie in the tables' zero padding (kTabPad rows each
+        // side); they only reach steps whose chains are zero or whose
+        // emissions meet zero rows of X.  (The spin factor is held in the
+        // output precision: it multiplies a value rounded to T on emission
+        // anyway.)
         constexpr int PD = TK / 2;
         const unsigned jo = (unsigned)(jvalid ? j : 0);
         double2 tj[PD];
         T wj[PD];
-        auto load_step = [&](int chunk, int kk, double2 &t, T &w) {
-            if (kk >= TK) {
-                ++chunk;
-                kk -= TK;
-            } else if (kk < 0) {
-                ++chunk;
-                kk += TK;
+        const unsigned rowj = (unsigned)L * (unsigned)sizeof(double2), roww = (unsigned)L * (unsigned)sizeof(T);
+        const int prow = L + 2 * kTabPad;
+        const __amdgpu_buffer_rsrc_t jrs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.jtab - (size_t)kTabPad * L), (short)0, prow * L * (int)sizeof(double2), kBufWord3);
+        const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.wtab - (size_t)kTabPad * L), (short)0, prow * L * (int)sizeof(T), kBufWord3);
+        const unsigned jvo = jo * (unsigned)sizeof(double2), wvo = jo * (unsigned)sizeof(T);
+        // padded row of the next step to load, in processing order
+        const int krow0 = kbase_of(0) + (MODE == kInverse ? 0 : TK - 1) + kTabPad;
+        unsigned soj = (unsigned)krow0 * rowj, sow = (unsigned)krow0 * roww;
+        auto load_next = [&](double2 &t, T &w) {
+            t = buffer_load_d2(jrs, jvo, soj);
+            w = buffer_load<T>(wrs, wvo, sow);
+            if (MODE == kInverse) {
+                soj += rowj;
+                sow += roww;
+            } else {
+                soj -= rowj;
+                sow -= roww;
             }
-            int k = kbase_of(chunk) + kk;
-            k = k < 0 ? 0 : (k > L - 1 ? L - 1 : k);
-            t = (a.jtab + (size_t)k * L)[jo];
-            w = (a.wtab + (size_t)k * L)[jo];
         };
         // order-side factors of the l-recursion (inverse), staged through LDS
         // one slab ahead: loaded at the start of a slab, stored at its end
@@ -373,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                             fb[g] = fbm[buf][sub * NCH + g][kk + 1];
                         }
                     }
-                    load_step(chunk, kk + PD, tj[kk % PD], wj[kk % PD]);
+                    load_next(tj[kk % PD], wj[kk % PD]);
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
                         emit(buf, sub * NCH + g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
@@ -393,7 +412,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                     const int k = kbase + kk;  // m'
                     const double2 t = tj[kk % PD];
                     const T W = wj[kk % PD];
-                    load_step(chunk, kk - PD, tj[kk % PD], wj[kk % PD]);
+                    load_next(tj[kk % PD], wj[kk % PD]);
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
                         emit(buf, sub * NCH + g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
@@ -441,7 +460,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
             const int kk = MODE == kInverse ? i : TK - 1 - i;
-            load_step(0, kk, tj[kk % PD], wj[kk % PD]);
+            load_next(tj[kk % PD], wj[kk % PD]);
         }
         fetch_factors(0);
         store_factors(0);

@@ -69,6 +69,13 @@ template <typename T> struct FftTables {
 // tile width class (TJ = 64: FP64, TJ = 128: FP32 / BF16x3), the
 // (order group, j tile) pairs that have work, as (group << 8) | tile, sorted
 // by the length of their K loop, longest first (nsched entries each).
+// The tables the contraction streams row by row (jti, jtf and the spin
+// factors wi, wf, wi32, wf32) are stored with kTabPad zero rows before row 0
+// and after row L - 1: a tile's K loop may run up to two slabs past either end
+// of [0, L), and the padding lets it load those rows unguarded.  The pointers
+// point at row 0; the allocation starts kTabPad rows earlier.
+constexpr int kTabPad = 32;
+
 struct RecTables {
     double *ri = nullptr;
     double *rf = nullptr;
