@@ -229,6 +229,35 @@ int sht_tile_set(int L, int columns, int precision, int tile);
 int sht_tune(int L, int spin, int batch, int precision, void *workspace, size_t ws_bytes, void *stream,
              int *tile_out);
 
+/*
+ * Error metrics of a reconstruction against a reference: the five measures
+ * of the paper's round-trip stability test (Section 4.2), computed on the GPU
+ * in FP64.  Over the n complex entries of ref (f) and val (g):
+ *   out[0] = max |f - g|          out[1] = mean |f - g|
+ *   out[2] = median |f - g|       (for even n the mean of the two middle
+ *                                  values; the exact elements, by radix
+ *                                  selection)
+ *   out[3] = rms = sqrt(mean |f - g|^2)
+ *   out[4] = relative rms = sqrt(sum |f - g|^2 / sum |f|^2), or
+ *            sqrt(sum |f - g|^2) if f is all zero
+ * All five are 0 for n = 0.  Finite inputs.
+ *   precision  element type: SHT_FP64 complex double, SHT_FP32 / SHT_BF16X3
+ *              complex float (SHT_ERR_UNSUPPORTED otherwise)
+ *   ref, val   device arrays of n elements (may be NULL if n = 0), aligned
+ *              to the element's real part; only read
+ *   out        device array of 5 doubles, 8-byte aligned, written
+ *   workspace  device scratch of at least sht_error_workspace_bytes() bytes,
+ *              256-byte aligned, owned by the caller, overwritten
+ *   stream     HIP stream (NULL = default); the call is asynchronous, out is
+ *              ready when the stream reaches this point
+ * Errors: SHT_ERR_INVALID_ARG (NULL out / workspace, NULL arrays with n > 0,
+ * more than 2^40 bytes per array), SHT_ERR_ALIGNMENT, SHT_ERR_WORKSPACE,
+ * SHT_ERR_HIP.  Checks run before any HIP call.
+ */
+size_t sht_error_workspace_bytes(void);
+int sht_error_metrics(int precision, size_t n, const void *ref, const void *val, double *out, void *workspace,
+                      size_t ws_bytes, void *stream);
+
 /* Free every cached plan on every device, after destroying every live graph.
  * The caller must make sure no enqueued transform still uses them (e.g.
  * synchronise first). */

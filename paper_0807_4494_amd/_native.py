@@ -28,7 +28,7 @@ SHT_TRI_L_MAX = 128
 EXPORTS = ("sht_inverse", "sht_forward", "sht_inverse_real", "sht_forward_real", "sht_forward_triangular",
            "sht_spin_pair", "sht_workspace_bytes", "sht_plan_warmup",
            "sht_plan_tables", "sht_graph_create", "sht_graph_launch", "sht_graph_destroy",
-           "sht_tile_set", "sht_tune",
+           "sht_tile_set", "sht_tune", "sht_error_workspace_bytes", "sht_error_metrics",
            "sht_release_all", "sht_status_string", "sht_version", "sht_last_hip_error",
            "sht_trace_enable", "sht_trace_read")
 
@@ -85,6 +85,10 @@ def load() -> ctypes.CDLL:
     lib.sht_tile_set.restype = i
     lib.sht_tune.argtypes = [i, i, i, i, vp, sz, vp, ctypes.POINTER(i)]
     lib.sht_tune.restype = i
+    lib.sht_error_workspace_bytes.argtypes = []
+    lib.sht_error_workspace_bytes.restype = sz
+    lib.sht_error_metrics.argtypes = [i, sz, vp, vp, vp, vp, sz, vp]
+    lib.sht_error_metrics.restype = i
     lib.sht_release_all.argtypes = []
     lib.sht_release_all.restype = i
     lib.sht_status_string.argtypes = [i]

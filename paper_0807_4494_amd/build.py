@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsht.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "plan.hip", "fft.hip", "layout.hip", "contract.hip", "tri.hip"]
+SOURCES = ["api.hip", "plan.hip", "fft.hip", "layout.hip", "contract.hip", "tri.hip", "metrics.hip"]
 
 
 def hipcc() -> str:

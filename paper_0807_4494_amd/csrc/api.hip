@@ -464,6 +464,22 @@ int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) 
     return prepare(L, spin, (hipStream_t)stream, &ds, &plan, &sp);
 }
 
+size_t sht_error_workspace_bytes(void) { return error_workspace_bytes(); }
+
+int sht_error_metrics(int precision, size_t n, const void *ref, const void *val, double *out, void *workspace,
+                      size_t ws_bytes, void *stream) {
+    if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_ERR_UNSUPPORTED;
+    if (!out || !workspace || (n > 0 && (!ref || !val))) return SHT_ERR_INVALID_ARG;
+    const size_t esz = precision == SHT_FP64 ? 16 : 8;
+    if (n > ((size_t)1 << 40) / esz) return SHT_ERR_INVALID_ARG;
+    if (misaligned(workspace, 256) || misaligned(out, 8) || misaligned(ref, esz / 2) || misaligned(val, esz / 2))
+        return SHT_ERR_ALIGNMENT;
+    if (ws_bytes < error_workspace_bytes()) return SHT_ERR_WORKSPACE;
+    SHT_HIP(launch_error_metrics(precision == SHT_FP64, ref, val, n, out, workspace, (hipStream_t)stream),
+            "error metrics");
+    return SHT_OK;
+}
+
 int sht_tile_set(int L, int columns, int precision, int tile) {
     if (L < 1 || L > SHT_L_MAX || columns < 1 || columns > 4 * SHT_BATCH_MAX) return SHT_ERR_INVALID_ARG;
     if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_ERR_UNSUPPORTED;

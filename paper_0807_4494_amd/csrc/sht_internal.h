@@ -162,6 +162,12 @@ hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const Re
                          hipStream_t st);
 // fills rt.sched / rt.nsched for L (host sort, synchronous copy); 0 on success
 int build_contract_schedules(int L, RecTables &rt);
+
+// metrics.hip: error metrics of g against f (n complex entries, complex double
+// if fp64 else complex float) into out[0..4] (device), asynchronous on st
+size_t error_workspace_bytes();
+hipError_t launch_error_metrics(bool fp64, const void *f, const void *g, size_t n, double *out, void *ws,
+                                hipStream_t st);
 // Column tile of the contraction (16, 32 or 64 columns per workgroup) for
 // (current device, L, columns C, precision class): set_contract_tile pins it
 // (0 restores the default cost model).

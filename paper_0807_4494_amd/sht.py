@@ -213,6 +213,34 @@ def tune(L: int, spin: int, batch: int, precision="fp32", device=None) -> int:
     return int(out.value)
 
 
+ERROR_METRICS = ("max", "mean", "median", "rms", "rel_rms")
+
+
+def error_metrics(ref: torch.Tensor, val: torch.Tensor) -> dict:
+    """The five error measures of the paper's stability test (Section 4.2)
+    of ``val`` against ``ref`` (same shape, complex64 or complex128, on the
+    GPU), computed on the device in FP64 (``sht_error_metrics``): max, mean,
+    median and rms of |ref - val| and the relative rms
+    sqrt(sum |ref - val|^2 / sum |ref|^2).  Synchronises the current stream."""
+    if ref.shape != val.shape or ref.dtype != val.dtype:
+        raise ValueError("ref and val must have the same shape and dtype")
+    if ref.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError("ref and val must be complex64 or complex128")
+    if not (ref.is_cuda and val.is_cuda) or ref.device != val.device:
+        raise ValueError("ref and val must be GPU tensors on one device")
+    p = N.SHT_FP64 if ref.dtype == torch.complex128 else N.SHT_FP32
+    f, g = ref.contiguous(), val.contiguous()
+    lib = N.load()
+    need = lib.sht_error_workspace_bytes()
+    ws = torch.empty(need, dtype=torch.uint8, device=ref.device)
+    out = torch.empty(5, dtype=torch.float64, device=ref.device)
+    N.check(lib.sht_error_metrics(p, f.numel(), f.data_ptr() if f.numel() else None,
+                                  g.data_ptr() if g.numel() else None, out.data_ptr(), ws.data_ptr(), need,
+                                  _stream_handle(ref.device)), "sht_error_metrics")
+    vals = out.cpu().tolist()
+    return dict(zip(ERROR_METRICS, vals))
+
+
 class Graph:
     """Captured inverse + forward of one shape (``sht_graph_create``): the
     inverse of ``flm_in`` into ``map`` and the forward of ``map`` into

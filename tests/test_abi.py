@@ -119,6 +119,25 @@ def test_tile_and_tune_argument_checks_run_before_any_hip_call():
     assert lib.sht_tune(64, 0, 1, 1, fake, 16, None, None) == N.SHT_ERR_WORKSPACE
 
 
+def test_error_metrics_argument_checks_run_before_any_hip_call():
+    N, lib = _lib()
+    need = lib.sht_error_workspace_bytes()
+    assert need >= 32 * 1024 and need % 256 == 0
+    fake = ctypes.c_void_p(1 << 20)
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    call = lib.sht_error_metrics
+    assert call(7, 10, fake, fake, fake, fake, need, None) == N.SHT_ERR_UNSUPPORTED
+    assert call(1, 10, None, fake, fake, fake, need, None) == N.SHT_ERR_INVALID_ARG
+    assert call(1, 10, fake, None, fake, fake, need, None) == N.SHT_ERR_INVALID_ARG
+    assert call(1, 10, fake, fake, None, fake, need, None) == N.SHT_ERR_INVALID_ARG
+    assert call(1, 10, fake, fake, fake, None, need, None) == N.SHT_ERR_INVALID_ARG
+    assert call(0, 1 << 37, fake, fake, fake, fake, need, None) == N.SHT_ERR_INVALID_ARG
+    assert call(1, 10, fake, fake, fake, odd, need, None) == N.SHT_ERR_ALIGNMENT
+    assert call(0, 10, odd, fake, fake, fake, need, None) == N.SHT_ERR_ALIGNMENT
+    assert call(1, 10, fake, fake, ctypes.c_void_p((1 << 20) + 2), fake, need, None) == N.SHT_ERR_ALIGNMENT
+    assert call(1, 10, fake, fake, fake, fake, need - 256, None) == N.SHT_ERR_WORKSPACE
+
+
 def test_workspace_size_formula():
     N, lib = _lib()
     for L, B, p in [(32, 1, 0), (1024, 16, 1), (2048, 4, 1), (255, 3, 0)]:
