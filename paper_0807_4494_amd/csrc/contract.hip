@@ -79,6 +79,10 @@ __device__ __forceinline__ double2 buffer_load_d2(__amdgpu_buffer_rsrc_t r, unsi
     return make_double2(v.x, v.y);
 }
 
+__device__ __forceinline__ float4 buffer_load_f4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+
 // BF16 pair of an FP32 value: hi = v rounded to BF16 (nearest, ties to
 // even), lo = the remainder v - hi rounded the same way; hi + lo carries
 // about 16 significant bits.  Finite inputs only.
@@ -107,17 +111,21 @@ template <> struct Prec<kP32> { using T = float; static constexpr int TJ = 128, 
 template <> struct Prec<kPBF> { using T = float; static constexpr int TJ = 128, WJ = 32; };
 
 // LDS slabs.  FP32 / FP64: M slab [k][j] with rows padded by 16 so the four K
-// rows an MFMA fragment spans hit disjoint banks; X slab [c][k] with an odd
-// row length.  BF16x3: the 16x16x16 BF16 fragments hold four consecutive k
+// rows an MFMA fragment spans hit disjoint banks; X slab [c][k] with rows of
+// TK + 1 (FP64) or TK + 4 (FP32: four consecutive k are one aligned 16-byte
+// store, and the fragment reads, 16 columns x 4 k, still hit 64 distinct
+// banks).  BF16x3: the 16x16x16 BF16 fragments hold four consecutive k
 // per lane, so M is stored [k/4][j][k%4] and X [c][k] (row of TK + 4, so a
 // lane's four k are one aligned 8-byte read), each as hi and lo planes.
 template <int P, int CTILE> struct Slabs {
     using T = typename Prec<P>::T;
+    static constexpr int XROW = P == kP32 ? TK + 4 : TK + 1;
     T M[2][GM][TK][Prec<P>::TJ + 16];
-    T X[2][GM][CTILE][TK + 1];
+    alignas(16) T X[2][GM][CTILE][XROW];
 };
 template <int CTILE> struct Slabs<kPBF, CTILE> {
     static constexpr int TJ = Prec<kPBF>::TJ;
+    static constexpr int XROW = TK + 4;
     alignas(16) unsigned short Mh[2][GM][TK / 4][TJ + 16][4];
     alignas(16) unsigned short Ml[2][GM][TK / 4][TJ + 16][4];
     alignas(16) unsigned short Xh[2][GM][CTILE][TK + 4];
@@ -150,6 +158,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
     constexpr int NCH = GM / NPJ;   // main chains per producer thread
     constexpr int NCI = CTILE / 16, NJI = WJ / 16;
     constexpr int XPT = GM * CTILE * TK / NC;  // X slab elements per consumer thread
+    static_assert(XPT % 4 == 0, "X slab quadruples");
     using acc_t = typename Mfma<T>::acc;
 
     __shared__ Slabs<P, CTILE> sm;
@@ -476,17 +485,35 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 
     // ================= consumers: MFMA =================
     // X slab: element i of this thread is (g, c, kk); 32-bit offsets from the
-    // group's panel base, fixed for the whole K loop
-    int xoff[XPT], xsl[XPT];
+    // group's panel base, fixed for the whole K loop.  FP32 / BF16x3: element
+    // 4 q + r is k = 4 kq + r of the q-th (g, c, kq) quadruple, so a thread's
+    // four consecutive elements are four consecutive k of one row (one
+    // 16-byte load when the rows are 16-byte aligned)
+    constexpr bool V4 = P != kP64;
+    constexpr int XROW = Slabs<P, CTILE>::XROW;
+    int xoff[XPT], xsl[XPT], xkk[XPT], xg[XPT];
     bool xok[XPT];
 #pragma unroll
     for (int i = 0; i < XPT; ++i) {
-        const int e = tid + i * NC;  // over [GM][CTILE][TK]
-        const int g = e / (CTILE * TK), rem = e % (CTILE * TK);
-        const int c = rem / TK, kk = rem % TK;
+        int g, c, kk;
+        if constexpr (V4) {
+            const int e4 = tid + (i / 4) * NC;  // over [GM][CTILE][TK / 4]
+            g = e4 / (CTILE * TK / 4);
+            const int rem = e4 % (CTILE * TK / 4);
+            c = rem / (TK / 4);
+            kk = 4 * (rem % (TK / 4)) + i % 4;
+        } else {
+            const int e = tid + i * NC;  // over [GM][CTILE][TK]
+            g = e / (CTILE * TK);
+            const int rem = e % (CTILE * TK);
+            c = rem / TK;
+            kk = rem % TK;
+        }
+        xg[i] = g;
+        xkk[i] = kk;
         xok[i] = (m0 + g) < L && (c0 + c) < Cn;
         xoff[i] = (g * Cn + c0 + c) * L + kk;
-        xsl[i] = (g * CTILE + c) * (BF ? TK + 4 : TK + 1) + kk;
+        xsl[i] = (g * CTILE + c) * XROW + kk;
     }
     const T *xbase = a.X + (size_t)m0 * Cn * L;
     bool xall = true;
@@ -516,17 +543,27 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             // added by the memory unit
             const unsigned so = (unsigned)kbase * (unsigned)sizeof(T);
             if constexpr (P != kP64) {
+                if ((L & 3) == 0) {
+                    // rows and slab start 16-byte aligned (kbase is a multiple of TK)
 #pragma unroll
-                for (int i = 0; i < XPT; ++i) xr[i] = buffer_load<T>(xrsrc, xvo[i], so);
+                    for (int i = 0; i < XPT; i += 4) {
+                        const float4 v = buffer_load_f4(xrsrc, xvo[i], so);
+                        xr[i] = v.x;
+                        xr[i + 1] = v.y;
+                        xr[i + 2] = v.z;
+                        xr[i + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < XPT; ++i) xr[i] = buffer_load<T>(xrsrc, xvo[i], so);
+                }
             }
         } else {
 #pragma unroll
             for (int i = 0; i < XPT; ++i) {
-                const int e = tid + i * NC;
-                const int g = e / (CTILE * TK), kk = e % TK;
-                const int k = kbase + kk;
+                const int k = kbase + xkk[i];
                 bool ok = xok[i] && k >= 0 && k < L;
-                if (MODE == kInverse) ok = ok && k >= m0 + g;
+                if (MODE == kInverse) ok = ok && k >= m0 + xg[i];
                 xr[i] = ok ? xbase[xoff[i] + kbase] : T(0);
             }
         }
@@ -541,6 +578,10 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                 xh[xsl[i]] = hi;
                 xl[xsl[i]] = lo;
             }
+        } else if constexpr (P == kP32) {
+            float *xt = &sm.X[buf][0][0][0];
+#pragma unroll
+            for (int i = 0; i < XPT; i += 4) *(float4 *)&xt[xsl[i]] = make_float4(xr[i], xr[i + 1], xr[i + 2], xr[i + 3]);
         } else {
             T *xt = &sm.X[buf][0][0][0];
 #pragma unroll
@@ -611,7 +652,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             // constant offset from them
             const T *xl = &sm.X[buf][0][lane & 15][lane >> 4];
             const T *ml = &sm.M[buf][0][lane >> 4][wave * WJ + (lane & 15)];
-            constexpr int XR = TK + 1, MR = TJ + 16;
+            constexpr int XR = Slabs<P, CTILE>::XROW, MR = TJ + 16;
             auto ldfrag = [&](int idx, int slot) {
                 const int g = idx / NKS, ks = idx % NKS;
 #pragma unroll
