@@ -276,6 +276,50 @@ def tile_autotune(prec: str, shapes) -> dict:
     return out
 
 
+def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict:
+    """The stability test of Section 4.2 on the GPU path: real spin-0 test
+    functions with Re, Im ~ U[-1, 1] (f_{l,-m} = (-1)^m conj(f_lm), f_l0
+    real), inverse then forward, the five error measures computed on the
+    device and averaged over the functions.  Forwards: the quadrature (FP64
+    and FP32) at every L, and the paper's triangular systems (FP64, up to
+    L = 128)."""
+    import numpy as np
+    import torch
+
+    import paper_0807_4494_amd as sht
+    import sht_synth
+
+    dev = torch.device("cuda", 0)
+    out = {"protocol": f"real spin-0 U[-1,1] test functions, {n_funcs} per L, inverse then forward; "
+                       "each measure averaged over the functions",
+           "quadrature_fp64": {}, "quadrature_fp32": {}, "triangular_fp64": {}}
+    for L in Ls:
+        l_of = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
+        m_of = np.arange(L * L) - l_of * l_of - l_of
+        mirror = l_of * l_of + l_of - m_of           # index of (l, -m)
+        fs = []
+        for k in range(n_funcs):
+            f = sht_synth.uniform_flm(L, 0, sht_synth.SEED_BASE + 9000 + 31 * L + k)
+            f[m_of == 0] = f[m_of == 0].real
+            neg = m_of < 0
+            f[neg] = (-1.0) ** m_of[neg] * np.conj(f[mirror[neg]])
+            fs.append(f)
+        flm = torch.from_numpy(np.stack(fs)).to(dev)
+        legs = [("quadrature_fp64", "fp64", None), ("quadrature_fp32", "fp32", None)]
+        if L <= 128:
+            legs.append(("triangular_fp64", "fp64", "tri"))
+        for name, prec, kind in legs:
+            f_in = flm.to(sht.io_dtype(prec))
+            fmap = sht.inverse(f_in, L, 0, prec)
+            back = sht.forward_triangular(fmap, L, 0) if kind == "tri" else sht.forward(fmap, L, 0, prec)
+            acc = {}
+            for k in range(n_funcs):
+                for key, v in sht.error_metrics(f_in[k], back[k].to(f_in.dtype)).items():
+                    acc[key] = acc.get(key, 0.0) + v / n_funcs
+            out[name][str(L)] = {k: float(f"{v:.3g}") for k, v in acc.items()}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +336,7 @@ def main() -> int:
     ap.add_argument("--serve-graphs", type=int, default=32,
                     help="captured transforms the serving loop keeps (0: eager launches only)")
     ap.add_argument("--no-real", action="store_true")
+    ap.add_argument("--no-stability", action="store_true", help="skip the Section 4.2 stability leg")
     ap.add_argument("--tables", action="store_true",
                     help="also time the cached-table design (an L^3 table per spin, 4 GiB each in FP32 at L=1024)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -459,6 +504,8 @@ def main() -> int:
         out["real_signal_path"] = {"workload": f"L={L}, spin 0, {B} real maps, inverse + forward",
                                    "value": round(B / (ms_r / 1e3), 2), "unit": "transforms/s",
                                    "ms_per_batch": round(ms_r, 4), "round_trip_rel_l2_m_ge_0": rt_r}
+    if not args.no_stability:
+        out["stability"] = stability()
     if args.tables:
         # the precomputed-table design: M streamed from a cached L^3 table
         for s in wl.spins:
