@@ -117,13 +117,20 @@ template <> struct Prec<kPBF> { using T = float; static constexpr int TJ = 128, 
 // banks).  BF16x3: the 16x16x16 BF16 fragments hold four consecutive k
 // per lane, so M is stored [k/4][j][k%4] and X [c][k] (row of TK + 4, so a
 // lane's four k are one aligned 8-byte read), each as hi and lo planes.
-template <int P, int CTILE> struct Slabs {
+// KP (FP32 forward): M stored [k/2][j][k%2] for K-paired fragments (see the
+// consumers).
+template <int P, int CTILE, bool KP = false> struct Slabs {
     using T = typename Prec<P>::T;
     static constexpr int XROW = P == kP32 ? TK + 4 : TK + 1;
     T M[2][GM][TK][Prec<P>::TJ + 16];
     alignas(16) T X[2][GM][CTILE][XROW];
 };
-template <int CTILE> struct Slabs<kPBF, CTILE> {
+template <int CTILE> struct Slabs<kP32, CTILE, true> {
+    static constexpr int TJ = Prec<kP32>::TJ, XROW = TK + 4;
+    alignas(16) float M[2][GM][TK / 2][TJ + 16][2];
+    alignas(16) float X[2][GM][CTILE][XROW];
+};
+template <int CTILE> struct Slabs<kPBF, CTILE, false> {
     static constexpr int TJ = Prec<kPBF>::TJ;
     static constexpr int XROW = TK + 4;
     alignas(16) unsigned short Mh[2][GM][TK / 4][TJ + 16][4];
@@ -161,7 +168,10 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
     static_assert(XPT % 4 == 0, "X slab quadruples");
     using acc_t = typename Mfma<T>::acc;
 
-    __shared__ Slabs<P, CTILE> sm;
+    // FP32 forward: K-paired MFMA fragments (measured faster there; the
+    // inverse keeps the plain layout, where pairing measured slower)
+    constexpr bool KP = P == kP32 && MODE == kForward;
+    __shared__ Slabs<P, CTILE, KP> sm;
     __shared__ double fam[2][GM][TK], fbm[2][GM][TK];
 
     const int L = a.L, s = a.s, Cn = a.C;
@@ -224,6 +234,8 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                 bf16_split(v, hi, lo);
                 sm.Mh[buf][gi][kk >> 2][jl][kk & 3] = hi;
                 sm.Ml[buf][gi][kk >> 2][jl][kk & 3] = lo;
+            } else if constexpr (KP) {
+                sm.M[buf][gi][kk >> 1][jl][kk & 1] = v;
             } else {
                 sm.M[buf][gi][kk][jl] = v;
             }
@@ -349,12 +361,25 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             }
         };
         // one entry of M, rounded to the MFMA precision, into LDS
-        auto emit = [&](int buf, int gi, int kk, double dv, T W) {
+        // KP: the two entries of a K pair are written together as one 8-byte
+        // store when the second of them (in processing order, m' descending)
+        // is emitted; the first waits in `held`
+        T held[NCH];
+        auto emit = [&](int buf, int g, int kk, double dv, T W) {
+            const int gi = sub * NCH + g;
             if constexpr (BF) {
                 unsigned short hi, lo;
                 bf16_split((float)dv * W, hi, lo);
                 sm.Mh[buf][gi][kk >> 2][jl][kk & 3] = hi;
                 sm.Ml[buf][gi][kk >> 2][jl][kk & 3] = lo;
+            } else if constexpr (KP) {
+                const T v = (T)dv * W;
+                if (kk & 1) {
+                    held[g] = v;
+                } else {
+                    typedef float f32x2 __attribute__((ext_vector_type(2)));
+                    *(f32x2 *)&sm.M[buf][gi][kk >> 1][jl][0] = f32x2{v, held[g]};
+                }
             } else {
                 sm.M[buf][gi][kk][jl] = (T)dv * W;
             }
@@ -404,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                     load_next(tj[kk % PD], wj[kk % PD]);
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        emit(buf, sub * NCH + g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
+                        emit(buf, g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
                     // step l -> l+1
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
@@ -424,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                     load_next(tj[kk % PD], wj[kk % PD]);
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        emit(buf, sub * NCH + g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
+                        emit(buf, g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
                     // step m' -> m'-1
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
@@ -490,7 +515,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
     // four consecutive elements are four consecutive k of one row (one
     // 16-byte load when the rows are 16-byte aligned)
     constexpr bool V4 = P != kP64;
-    constexpr int XROW = Slabs<P, CTILE>::XROW;
+    constexpr int XROW = Slabs<P, CTILE, KP>::XROW;
     int xoff[XPT], xsl[XPT], xkk[XPT], xg[XPT];
     bool xok[XPT];
 #pragma unroll
@@ -643,6 +668,37 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                         acc[g][ci][ji] = c;
                     }
             }
+        } else if constexpr (KP) {
+            // K slots in pairs: pair group (g, h) covers steps 2h and 2h + 1
+            // of order g; slot q of step 2h + e takes k = 8h + 2q + e, so a
+            // lane's two operands of a pair group are one 8-byte read from each
+            // slab.  Fragments double-buffered as below.
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            constexpr int NPG = GM * 2;
+            f32x2 av[2][NCI], bv[2][NJI];
+            const float *xl = &sm.X[buf][0][lane & 15][2 * (lane >> 4)];
+            const float *ml = &sm.M[buf][0][lane >> 4][wave * WJ + (lane & 15)][0];
+            constexpr int XR = Slabs<P, CTILE, KP>::XROW, MR = (TJ + 16) * 2;
+            auto ldfrag = [&](int idx, int slot) {
+                const int g = idx / 2, h = idx % 2;
+#pragma unroll
+                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = *(const f32x2 *)&xl[(g * CTILE + ci * 16) * XR + 8 * h];
+#pragma unroll
+                for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = *(const f32x2 *)&ml[(g * (TK / 2) + 4 * h) * MR + ji * 32];
+            };
+            ldfrag(0, 0);
+#pragma unroll
+            for (int idx = 0; idx < NPG; ++idx) {
+                if (idx + 1 < NPG) ldfrag(idx + 1, (idx + 1) & 1);
+                const int g = idx / 2;
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+#pragma unroll
+                    for (int ci = 0; ci < NCI; ++ci)
+#pragma unroll
+                        for (int ji = 0; ji < NJI; ++ji)
+                            acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci][e], bv[idx & 1][ji][e], acc[g][ci][ji]);
+            }
         } else {
             // operand fragments double-buffered: group idx+1 is read from LDS
             // while the MFMAs of group idx run
@@ -652,7 +708,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             // constant offset from them
             const T *xl = &sm.X[buf][0][lane & 15][lane >> 4];
             const T *ml = &sm.M[buf][0][lane >> 4][wave * WJ + (lane & 15)];
-            constexpr int XR = Slabs<P, CTILE>::XROW, MR = TJ + 16;
+            constexpr int XR = Slabs<P, CTILE, KP>::XROW, MR = TJ + 16;
             auto ldfrag = [&](int idx, int slot) {
                 const int g = idx / NKS, ks = idx % NKS;
 #pragma unroll
