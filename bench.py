@@ -281,8 +281,8 @@ def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict
     functions with Re, Im ~ U[-1, 1] (f_{l,-m} = (-1)^m conj(f_lm), f_l0
     real), inverse then forward, the five error measures computed on the
     device and averaged over the functions.  Forwards: the quadrature (FP64
-    and FP32) at every L, and the paper's triangular systems (FP64, up to
-    L = 128)."""
+    and FP32) at every L, the paper's triangular systems and their all-rows
+    least-squares variant (FP64, up to L = 128)."""
     import numpy as np
     import torch
 
@@ -292,7 +292,7 @@ def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict
     dev = torch.device("cuda", 0)
     out = {"protocol": f"real spin-0 U[-1,1] test functions, {n_funcs} per L, inverse then forward; "
                        "each measure averaged over the functions",
-           "quadrature_fp64": {}, "quadrature_fp32": {}, "triangular_fp64": {}}
+           "quadrature_fp64": {}, "quadrature_fp32": {}, "triangular_fp64": {}, "lstsq_fp64": {}}
     for L in Ls:
         l_of = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
         m_of = np.arange(L * L) - l_of * l_of - l_of
@@ -308,10 +308,16 @@ def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict
         legs = [("quadrature_fp64", "fp64", None), ("quadrature_fp32", "fp32", None)]
         if L <= 128:
             legs.append(("triangular_fp64", "fp64", "tri"))
+            legs.append(("lstsq_fp64", "fp64", "lstsq"))
         for name, prec, kind in legs:
             f_in = flm.to(sht.io_dtype(prec))
             fmap = sht.inverse(f_in, L, 0, prec)
-            back = sht.forward_triangular(fmap, L, 0) if kind == "tri" else sht.forward(fmap, L, 0, prec)
+            if kind == "tri":
+                back = sht.forward_triangular(fmap, L, 0)
+            elif kind == "lstsq":
+                back = sht.forward_lstsq(fmap, L, 0)
+            else:
+                back = sht.forward(fmap, L, 0, prec)
             acc = {}
             for k in range(n_funcs):
                 for key, v in sht.error_metrics(f_in[k], back[k].to(f_in.dtype)).items():

@@ -156,6 +156,23 @@ int sht_forward_triangular(int L, int spin, int batch, int sampling, int precisi
                            const void *map, void *flm, void *workspace, size_t ws_bytes,
                            void *stream);
 
+/*
+ * The stable comparison to sht_forward_triangular: the same per-order
+ * systems of Eq. (matrix_fwd), but all their rows m' = 0..L-1 (the square
+ * block plus the rows m' < max(|m0|, |s|) that the paper's solve drops),
+ * solved in the least-squares sense -- not the paper's method.  Those extra
+ * rows make the systems well conditioned, so the result stays at FP64
+ * rounding where the triangular solve loses all accuracy (Section 4.2).
+ * Solved on the GPU by conjugate gradients on the normal equations until
+ * the normal-equation residual has fallen by 1e-14 (at most 2L + 32
+ * iterations).
+ *   Arguments, precision, L limit, workspace and errors: as for
+ *   sht_forward_triangular.
+ */
+int sht_forward_lstsq(int L, int spin, int batch, int sampling, int precision,
+                      const void *map, void *flm, void *workspace, size_t ws_bytes,
+                      void *stream);
+
 /* Workspace bytes needed by sht_inverse / sht_forward with these arguments
  * (the same size serves both directions).  0 if the arguments are invalid. */
 size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precision);

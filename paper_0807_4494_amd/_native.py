@@ -26,6 +26,7 @@ SHT_TRI_L_MAX = 128
 
 #: every symbol include/sht.h declares
 EXPORTS = ("sht_inverse", "sht_forward", "sht_inverse_real", "sht_forward_real", "sht_forward_triangular",
+           "sht_forward_lstsq",
            "sht_spin_pair", "sht_workspace_bytes", "sht_plan_warmup",
            "sht_plan_tables", "sht_graph_create", "sht_graph_launch", "sht_graph_destroy",
            "sht_tile_set", "sht_tune", "sht_error_workspace_bytes", "sht_error_metrics",
@@ -59,7 +60,7 @@ def load() -> ctypes.CDLL:
                           "(or __graft_entry__.build()) first")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
-    for name in ("sht_inverse", "sht_forward", "sht_forward_triangular"):
+    for name in ("sht_inverse", "sht_forward", "sht_forward_triangular", "sht_forward_lstsq"):
         f = getattr(lib, name)
         f.argtypes = [i, i, i, i, i, vp, vp, vp, sz, vp]
         f.restype = i

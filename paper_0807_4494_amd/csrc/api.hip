@@ -411,6 +411,32 @@ int sht_forward_triangular(int L, int spin, int batch, int sampling, int precisi
     return SHT_OK;
 }
 
+int sht_forward_lstsq(int L, int spin, int batch, int sampling, int precision, const void *map, void *flm,
+                      void *workspace, size_t ws_bytes, void *stream) {
+    int rc = check_args(L, spin, batch, sampling, precision);
+    if (rc != SHT_OK) return rc;
+    if (precision != SHT_FP64 || L > SHT_TRI_L_MAX) return SHT_ERR_UNSUPPORTED;
+    rc = check_buffers(L, batch, precision, map, flm, workspace, ws_bytes);
+    if (rc != SHT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    if (rc != SHT_OK) return rc;
+    size_t ra, rb;
+    regions(L, batch, precision, ra, rb);
+    unsigned char *w = (unsigned char *)workspace;
+    void *A = (void *)w;         // phi-stage output, later the torus coefficients
+    void *Bq = (void *)(w + ra); // the same rows over t
+    const FftTables<double> &ft = plan->f64;
+    SHT_HIP(launch_phi_fwd<double>(ft, batch, map, A, st), "phi forward");
+    SHT_HIP(launch_transpose<double>(batch, L, ft.N, A, Bq, st), "transpose");
+    SHT_HIP(launch_theta_dft<double>(ft, spin, batch, Bq, A, st), "theta dft");
+    SHT_HIP(launch_tri_lstsq(L, spin, batch, A, flm, ds->E, *sp, plan->rec, st), "least-squares solve");
+    return SHT_OK;
+}
+
 int sht_spin_pair(int L, int spin, int batch, int precision, const void *flm_s, void *flm_ms, void *stream) {
     int rc = check_args(L, spin, batch, SHT_SAMPLING_MW, precision);
     if (rc != SHT_OK) return rc;

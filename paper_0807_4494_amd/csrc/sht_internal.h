@@ -181,6 +181,9 @@ hipError_t launch_contract_bf16x3(int mode, int L, int s, int C, const float *X,
 // tri.hip: the paper's per-order triangular systems (FP64, L <= SHT_TRI_L_MAX)
 hipError_t launch_tri_solve(int L, int s, int B, const void *F, void *flm, const EdgeTable &E,
                             const SpinPlan &sp, const RecTables &rt, hipStream_t st);
+// ... and the least-squares solution of all their rows (the stable comparison)
+hipError_t launch_tri_lstsq(int L, int s, int B, const void *F, void *flm, const EdgeTable &E,
+                            const SpinPlan &sp, const RecTables &rt, hipStream_t st);
 
 // ------------------------------------------------------------- helpers -----
 inline int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }

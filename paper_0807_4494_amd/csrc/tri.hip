@@ -113,7 +113,213 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_solve(int L, int s, int B
     }
 }
 
+// The stable comparison: for one order, all rows m' = 0 .. L-1 of the same
+// system (columns l0 .. L-1), solved in the least-squares sense.  The rows
+// m' < l0 that the square block drops make these systems well conditioned.
+// Solved by conjugate gradients on the normal equations (CGNR: x, the
+// residual r = F - D x and z = D^T r), MBL maps (2 MBL real right-hand sides,
+// since the real factor of D is real) at a time, until every z has fallen by
+// kLsqTol relative to its start or after 2 L + 32 iterations.  D is stored
+// transposed with rows padded to L + 1, Dt[l][j], so both products read it
+// with at most 2-way bank conflicts:
+//   w = D p:    thread j sums Dt[l][j] p_l over l >= max(j, l0)
+//   z = D^T r:  thread l sums Dt[l][j] r_j over j <= l
+constexpr int MBL = 4;
+constexpr int NV = 2 * MBL;
+constexpr double kLsqTol = 1e-28;  // on |z|^2, i.e. 1e-14 on |z|
+
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_lstsq(int L, int s, int B, const cplx64 *__restrict__ F,
+                                                            cplx64 *__restrict__ flm, EdgeTable E,
+                                                            const double *__restrict__ wi,
+                                                            const double *__restrict__ ri,
+                                                            const double2 *__restrict__ fab) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int LP = L + 1;
+    double *Dt = reinterpret_cast<double *>(smem_raw);  // [L][L + 1]
+    double *vs = Dt + (size_t)L * LP;                   // [NV][L]: p, then r, shared by all threads
+    double *red = vs + (size_t)NV * L;                  // [NV][waves] partial sums
+    const int N = 2 * L - 1, h = L - 1;
+    const int m0 = (int)blockIdx.x - h;
+    const int am = m0 < 0 ? -m0 : m0;
+    const int as = s < 0 ? -s : s;
+    const int l0 = am > as ? am : as;
+    const int t = threadIdx.x, nw = (int)blockDim.x / 64, wave = t >> 6, lane = t & 63;
+
+    // ---- the real factor of D at columns l >= l0, every row j ----
+    for (int i = t; i < L * LP; i += blockDim.x) Dt[i] = 0.0;
+    __syncthreads();
+    if (t < L) {
+        const int j = t;
+        const int lc = j > am ? j : am;  // edge of the (j, |m0|) chain
+        Chain c;
+        c.inject(edge_seed(E, j, am));
+        double q = 0.0;  // multiplies d^{l-1}, which is zero at the edge
+        for (int l = lc; l < L; ++l) {
+            if (l >= l0) {
+                double d = c.value();
+                if (m0 < 0 && ((l + j) & 1)) d = -d;  // Delta^l_{j,-m} = (-1)^{l+j} Delta^l_{jm}
+                Dt[(size_t)l * LP + j] = wi[(size_t)l * L + j] * d;
+            }
+            if (l + 1 < L) {
+                const double r = ri[(size_t)l * L + j];
+                const double ap = (double)j * r, bp = q * r;
+                q = ((double)(l + 1) * (l + 1) - (double)j * j) * r;
+                const double2 f = fab[(size_t)am * L + l];
+                c.push(-(ap * f.x * c.d + bp * f.y * c.dp));
+            }
+        }
+    }
+    __syncthreads();
+
+    const bool row = t < L;                 // owns row j = t of the m-side vectors
+    const bool col = t >= l0 && t < L;      // owns column l = t of the n-side vectors
+    auto block_sums = [&](double (&v)[NV], double (&out)[NV]) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double w = wave_sum64(v[k]);
+            if (lane == 0) red[k * nw + wave] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double a = 0.0;
+            for (int i = 0; i < nw; ++i) a += red[k * nw + i];
+            out[k] = a;
+        }
+        __syncthreads();
+    };
+    // z = D^T r for the r held by the row owners
+    auto at_times = [&](const double (&r)[NV], double (&z)[NV]) {
+        if (row) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) vs[k * L + t] = r[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) z[k] = 0.0;
+        if (col) {
+            const double *dl = Dt + (size_t)t * LP;
+            for (int j = 0; j <= t; ++j) {
+                const double d = dl[j];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) z[k] += d * vs[k * L + j];
+            }
+        }
+        __syncthreads();
+    };
+    // w = D p for the p held by the column owners
+    auto a_times = [&](const double (&p)[NV], double (&w)[NV]) {
+        if (t < L) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) vs[k * L + t] = col ? p[k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) w[k] = 0.0;
+        if (row) {
+            for (int l = t > l0 ? t : l0; l < L; ++l) {
+                const double d = Dt[(size_t)l * LP + t];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) w[k] += d * vs[k * L + l];
+            }
+        }
+        __syncthreads();
+    };
+
+    const int ph = ((m0 + s) % 4 + 4) % 4;
+    const double sgn = (s & 1) ? -1.0 : 1.0;
+    const int max_iter = 2 * L + 32;
+    for (int b0 = 0; b0 < B; b0 += MBL) {
+        double r[NV], x[NV], z[NV], p[NV], w[NV], zz[NV], zz0[NV], ww[NV], sq[NV];
+#pragma unroll
+        for (int q = 0; q < MBL; ++q) {
+            cplx64 f{0.0, 0.0};
+            if (row && b0 + q < B) f = F[((size_t)(b0 + q) * N + (m0 + h)) * L + t];
+            r[2 * q] = f.x;
+            r[2 * q + 1] = f.y;
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) x[k] = 0.0;
+        at_times(r, z);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            p[k] = z[k];
+            sq[k] = z[k] * z[k];
+        }
+        block_sums(sq, zz);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) zz0[k] = zz[k];
+        for (int it = 0; it < max_iter; ++it) {
+            bool done = true;  // uniform: zz is a block sum
+#pragma unroll
+            for (int k = 0; k < NV; ++k) done = done && zz[k] <= kLsqTol * zz0[k];
+            if (done) break;
+            a_times(p, w);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sq[k] = w[k] * w[k];
+            block_sums(sq, ww);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const double alpha = (zz[k] > 0.0 && ww[k] > 0.0) ? zz[k] / ww[k] : 0.0;
+                x[k] += alpha * p[k];
+                r[k] -= alpha * w[k];
+            }
+            at_times(r, z);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sq[k] = z[k] * z[k];
+            double zn[NV];
+            block_sums(sq, zn);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const double beta = zz[k] > 0.0 ? zn[k] / zz[k] : 0.0;
+                p[k] = z[k] + beta * p[k];
+                zz[k] = zn[k];
+            }
+        }
+        // f_{l m0} = x (-1)^s i^{m0+s}
+        if (t < L && am <= t) {
+#pragma unroll
+            for (int q = 0; q < MBL; ++q) {
+                if (b0 + q >= B) continue;
+                cplx64 v{0.0, 0.0};
+                if (col) {
+                    const cplx64 xv{x[2 * q], x[2 * q + 1]};
+                    switch (ph) {
+                        case 0: v = xv; break;
+                        case 1: v = cplx64{-xv.y, xv.x}; break;
+                        case 2: v = cplx64{-xv.x, -xv.y}; break;
+                        default: v = cplx64{xv.y, -xv.x}; break;
+                    }
+                    v = cplx64{v.x * sgn, v.y * sgn};
+                }
+                flm[(size_t)(b0 + q) * L * L + (size_t)t * t + t + m0] = v;
+            }
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_tri_lstsq(int L, int s, int B, const void *F, void *flm, const EdgeTable &E, const SpinPlan &sp,
+                            const RecTables &rt, hipStream_t st) {
+    if (L > SHT_TRI_L_MAX) return hipErrorInvalidValue;
+    const int threads = ((L + 63) / 64) * 64;
+    const size_t lds = ((size_t)L * (L + 1) + (size_t)NV * L + (size_t)NV * (threads / 64)) * sizeof(double);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_tri_lstsq, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_tri_lstsq, dim3(2 * L - 1), dim3(threads), lds, st, L, s, B, (const cplx64 *)F,
+                       (cplx64 *)flm, E, sp.wi, rt.ri, rt.fab);
+    return hipGetLastError();
+}
 
 hipError_t launch_tri_solve(int L, int s, int B, const void *F, void *flm, const EdgeTable &E, const SpinPlan &sp,
                             const RecTables &rt, hipStream_t st) {

@@ -157,10 +157,7 @@ def spin_pair(flm_s: torch.Tensor, L: int, spin: int, precision="fp64",
     return out[0] if single else out
 
 
-def forward_triangular(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch.Tensor] = None,
-                       workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """The paper's own forward transform (per-order triangular systems), FP64,
-    L <= 128.  Ill conditioned beyond small L; see :func:`forward`."""
+def _forward_tri(fmap, L, spin, out, workspace, entry):
     p = N.SHT_FP64
     single = fmap.dim() == 2
     g = fmap.reshape(1, *fmap.shape) if single else fmap
@@ -173,11 +170,25 @@ def forward_triangular(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[
     if out is None:
         out = torch.empty((B, L * L), dtype=torch.complex128, device=g.device)
     ws, nbytes = _workspace(L, spin, B, p, g.device, workspace)
-    rc = N.load().sht_forward_triangular(L, spin, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
-                                         ws.data_ptr() if ws is not None else None, nbytes,
-                                         _stream_handle(g.device))
-    N.check(rc, "sht_forward_triangular")
+    rc = getattr(N.load(), entry)(L, spin, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
+                                  ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(g.device))
+    N.check(rc, entry)
     return out[0] if single else out
+
+
+def forward_triangular(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch.Tensor] = None,
+                       workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The paper's own forward transform (per-order triangular systems), FP64,
+    L <= 128.  Ill conditioned beyond small L; see :func:`forward`."""
+    return _forward_tri(fmap, L, spin, out, workspace, "sht_forward_triangular")
+
+
+def forward_lstsq(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """All rows of the per-order systems, least squares (the stable
+    comparison to :func:`forward_triangular`; not the paper's method), FP64,
+    L <= 128."""
+    return _forward_tri(fmap, L, spin, out, workspace, "sht_forward_lstsq")
 
 
 def plan_warmup(L: int, spin: int = 0, precision="fp64", device=None) -> None:

@@ -84,6 +84,13 @@ def test_argument_checks_run_before_any_hip_call():
     assert tri(N.SHT_TRI_L_MAX + 1, 0, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
     assert tri(8, 8, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
     assert tri(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
+    # the least-squares variant: the same checks
+    lsq = lib.sht_forward_lstsq
+    assert lsq(8, 0, 1, 0, 1, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
+    assert lsq(N.SHT_TRI_L_MAX + 1, 0, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
+    assert lsq(8, 8, 1, 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert lsq(8, 0, 1, 0, 0, None, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert lsq(8, 0, 1, 0, 0, fake, fake, fake, need - 1, None) == N.SHT_ERR_WORKSPACE
 
 
 def test_graph_argument_checks_run_before_any_hip_call():

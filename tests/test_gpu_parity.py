@@ -168,6 +168,28 @@ def test_triangular_forward_matches_oracle(L, s):
     assert rel(flm, got) < 1e-9
 
 
+@pytest.mark.parametrize("L,s", [(1, 0), (2, 1), (5, 0), (8, -2), (12, 3), (16, 0), (24, 2), (33, -1)])
+def test_least_squares_forward_matches_oracle(L, s):
+    """All rows of the per-order systems, least squares on the GPU (conjugate
+    gradients on the normal equations) against the oracle's dense solve, on
+    band-limited maps (both recover the coefficients) and on unstructured
+    maps (a genuine least-squares problem)."""
+    sht = _sht()
+    print(f"[least squares] L={L} s={s}", flush=True)
+    from oracle import triangular as T
+    B = 5  # more than one pass of maps
+    flm = np.stack([sht_synth.gaussian_flm(L, s, 700 + 13 * L + b) for b in range(B)])
+    fmap = oracle.inverse_batch(flm, L, s)
+    got = sht.forward_lstsq(to_dev(fmap, "fp64"), L, s).cpu().numpy()
+    ref = np.stack([T.forward_lstsq(fmap[b], L, s) for b in range(B)])
+    assert rel(ref, got) < 1e-11, rel(ref, got)
+    assert rel(flm, got) < 1e-11
+    noisy = np.stack([sht_synth.random_complex_map(L, 900 + b) for b in range(2)])
+    got = sht.forward_lstsq(to_dev(noisy, "fp64"), L, s).cpu().numpy()
+    ref = np.stack([T.forward_lstsq(noisy[b], L, s) for b in range(2)])
+    assert rel(ref, got) < 1e-10, rel(ref, got)
+
+
 def test_triangular_forward_instability_on_the_gpu():
     """Section 4.2 on the GPU: real spin-0 U[-1, 1] test functions; the
     paper's forward is exact at L = 8 and loses accuracy by L = 64, while the
@@ -184,8 +206,10 @@ def test_triangular_forward_instability_on_the_gpu():
         fmap = sht.inverse(to_dev(f, "fp64"), L, 0, "fp64")
         g = sht.forward_triangular(fmap, L, 0).cpu().numpy()
         q = sht.forward(fmap, L, 0, "fp64").cpu().numpy()
+        ls = sht.forward_lstsq(fmap, L, 0).cpu().numpy()
         errs[L] = rel(f, g)
         assert rel(f, q) < 1e-12
+        assert rel(f, ls) < 1e-12, (L, rel(f, ls))   # the least-squares variant stays exact
     print(f"[triangular] rel rms error by L: {errs}", flush=True)
     assert errs[8] < 1e-12
     assert errs[64] > 1e-3
