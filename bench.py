@@ -46,6 +46,9 @@ PEAK = {  # MI355X published peaks
 }
 
 
+SPECTRA = {"flat": "C_l = 1", "inv_lp1_sq": "C_l = 1/(l+1)^2", "inv_l_lp1": "C_l = 1/(l(l+1))"}
+
+
 def contraction_flops(L: int, s: int, B: int) -> float:
     """Algorithmic flops of one contraction launch (one direction, B maps):
     4 sum_{l=|s|}^{L-1} (2l+1)(l+1) per map -- real multiply-adds x 2 over the
@@ -459,7 +462,7 @@ def main() -> int:
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[prec],
         "data": "synthetic",
         "config": {"workload": wl.name, "L": L, "batch": B, "spins": list(wl.spins),
-                   "spectrum": "C_l = 1/(l+1)^2", "precision": prec,
+                   "spectrum": SPECTRA.get(wl.spec, wl.spec), "precision": prec,
                    "maps_per_step": per_step, "wigner_recursion": "f64"},
         "roofline": roof,
         "round_trip_rel_l2": rt,
