@@ -190,6 +190,21 @@ def test_least_squares_forward_matches_oracle(L, s):
     assert rel(ref, got) < 1e-10, rel(ref, got)
 
 
+@pytest.mark.parametrize("s", [0, 2, -3])
+def test_least_squares_forward_is_exact_at_the_largest_band_limit(s):
+    """At L = SHT_TRI_L_MAX, where the square triangular systems are hopeless,
+    the all-rows least-squares solve still recovers band-limited
+    coefficients to FP64 rounding, for every spin class."""
+    sht = _sht()
+    from paper_0807_4494_amd import _native as N
+    L = N.SHT_TRI_L_MAX
+    print(f"[least squares] L={L} s={s}", flush=True)
+    flm = np.stack([sht_synth.gaussian_flm(L, s, 750 + b) for b in range(2)])
+    fmap = sht.inverse(to_dev(flm, "fp64"), L, s, "fp64")
+    got = sht.forward_lstsq(fmap, L, s).cpu().numpy()
+    assert rel(flm, got) < 1e-12, rel(flm, got)
+
+
 def test_triangular_forward_instability_on_the_gpu():
     """Section 4.2 on the GPU: real spin-0 U[-1, 1] test functions; the
     paper's forward is exact at L = 8 and loses accuracy by L = 64, while the
