@@ -279,6 +279,27 @@ def tile_autotune(prec: str, shapes) -> dict:
     return out
 
 
+def real_test_functions(L: int, n: int):
+    """The stability test functions of Section 4.2: coefficients of real
+    spin-0 maps, Re and Im of f_lm (m > 0) drawn from U[-1, 1], f_l0 real,
+    f_{l,-m} = (-1)^m conj(f_lm); [n, L*L] complex128, seeded per (L, k)."""
+    import numpy as np
+
+    import sht_synth
+
+    l_of = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
+    m_of = np.arange(L * L) - l_of * l_of - l_of
+    mirror = l_of * l_of + l_of - m_of           # index of (l, -m)
+    neg = m_of < 0
+    fs = []
+    for k in range(n):
+        f = sht_synth.uniform_flm(L, 0, sht_synth.SEED_BASE + 9000 + 31 * L + k)
+        f[m_of == 0] = f[m_of == 0].real
+        f[neg] = (-1.0) ** m_of[neg] * np.conj(f[mirror[neg]])
+        fs.append(f)
+    return np.stack(fs)
+
+
 def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict:
     """The stability test of Section 4.2 on the GPU path: real spin-0 test
     functions with Re, Im ~ U[-1, 1] (f_{l,-m} = (-1)^m conj(f_lm), f_l0
@@ -297,17 +318,7 @@ def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict
                        "each measure averaged over the functions",
            "quadrature_fp64": {}, "quadrature_fp32": {}, "triangular_fp64": {}, "lstsq_fp64": {}}
     for L in Ls:
-        l_of = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
-        m_of = np.arange(L * L) - l_of * l_of - l_of
-        mirror = l_of * l_of + l_of - m_of           # index of (l, -m)
-        fs = []
-        for k in range(n_funcs):
-            f = sht_synth.uniform_flm(L, 0, sht_synth.SEED_BASE + 9000 + 31 * L + k)
-            f[m_of == 0] = f[m_of == 0].real
-            neg = m_of < 0
-            f[neg] = (-1.0) ** m_of[neg] * np.conj(f[mirror[neg]])
-            fs.append(f)
-        flm = torch.from_numpy(np.stack(fs)).to(dev)
+        flm = torch.from_numpy(real_test_functions(L, n_funcs)).to(dev)
         legs = [("quadrature_fp64", "fp64", None), ("quadrature_fp32", "fp32", None)]
         if L <= 128:
             legs.append(("triangular_fp64", "fp64", "tri"))
