@@ -71,7 +71,9 @@ enum sht_status {
     SHT_ERR_WORKSPACE = -3,     /* ws_bytes < sht_workspace_bytes(...) */
     SHT_ERR_ALIGNMENT = -4,     /* flm / map not element-aligned, workspace not 256-byte aligned */
     SHT_ERR_OOM = -5,           /* plan allocation failed */
-    SHT_ERR_HIP = -6            /* a HIP call or kernel launch failed */
+    SHT_ERR_HIP = -6,           /* a HIP call or kernel launch failed */
+    SHT_ERR_BUSY = -7,          /* the resource is in use (sht_plan_tables: a captured graph reads the table) */
+    SHT_ERR_NOT_READY = -8      /* a call that allocates nothing found its plan missing */
 };
 
 enum sht_sampling { SHT_SAMPLING_MW = 0 };
@@ -191,7 +193,10 @@ int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream);
  * -- the precomputation Section 4.1 describes; from then on the transforms at
  * that (L, spin) and precision class stream M from the table instead of
  * running the recursions.  enable = 0 frees the table.  Synchronises the
- * stream.  SHT_ERR_OOM if the table does not fit.
+ * stream.  SHT_ERR_OOM if the table does not fit.  A graph captured
+ * (sht_graph_create) while the table existed reads it on every replay, so
+ * enable = 0 returns SHT_ERR_BUSY, and frees nothing, until every such graph
+ * has been destroyed.
  */
 int sht_plan_tables(int L, int spin, int precision, int enable, void *stream);
 

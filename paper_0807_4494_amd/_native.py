@@ -19,6 +19,8 @@ SHT_ERR_WORKSPACE = -3
 SHT_ERR_ALIGNMENT = -4
 SHT_ERR_OOM = -5
 SHT_ERR_HIP = -6
+SHT_ERR_BUSY = -7
+SHT_ERR_NOT_READY = -8
 
 SHT_SAMPLING_MW = 0
 SHT_FP64, SHT_FP32, SHT_BF16X3 = 0, 1, 2

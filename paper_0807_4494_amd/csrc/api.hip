@@ -41,6 +41,10 @@ std::map<std::tuple<int, int, int>, SpinPlan *> g_spin;      // (device, L, spin
 struct sht_graph_s {
     int device;
     hipGraphExec_t exec;
+    // the cached contraction table the captured kernels read (or none): its
+    // use count in tab_sp->mtab_users[tab_cls] keeps it alive
+    sht::SpinPlan *tab_sp;
+    int tab_cls;
 };
 namespace {
 std::mutex g_graph_mu;
@@ -463,6 +467,7 @@ int sht_plan_tables(int L, int spin, int precision, int enable, void *stream) {
     const bool f64 = precision == SHT_FP64;
     void **slot = f64 ? (void **)&sp->mtab64 : (void **)&sp->mtab32;
     if (!enable) {
+        if (sp->mtab_users[f64 ? 1 : 0] > 0) return SHT_ERR_BUSY;  // a captured graph streams it
         if (*slot) {
             SHT_HIP(hipStreamSynchronize(st), "table release sync");
             SHT_HIP(hipFree(*slot), "table free");
@@ -593,8 +598,28 @@ int sht_graph_create(int L, int spin, int batch, int sampling, int precision, co
     if (rc != SHT_OK) return rc;
     int dev = 0;
     SHT_HIP(hipGetDevice(&dev), "graph device");
+    // a cached table that the captured contraction will read stays alive
+    // until the graph is destroyed (sht_plan_tables refuses to free it)
+    SpinPlan *tab_sp = nullptr;
+    const int tab_cls = precision == SHT_FP64 ? 1 : 0;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_spin.find(std::make_tuple(dev, L, spin));
+        if (it != g_spin.end() && (tab_cls ? (void *)it->second->mtab64 : (void *)it->second->mtab32)) {
+            tab_sp = it->second;
+            ++tab_sp->mtab_users[tab_cls];
+        }
+    }
+    auto drop_table_use = [&]() {
+        if (!tab_sp) return;
+        std::lock_guard<std::mutex> lock(g_mu);
+        --tab_sp->mtab_users[tab_cls];
+    };
     hipStream_t cs;
-    SHT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph capture stream");
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        drop_table_use();
+        return hip_fail(hipGetLastError(), "graph capture stream");
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -619,8 +644,11 @@ int sht_graph_create(int L, int spin, int batch, int sampling, int precision, co
     }
     if (g) (void)hipGraphDestroy(g);
     (void)hipStreamDestroy(cs);
-    if (rc != SHT_OK) return rc;
-    sht_graph_s *h = new sht_graph_s{dev, ex};
+    if (rc != SHT_OK) {
+        drop_table_use();
+        return rc;
+    }
+    sht_graph_s *h = new sht_graph_s{dev, ex, tab_sp, tab_cls};
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
         g_graphs.insert(h);
@@ -647,6 +675,10 @@ int sht_graph_destroy(sht_graph graph) {
     if (!graph || !g_graphs.count(graph)) return SHT_ERR_INVALID_ARG;
     g_graphs.erase(graph);
     const hipError_t e = hipGraphExecDestroy(graph->exec);
+    if (graph->tab_sp) {
+        std::lock_guard<std::mutex> lock(g_mu);
+        --graph->tab_sp->mtab_users[graph->tab_cls];
+    }
     delete graph;
     if (e != hipSuccess) return hip_fail(e, "graph destroy");
     return SHT_OK;
@@ -708,6 +740,8 @@ const char *sht_status_string(int status) {
         case SHT_ERR_ALIGNMENT: return "misaligned buffer";
         case SHT_ERR_OOM: return "device allocation for a plan failed";
         case SHT_ERR_HIP: return "HIP error (see sht_last_hip_error)";
+        case SHT_ERR_BUSY: return "resource in use (a captured graph streams this table)";
+        case SHT_ERR_NOT_READY: return "plan not resident (call sht_plan_warmup first)";
         default: return "unknown status";
     }
 }

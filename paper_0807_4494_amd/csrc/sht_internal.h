@@ -106,6 +106,9 @@ struct SpinPlan {
     // [m][l][m'] (L^3 entries), FP64 and FP32 (the latter also feeds BF16x3)
     double *mtab64 = nullptr;
     float *mtab32 = nullptr;
+    // captured graphs whose transforms stream a table ([0] FP32, [1] FP64):
+    // the table is not freed while any of them exists
+    int mtab_users[2] = {0, 0};
 };
 
 // -------------------------------------------------------- kernel launches ---

@@ -42,6 +42,32 @@ def workspace_bytes(L: int, spin: int, batch: int, precision="fp64") -> int:
     return int(N.load().sht_workspace_bytes(L, spin, batch, N.SHT_SAMPLING_MW, _prec(precision)))
 
 
+def check_out(name: str, t: torch.Tensor, shape, dtype: torch.dtype, device: torch.device) -> None:
+    """A caller's output tensor must be exactly what the library writes: the
+    expected shape and dtype, contiguous, on the input's device (the library
+    writes through its data pointer, so anything smaller or strided would be
+    written past its end)."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch.Tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the input on {device}")
+
+
+def check_workspace(t: torch.Tensor, device: torch.device) -> None:
+    """A caller's workspace: contiguous uint8 on the input's device (its size
+    is checked by the library against sht_workspace_bytes)."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_contiguous():
+        raise ValueError("workspace must be a contiguous torch.uint8 tensor")
+    if t.device != device:
+        raise ValueError(f"workspace is on {t.device}, the input on {device}")
+
+
 def _workspace(L, spin, batch, p, device, workspace):
     need = N.load().sht_workspace_bytes(L, spin, batch, N.SHT_SAMPLING_MW, p)
     if need == 0:
@@ -49,7 +75,17 @@ def _workspace(L, spin, batch, p, device, workspace):
         return None, 0
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=device)
+    else:
+        check_workspace(workspace, device)
     return workspace, workspace.numel() * workspace.element_size()
+
+
+def _out(out, shape, dtype, device, name="out"):
+    """The caller's output tensor after the checks of :func:`check_out`, or a new one."""
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    check_out(name, out, shape, dtype, device)
+    return out
 
 
 def inverse(flm: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Optional[torch.Tensor] = None,
@@ -64,8 +100,7 @@ def inverse(flm: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Opt
         raise ValueError("flm must be a GPU tensor")
     f = f.to(io_dtype(p)).contiguous()
     B = f.shape[0]
-    if out is None:
-        out = torch.empty((B, L, 2 * L - 1), dtype=io_dtype(p), device=f.device)
+    out = _out(out, (B, L, 2 * L - 1), io_dtype(p), f.device)
     ws, nbytes = _workspace(L, spin, B, p, f.device, workspace)
     rc = N.load().sht_inverse(L, spin, B, N.SHT_SAMPLING_MW, p, f.data_ptr(), out.data_ptr(),
                               ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(f.device))
@@ -85,8 +120,7 @@ def forward(fmap: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Op
         raise ValueError("map must be a GPU tensor")
     g = g.to(io_dtype(p)).contiguous()
     B = g.shape[0]
-    if out is None:
-        out = torch.empty((B, L * L), dtype=io_dtype(p), device=g.device)
+    out = _out(out, (B, L * L), io_dtype(p), g.device)
     ws, nbytes = _workspace(L, spin, B, p, g.device, workspace)
     rc = N.load().sht_forward(L, spin, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
                               ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(g.device))
@@ -110,8 +144,7 @@ def inverse_real(flm: torch.Tensor, L: int, precision="fp64", out: Optional[torc
         raise ValueError("flm must be a GPU tensor")
     f = f.to(io_dtype(p)).contiguous()
     B = f.shape[0]
-    if out is None:
-        out = torch.empty((B, L, 2 * L - 1), dtype=real_dtype(p), device=f.device)
+    out = _out(out, (B, L, 2 * L - 1), real_dtype(p), f.device)
     ws, nbytes = _workspace(L, 0, B, p, f.device, workspace)
     rc = N.load().sht_inverse_real(L, B, N.SHT_SAMPLING_MW, p, f.data_ptr(), out.data_ptr(),
                                    ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(f.device))
@@ -133,8 +166,7 @@ def forward_real(fmap: torch.Tensor, L: int, precision="fp64", out: Optional[tor
         raise ValueError("forward_real takes a real map")
     g = g.to(real_dtype(p)).contiguous()
     B = g.shape[0]
-    if out is None:
-        out = torch.empty((B, L * L), dtype=io_dtype(p), device=g.device)
+    out = _out(out, (B, L * L), io_dtype(p), g.device)
     ws, nbytes = _workspace(L, 0, B, p, g.device, workspace)
     rc = N.load().sht_forward_real(L, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
                                    ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(g.device))
@@ -150,8 +182,9 @@ def spin_pair(flm_s: torch.Tensor, L: int, spin: int, precision="fp64",
     f = (flm_s.reshape(1, -1) if single else flm_s).to(io_dtype(p)).contiguous()
     if f.shape[-1] != L * L or not f.is_cuda:
         raise ValueError("flm_s must be a GPU tensor [batch, L*L]")
-    if out is None:
-        out = torch.empty_like(f)
+    out = _out(out, tuple(f.shape), f.dtype, f.device)
+    if out.data_ptr() == f.data_ptr():
+        raise ValueError("out must not be the input")
     N.check(N.load().sht_spin_pair(L, spin, f.shape[0], p, f.data_ptr(), out.data_ptr(),
                                    _stream_handle(f.device)), "sht_spin_pair")
     return out[0] if single else out
@@ -167,8 +200,7 @@ def _forward_tri(fmap, L, spin, out, workspace, entry):
         raise ValueError("map must be a GPU tensor")
     g = g.to(torch.complex128).contiguous()
     B = g.shape[0]
-    if out is None:
-        out = torch.empty((B, L * L), dtype=torch.complex128, device=g.device)
+    out = _out(out, (B, L * L), torch.complex128, g.device)
     ws, nbytes = _workspace(L, spin, B, p, g.device, workspace)
     rc = getattr(N.load(), entry)(L, spin, B, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
                                   ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(g.device))
@@ -264,7 +296,9 @@ class Graph:
         self.L, self.spin, self.batch, self.p = L, spin, batch, _prec(precision)
         dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         dt = io_dtype(self.p)
-        self.flm_in = torch.zeros((batch, L * L), dtype=dt, device=dev)
+        # every replay's input overwrites all of flm_in, so it needs no clearing
+        # (a fill here would also be unordered with the caller's own streams)
+        self.flm_in = torch.empty((batch, L * L), dtype=dt, device=dev)
         self.map = torch.empty((batch, L, 2 * L - 1), dtype=dt, device=dev)
         self.flm_out = torch.empty((batch, L * L), dtype=dt, device=dev)
         self.workspace, nbytes = _workspace(L, spin, batch, self.p, dev, None)

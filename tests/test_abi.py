@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_status_strings():
     N, lib = _lib()
     assert lib.sht_version() == 10000
-    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -99):
         assert lib.sht_status_string(code)
 
 
