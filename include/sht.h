@@ -108,6 +108,30 @@ int sht_forward(int L, int spin, int batch, int sampling, int precision,
                 void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the inverse
+ * transform of sht_inverse, with the workspace taken from a static device
+ * array of SHT_NOALLOC_SCRATCH_BYTES bytes that the library holds on each
+ * device it runs on until the process ends.  The caller still passes flm and
+ * map (layouts, alignment and precisions as for sht_inverse).
+ *   - The plan of (L, spin) must be resident on the current device: call
+ *     sht_plan_warmup (which allocates) beforehand, else SHT_ERR_NOT_READY.
+ *   - Shapes whose sht_workspace_bytes(...) exceeds SHT_NOALLOC_SCRATCH_BYTES
+ *     return SHT_ERR_WORKSPACE (e.g. L = 512 fits up to 8 maps in FP32 and 4 in
+ *     FP64).
+ *   - The call allocates nothing: no hipMalloc / hipFree, no trace events.
+ *   - Every call on one device uses that device's single array, which keeps
+ *     the previous call's contents (nothing in it needs clearing): calls that
+ *     overlap on one device (several streams, or several host threads) race
+ *     and give wrong results; serialise them.
+ * Errors as for sht_inverse, plus SHT_ERR_NOT_READY; argument, alignment and
+ * size checks run before any HIP call.
+ */
+#define SHT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sht_inverse_noalloc(int L, int spin, int batch, int sampling, int precision,
+                        const void *flm, void *map, void *stream);
+
+/*
  * Real spin-0 signals (Section 3.3): for a real map f, f_{l,-m} =
  * (-1)^m conj(f_lm), and only the orders m >= 0 are transformed (half the
  * contraction columns and half the theta-stage rows of the complex path).

@@ -57,6 +57,7 @@ struct TraceRec {
 };
 bool g_trace_on = false;
 thread_local bool t_capturing = false;  // inside sht_graph_create's capture
+thread_local bool t_noalloc = false;    // inside sht_inverse_noalloc (no trace events)
 std::mutex g_trace_mu;
 std::vector<TraceRec> g_trace_pending;
 std::vector<hipEvent_t> g_event_pool;
@@ -74,7 +75,7 @@ hipEvent_t pool_event() {
 
 // Runs `launch` (returns hipError_t), bracketed by events when tracing is on.
 template <typename F> hipError_t traced(int stage, hipStream_t st, F launch) {
-    if (!g_trace_on || t_capturing) return launch();
+    if (!g_trace_on || t_capturing || t_noalloc) return launch();
     hipEvent_t a, b;
     {
         std::lock_guard<std::mutex> lk(g_trace_mu);
@@ -190,6 +191,8 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     }
     SHT_HIP(launch_fft_tables<double>(p->f64, nullptr, st), "fft tables f64");
     SHT_HIP(launch_fft_tables<float>(p->f32, &p->f64, st), "fft tables f32");
+    SHT_HIP(prepare_row_kernels<double>(p->f64), "row kernel attributes f64");
+    SHT_HIP(prepare_row_kernels<float>(p->f32), "row kernel attributes f32");
     SHT_HIP(hipStreamSynchronize(st), "plan sync");
     g_plans[key] = p;
     *out = p;
@@ -358,9 +361,80 @@ int transform(bool inverse, bool real, int L, int spin, int batch, int sampling,
                                         st);
 }
 
+// ---- the inverse that allocates nothing (sht_inverse_noalloc) ----
+// Its workspace: one static array per device, held until the process ends.
+// In host code `scratch` names a host-side stand-in; the device address of
+// each device's copy comes from hipGetSymbolAddress (scratch_on) and only that
+// address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SHT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up on the first
+// call on that device (with it current) and kept.
+int scratch_on(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return SHT_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "scratch address");
+        if (!p) return hip_fail(hipErrorInvalidSymbol, "scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SHT_OK;
+}
+
+// The resident plans of (current device, L, spin), or SHT_ERR_NOT_READY:
+// nothing is built here.
+int find_plans(int dev, int L, int spin, DeviceState **ds, Plan **plan, SpinPlan **sp) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto d = g_devices.find(dev);
+    auto p = g_plans.find(std::make_tuple(dev, L));
+    auto q = g_spin.find(std::make_tuple(dev, L, spin));
+    if (d == g_devices.end() || p == g_plans.end() || q == g_spin.end()) return SHT_ERR_NOT_READY;
+    *ds = &d->second;
+    *plan = p->second;
+    *sp = q->second;
+    return SHT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int sht_inverse_noalloc(int L, int spin, int batch, int sampling, int precision, const void *flm, void *map,
+                        void *stream) {
+    int rc = check_args(L, spin, batch, sampling, precision);
+    if (rc != SHT_OK) return rc;
+    if (!flm || !map) return SHT_ERR_INVALID_ARG;
+    const size_t ca = 2 * elem_bytes(precision);
+    if (misaligned(flm, ca) || misaligned(map, ca)) return SHT_ERR_ALIGNMENT;
+    size_t ra, rb;
+    regions(L, batch, precision, ra, rb);
+    if (ra + rb > (size_t)SHT_NOALLOC_SCRATCH_BYTES) return SHT_ERR_WORKSPACE;
+    int dev = 0;
+    SHT_HIP(hipGetDevice(&dev), "hipGetDevice");
+    void *ws = nullptr;
+    rc = scratch_on(dev, &ws);
+    if (rc != SHT_OK) return rc;
+    DeviceState *ds;
+    Plan *plan;
+    SpinPlan *sp;
+    rc = find_plans(dev, L, spin, &ds, &plan, &sp);
+    if (rc != SHT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    t_noalloc = true;
+    rc = precision == SHT_FP64
+             ? run_inverse<double>(L, spin, batch, false, false, plan->f64, plan->rec, ds, sp, flm, map, ws, st)
+             : run_inverse<float>(L, spin, batch, precision == SHT_BF16X3, false, plan->f32, plan->rec, ds, sp, flm,
+                                  map, ws, st);
+    t_noalloc = false;
+    return rc;
+}
 
 size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precision) {
     if (check_args(L, spin, batch, sampling, precision) != SHT_OK) return 0;

@@ -895,6 +895,23 @@ hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out
     return hipGetLastError();
 }
 
+template <typename T> hipError_t prepare_row_kernels(const FftTables<T> &ft) {
+    return with_logm(ft.logM, [&](auto lm) {
+        constexpr int LM = decltype(lm)::value;
+        const size_t lds = lds_bytes(ft);
+        hipError_t e = set_lds(k_theta_inv<T, LM, true>, lds);
+        if (e == hipSuccess) e = set_lds(k_theta_inv<T, LM, false>, lds);
+        if (e == hipSuccess) e = set_lds(k_phi_inv<T, LM>, lds);
+        if (e == hipSuccess) e = set_lds(k_phi_fwd<T, LM>, lds);
+        if (e == hipSuccess) e = set_lds(k_theta_fwd<T, LM, true>, lds);
+        if (e == hipSuccess) e = set_lds(k_theta_fwd<T, LM, false>, lds);
+        if (e == hipSuccess) e = set_lds(k_phi_inv_real<T, LM>, lds);
+        if (e == hipSuccess) e = set_lds(k_phi_fwd_real<T, LM>, lds);
+        if (e == hipSuccess) e = set_lds(k_theta_dft<T, LM>, lds);
+        return e;
+    });
+}
+
 #define SHT_INST(T)                                                                                      \
     template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, bool, const T *, void *, hipStream_t); \
     template hipError_t launch_phi_inv_real<T>(const FftTables<T> &, int, const void *, T *, hipStream_t);  \
@@ -905,7 +922,8 @@ hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out
     template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, bool, const void *, T *, hipStream_t); \
     template hipError_t launch_transpose<T>(int, int, int, const void *, void *, hipStream_t);                \
     template hipError_t launch_fft_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \
-                                                  hipStream_t);
+                                                  hipStream_t);                                          \
+    template hipError_t prepare_row_kernels<T>(const FftTables<T> &);
 SHT_INST(double)
 SHT_INST(float)
 #undef SHT_INST

@@ -149,6 +149,9 @@ hipError_t launch_theta_dft(const FftTables<T> &ft, int s, int B, const void *Q,
 // out[b][c][r] = in[b][r][c] for complex T
 template <typename T>
 hipError_t launch_transpose(int B, int rows, int cols, const void *in, void *out, hipStream_t st);
+// raises the dynamic-LDS limit of every row kernel at the plan's FFT size
+// once (plan building), so that later launches set no attributes
+template <typename T> hipError_t prepare_row_kernels(const FftTables<T> &ft);
 // forward FFT (natural order) of one sequence per block, in place (plan building)
 template <typename T>
 hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows,

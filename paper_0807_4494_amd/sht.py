@@ -108,6 +108,25 @@ def inverse(flm: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Opt
     return out[0] if single else out
 
 
+def inverse_noalloc(flm: torch.Tensor, L: int, spin: int, precision, out: torch.Tensor) -> torch.Tensor:
+    """Inverse spin SHT through ``sht_inverse_noalloc``: no device memory is
+    allocated (the library's static scratch is the workspace), so ``out``
+    [batch, L, 2L-1] must be given and ``flm`` must already have the
+    precision's dtype and be contiguous; the plan of (L, spin) must be
+    resident (:func:`plan_warmup`).  Calls that overlap on one device race."""
+    p = _prec(precision)
+    if not flm.is_cuda or flm.dim() != 2 or flm.shape[-1] != L * L:
+        raise ValueError("flm must be a GPU tensor [batch, L*L]")
+    if flm.dtype != io_dtype(p) or not flm.is_contiguous():
+        raise ValueError(f"flm must be contiguous {io_dtype(p)}")
+    B = flm.shape[0]
+    check_out("out", out, (B, L, 2 * L - 1), io_dtype(p), flm.device)
+    rc = N.load().sht_inverse_noalloc(L, spin, B, N.SHT_SAMPLING_MW, p, flm.data_ptr(), out.data_ptr(),
+                                      _stream_handle(flm.device))
+    N.check(rc, "sht_inverse_noalloc")
+    return out
+
+
 def forward(fmap: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Optional[torch.Tensor] = None,
             workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Forward spin SHT: samples f(theta_t, phi_p) -> f_lm."""

@@ -156,3 +156,18 @@ def test_workspace_size_formula():
         assert lib.sht_workspace_bytes(L, 0, B, 0, p) == ra + rb
     assert lib.sht_workspace_bytes(8, 9, 1, 0, 0) == 0
     assert lib.sht_workspace_bytes(8, 0, 1, 3, 0) == 0
+
+
+def test_noalloc_argument_checks_run_before_any_hip_call():
+    N, lib = _lib()
+    fake = ctypes.c_void_p(1 << 20)
+    call = lib.sht_inverse_noalloc
+    assert call(4097, 0, 1, 0, 0, fake, fake, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 0, 1, 0, 5, fake, fake, None) == N.SHT_ERR_UNSUPPORTED
+    assert call(8, 0, 1, 0, 0, None, fake, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 0, 1, 0, 0, fake, ctypes.c_void_p((1 << 20) + 8), None) == N.SHT_ERR_ALIGNMENT
+    # beyond the static scratch: rejected by size, before any HIP call
+    assert lib.sht_workspace_bytes(1024, 0, 16, 0, 1) > N.SHT_NOALLOC_SCRATCH_BYTES
+    assert call(1024, 0, 16, 0, 1, fake, fake, None) == N.SHT_ERR_WORKSPACE
+    assert lib.sht_workspace_bytes(512, 0, 8, 0, 1) <= N.SHT_NOALLOC_SCRATCH_BYTES
+    assert lib.sht_workspace_bytes(512, 0, 9, 0, 1) > N.SHT_NOALLOC_SCRATCH_BYTES
