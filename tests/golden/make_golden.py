@@ -7,6 +7,13 @@ repository root:
     python tests/golden/make_golden.py L1024_s0pm2_b16
     python tests/golden/make_golden.py L2048_s0_b4
 
+With ``--round-trip`` it adds to an existing file, for map 0 of each spin,
+the oracle's round trip: the oracle's forward of the oracle's inverse of the
+input coefficients, sampled at the coefficients of the orders ``fwd_orders``
+(``rt_s<spin>``), and the relative l2 error of the whole round trip over all
+L^2 coefficients (``rt_rel_s<spin>``).  A test compares the samples with the
+input regenerated from its seed.
+
 For each spin of the workload it stores
   * inverse: the oracle's map of batch members ``INV_MAPS`` at ``NPIX``
     seeded random pixels (t, p);
@@ -72,11 +79,42 @@ def make(name: str) -> str:
             print(f"{name} s={s} b={b}: {time.time() - t0:.1f} s", flush=True)
         out[f"inv_s{s}"] = np.stack(inv)
         out[f"fwd_s{s}"] = np.stack(fwd)
+    out.update(round_trip(wl, idx))
     path = os.path.join(HERE, f"{name}.npz")
     np.savez_compressed(path, **out)
     return path
 
 
+def round_trip(wl, idx) -> dict:
+    """The oracle's inverse then forward of map 0 of each spin: sampled
+    coefficients and the whole round trip's relative l2 error."""
+    out = {}
+    for s in wl.spins:
+        f = wl.flm(s)[0]
+        t0 = time.time()
+        back = oracle.forward(oracle.inverse(f, wl.L, s), wl.L, s)
+        out[f"rt_s{s}"] = back[idx]
+        out[f"rt_rel_s{s}"] = np.float64(oracle.rel_l2(f, back))
+        print(f"{wl.name} s={s} round trip: rel_l2 {out[f'rt_rel_s{s}']:.3e} ({time.time() - t0:.1f} s)",
+              flush=True)
+    return out
+
+
+def add_round_trip(name: str) -> str:
+    wl = {w.name: w for w in sht_synth.WORKLOADS}[name]
+    path = os.path.join(HERE, f"{name}.npz")
+    with np.load(path) as d:
+        out = {k: d[k] for k in d.files}
+    out.update(round_trip(wl, out["fwd_index"]))
+    np.savez_compressed(path, **out)
+    return path
+
+
 if __name__ == "__main__":
-    for n in sys.argv[1:]:
-        print(make(n))
+    args = sys.argv[1:]
+    if args and args[0] == "--round-trip":
+        for n in args[1:]:
+            print(add_round_trip(n))
+    else:
+        for n in args:
+            print(make(n))

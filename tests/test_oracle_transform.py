@@ -138,6 +138,34 @@ def test_round_trip_exact(L, s):
     assert oracle.rel_l2(f, g) < 1e-13
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("L,s,spec,bar", [(256, 2, "inv_l_lp1", 1e-13), (1024, -2, "inv_lp1_sq", 1e-12)])
+def test_round_trip_at_the_configuration_sizes(L, s, spec, bar):
+    """The oracle's own round trip at the band-limits of the spin-2 and the
+    batched configurations, with their spectra: the exactness that makes the
+    oracle a valid reference there (the GPU bars are 1e-10 and 1e-5)."""
+    f = sht_synth.gaussian_flm(L, s, sht_synth.SEED_BASE + 8100 + L, spec)
+    g = oracle.forward(oracle.inverse(f, L, s), L, s)
+    err = oracle.rel_l2(f, g)
+    print(f"oracle round trip L={L} s={s}: {err:.3e}")
+    assert err <= bar
+
+
+def test_round_trip_at_the_largest_configuration_from_golden():
+    """L = 2048 (four minutes of oracle time, so stored by
+    tests/golden/make_golden.py --round-trip): the oracle's forward of its
+    inverse of map 0 equals the input coefficients, regenerated here from
+    their seed, at the stored orders, and over all L^2 coefficients."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "L2048_s0_b4.npz")
+    wl = {w.name: w for w in sht_synth.WORKLOADS}["L2048_s0_b4"]
+    with np.load(path) as d:
+        idx, rt, rel_all = d["fwd_index"], d["rt_s0"], float(d["rt_rel_s0"])
+    f = wl.flm(0)[0]
+    assert oracle.rel_l2(f[idx], rt) <= 1e-12
+    assert rel_all <= 1e-12
+
+
 def test_batch_equals_single_and_forward_rows_subset():
     L, s = 12, 1
     F = np.stack([sht_synth.gaussian_flm(L, s, 40 + b) for b in range(3)])
