@@ -60,9 +60,10 @@ extern "C" {
 #endif
 
 #define SHT_VERSION 10000          /* 1.0.0 */
-#define SHT_L_MAX 2048
+#define SHT_L_MAX 4096
 #define SHT_BATCH_MAX 64
 #define SHT_TRI_L_MAX 128          /* largest L of sht_forward_triangular */
+#define SHT_MULTI_SEG_MAX 8        /* spin segments of one sht_*_multi call */
 
 enum sht_status {
     SHT_OK = 0,
@@ -106,6 +107,25 @@ int sht_inverse(int L, int spin, int batch, int sampling, int precision,
 int sht_forward(int L, int spin, int batch, int sampling, int precision,
                 const void *map, void *flm, void *workspace, size_t ws_bytes,
                 void *stream);
+
+/*
+ * Maps of several spins at one band-limit in one call (a serving loop's
+ * same-L group): nseg segments, segment k holding batches[k] maps of spin
+ * spins[k], stored one after another in flm and map (segment 0's maps first;
+ * layouts per map as for sht_inverse / sht_forward).  The result of each map
+ * is that of sht_inverse / sht_forward at its spin; the O(L^3) contraction of
+ * every segment runs in one launch (its column blocks carry their segment's
+ * spin factors) and the phi stages in one launch over all maps.
+ *   nseg       1 <= nseg <= SHT_MULTI_SEG_MAX
+ *   spins, batches  host arrays of nseg entries: |spins[k]| < L,
+ *              batches[k] >= 1, sum of batches <= SHT_BATCH_MAX
+ *   workspace  sht_workspace_bytes(L, 0, sum of batches, sampling, precision)
+ * Errors, ownership and semantics as for sht_inverse / sht_forward.
+ */
+int sht_inverse_multi(int L, int nseg, const int *spins, const int *batches, int sampling, int precision,
+                      const void *flm, void *map, void *workspace, size_t ws_bytes, void *stream);
+int sht_forward_multi(int L, int nseg, const int *spins, const int *batches, int sampling, int precision,
+                      const void *map, void *flm, void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

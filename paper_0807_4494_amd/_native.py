@@ -25,10 +25,13 @@ SHT_ERR_NOT_READY = -8
 SHT_SAMPLING_MW = 0
 SHT_FP64, SHT_FP32, SHT_BF16X3 = 0, 1, 2
 SHT_TRI_L_MAX = 128
+SHT_MULTI_SEG_MAX = 8
+SHT_BATCH_MAX = 64
+SHT_L_MAX = 4096
 SHT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 #: every symbol include/sht.h declares
-EXPORTS = ("sht_inverse", "sht_inverse_noalloc", "sht_forward", "sht_inverse_real", "sht_forward_real", "sht_forward_triangular",
+EXPORTS = ("sht_inverse", "sht_inverse_noalloc", "sht_forward", "sht_inverse_multi", "sht_forward_multi", "sht_inverse_real", "sht_forward_real", "sht_forward_triangular",
            "sht_forward_lstsq",
            "sht_spin_pair", "sht_workspace_bytes", "sht_plan_warmup",
            "sht_plan_tables", "sht_graph_create", "sht_graph_launch", "sht_graph_destroy",
@@ -70,6 +73,10 @@ def load() -> ctypes.CDLL:
     for name in ("sht_inverse_real", "sht_forward_real"):
         f = getattr(lib, name)
         f.argtypes = [i, i, i, i, vp, vp, vp, sz, vp]
+        f.restype = i
+    for name in ("sht_inverse_multi", "sht_forward_multi"):
+        f = getattr(lib, name)
+        f.argtypes = [i, i, ctypes.POINTER(i), ctypes.POINTER(i), i, i, vp, vp, vp, sz, vp]
         f.restype = i
     lib.sht_inverse_noalloc.argtypes = [i, i, i, i, i, vp, vp, vp]
     lib.sht_inverse_noalloc.restype = i

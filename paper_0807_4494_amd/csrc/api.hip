@@ -106,7 +106,8 @@ size_t elem_bytes(int precision) { return precision == SHT_FP64 ? 8 : 4; }
 
 // Workspace: two regions, each large enough for a set of order-major panels
 // [L][4B][L] and for a B x L x N complex grid; the launch sequences below
-// alternate between them.
+// alternate between them.  Rows whose FFT buffer does not fit in LDS (FP64,
+// L > 2048) add a third region: the split rows' scratch slots.
 void regions(int L, int batch, int precision, size_t &ra, size_t &rb) {
     const size_t T = elem_bytes(precision);
     const size_t C = 4 * (size_t)batch, N = 2 * (size_t)L - 1;
@@ -114,6 +115,15 @@ void regions(int L, int batch, int precision, size_t &ra, size_t &rb) {
     const size_t grid = (size_t)batch * L * N * 2 * T;
     ra = align256(panel > grid ? panel : grid);
     rb = ra;
+}
+size_t split_region(int L, int precision) {
+    const int M = fft_size(L), cb = 2 * (int)elem_bytes(precision);
+    return rows_split(M, cb) ? align256((size_t)kSplitSlots * M * cb) : 0;
+}
+size_t workspace_total(int L, int batch, int precision) {
+    size_t ra, rb;
+    regions(L, batch, precision, ra, rb);
+    return ra + rb + split_region(L, precision);
 }
 
 int check_args(int L, int spin, int batch, int sampling, int precision) {
@@ -147,7 +157,10 @@ template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
     ft.M = fft_size(L);
     ft.logM = ilog2(ft.M);
     const size_t nptw = (size_t)fft_pass_offset(ft.logM, fft_npass(ft.logM));
-    const size_t n = (size_t)ft.M + 2 * (size_t)ft.N + 2 * (size_t)ft.N + nptw + 3 * (size_t)ft.M;
+    // split rows (two M/2-point halves) also need the M/2-point pass twiddles
+    const bool split = rows_split(ft.M, 2 * (int)sizeof(T));
+    const size_t nptwh = split ? (size_t)fft_pass_offset(ft.logM - 1, fft_npass(ft.logM - 1)) : 0;
+    const size_t n = (size_t)ft.M + 2 * (size_t)ft.N + 2 * (size_t)ft.N + nptw + 3 * (size_t)ft.M + nptwh;
     C *base = nullptr;
     if (hipMalloc(&base, n * sizeof(C)) != hipSuccess) return SHT_ERR_OOM;
     ft.tw = base;
@@ -158,6 +171,7 @@ template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
     ft.h_ip = ft.ptw + nptw;
     ft.h_fd = ft.h_ip + ft.M;
     ft.h_fk = ft.h_fd + ft.M;
+    ft.ptwh = split ? ft.h_fk + ft.M : nullptr;
     return SHT_OK;
 }
 
@@ -244,9 +258,7 @@ int check_buffers(int L, int batch, int precision, const void *in, const void *o
     if (!in || !out || !ws) return SHT_ERR_INVALID_ARG;
     const size_t ca = 2 * elem_bytes(precision);
     if (misaligned(in, ca) || misaligned(out, ca) || misaligned(ws, 256)) return SHT_ERR_ALIGNMENT;
-    size_t ra, rb;
-    regions(L, batch, precision, ra, rb);
-    if (ws_bytes < ra + rb) return SHT_ERR_WORKSPACE;
+    if (ws_bytes < workspace_total(L, batch, precision)) return SHT_ERR_WORKSPACE;
     return SHT_OK;
 }
 
@@ -257,108 +269,162 @@ int check_buffers_real(bool inverse, int L, int batch, int precision, const void
     const size_t e = elem_bytes(precision);
     const void *flm = inverse ? in : out, *map = inverse ? out : in;
     if (misaligned(flm, 2 * e) || misaligned(map, e) || misaligned(ws, 256)) return SHT_ERR_ALIGNMENT;
-    size_t ra, rb;
-    regions(L, batch, precision, ra, rb);
-    if (ws_bytes < ra + rb) return SHT_ERR_WORKSPACE;
+    if (ws_bytes < workspace_total(L, batch, precision)) return SHT_ERR_WORKSPACE;
     return SHT_OK;
 }
 
+// One spin's maps within a call: `B` maps, stored after the maps of the
+// earlier segments; their contraction columns follow those segments' too.
+struct Seg {
+    int spin, B;
+    const SpinPlan *sp;
+};
+constexpr int kMaxSegs = SHT_MULTI_SEG_MAX;
+
 // The contraction in the path's own precision, or as BF16x3 on FP32 data,
-// over C columns.
+// over every segment's columns in one launch.
 template <typename T>
-hipError_t contract(int mode, bool bf16x3, int L, int spin, int C, const T *X, T *Y, const DeviceState *ds,
-                    const SpinPlan *sp, const RecTables &rec, hipStream_t st) {
+hipError_t contract(int mode, bool bf16x3, int L, int nq, int nseg, const Seg *seg, const T *X, T *Y,
+                    const DeviceState *ds, const RecTables &rec, hipStream_t st) {
+    ContractSeg cs[kMaxSegs];
+    for (int k = 0; k < nseg; ++k) cs[k] = ContractSeg{nq * seg[k].B, seg[k].sp};
     if constexpr (sizeof(T) == 4) {
-        if (bf16x3) return launch_contract_bf16x3(mode, L, spin, C, X, Y, ds->E, *sp, rec, st);
+        if (bf16x3) return launch_contract_bf16x3(mode, L, nseg, cs, X, Y, ds->E, rec, st);
     }
-    return launch_contract<T>(mode, L, spin, C, X, Y, ds->E, *sp, rec, st);
+    return launch_contract<T>(mode, L, nseg, cs, X, Y, ds->E, rec, st);
 }
 
 // real: spin-0 real maps; only the orders m >= 0 are carried (2 columns per
 // map, L theta rows), and the phi stages read / write real rings.
+// The layout and theta stages run per segment (their spin enters the
+// phases and the parity extension), the contraction and the phi stages once
+// over all maps.
 template <typename T>
-int run_inverse(int L, int spin, int batch, bool bf16x3, bool real, const FftTables<T> &ft, const RecTables &rec,
-                const DeviceState *ds, const SpinPlan *sp, const void *flm, void *map, void *ws, hipStream_t st) {
+int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const FftTables<T> &ft,
+                const RecTables &rec, const DeviceState *ds, const void *flm, void *map, void *ws, hipStream_t st) {
+    int batch = 0;
+    for (int k = 0; k < nseg; ++k) batch += seg[k].B;
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
     T *P = (T *)w;            // region A: layout panels, later the theta-stage output
     T *R = (T *)(w + ra);     // region B: contraction output
-    const int C = (real ? 2 : 4) * batch;
-    SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st,
-                   [&] { return launch_layout_in<T>(L, spin, batch, real, flm, P, st); }),
-            "layout_in");
+    void *scr = w + ra + rb;  // split-row scratch (L > 2048, FP64)
+    const int nq = real ? 2 : 4, Cn = nq * batch;
+    const size_t cb = 2 * sizeof(T);                           // bytes per complex
+    const size_t ring = (size_t)L * (real ? L : 2 * L - 1);    // ring entries per map (theta stage output)
+    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
+        const void *f = (const unsigned char *)flm + (size_t)off * L * L * cb;
+        SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st,
+                       [&] { return launch_layout_in<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, real, f, P, st); }),
+                "layout_in");
+    }
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
-                   [&] { return contract<T>(kInverse, bf16x3, L, spin, C, P, R, ds, sp, rec, st); }),
+                   [&] { return contract<T>(kInverse, bf16x3, L, nq, nseg, seg, P, R, ds, rec, st); }),
             "contract inverse");
     // theta stage writes g_mu(theta_t) straight into the rings over mu that
     // the phi stage reads (region A; the panels are no longer needed)
-    SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
-                   [&] { return launch_theta_inv<T>(ft, spin, batch, real, R, (void *)P, st); }),
-            "theta inverse");
+    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
+        void *g = (unsigned char *)P + (size_t)off * ring * cb;
+        SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
+                       [&] {
+                           return launch_theta_inv<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, real, R, g, scr, st);
+                       }),
+                "theta inverse");
+    }
     SHT_HIP(traced(SHT_STAGE_PHI_INV, st,
                    [&] {
-                       return real ? launch_phi_inv_real<T>(ft, batch, (const void *)P, (T *)map, st)
-                                   : launch_phi_inv<T>(ft, batch, (const void *)P, map, st);
+                       return real ? launch_phi_inv_real<T>(ft, batch, (const void *)P, (T *)map, scr, st)
+                                   : launch_phi_inv<T>(ft, batch, (const void *)P, map, scr, st);
                    }),
             "phi inverse");
     return SHT_OK;
 }
 
 template <typename T>
-int run_forward(int L, int spin, int batch, bool bf16x3, bool real, const FftTables<T> &ft, const RecTables &rec,
-                const DeviceState *ds, const SpinPlan *sp, const void *map, void *flm, void *ws, hipStream_t st) {
+int run_forward(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const FftTables<T> &ft,
+                const RecTables &rec, const DeviceState *ds, const void *map, void *flm, void *ws, hipStream_t st) {
+    int batch = 0;
+    for (int k = 0; k < nseg; ++k) batch += seg[k].B;
     size_t ra, rb;
     regions(L, batch, sizeof(T) == 8 ? SHT_FP64 : SHT_FP32, ra, rb);
     unsigned char *w = (unsigned char *)ws;
     void *Q = (void *)(w + ra);   // region B: phi-stage output (rings over mu)
     T *X = (T *)w;                // region A: weighted theta coefficients
-    const int C = (real ? 2 : 4) * batch;
+    void *scr = w + ra + rb;      // split-row scratch (L > 2048, FP64)
+    const int nq = real ? 2 : 4, Cn = nq * batch;
+    const size_t cb = 2 * sizeof(T);
+    const size_t ring = (size_t)L * (real ? L : 2 * L - 1);
     SHT_HIP(traced(SHT_STAGE_PHI_FWD, st,
                    [&] {
-                       return real ? launch_phi_fwd_real<T>(ft, batch, (const T *)map, Q, st)
-                                   : launch_phi_fwd<T>(ft, batch, map, Q, st);
+                       return real ? launch_phi_fwd_real<T>(ft, batch, (const T *)map, Q, scr, st)
+                                   : launch_phi_fwd<T>(ft, batch, map, Q, scr, st);
                    }),
             "phi forward");
     // the theta stage reads its two orders as columns of the rings in place
-    SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
-                   [&] { return launch_theta_fwd<T>(ft, spin, batch, real, (const void *)Q, X, st); }),
-            "theta forward");
+    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
+        const void *q = (const unsigned char *)Q + (size_t)off * ring * cb;
+        SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
+                       [&] {
+                           return launch_theta_fwd<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, real, q, X, scr, st);
+                       }),
+                "theta forward");
+    }
     T *R = (T *)(w + ra);
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
-                   [&] { return contract<T>(kForward, bf16x3, L, spin, C, X, R, ds, sp, rec, st); }),
+                   [&] { return contract<T>(kForward, bf16x3, L, nq, nseg, seg, X, R, ds, rec, st); }),
             "contract forward");
-    SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st,
-                   [&] { return launch_layout_out<T>(L, spin, batch, real, R, flm, st); }),
-            "layout_out");
+    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
+        void *f = (unsigned char *)flm + (size_t)off * L * L * cb;
+        SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st,
+                       [&] { return launch_layout_out<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, real, R, f, st); }),
+                "layout_out");
+    }
     return SHT_OK;
+}
+
+// The transform of nseg spin segments (spins[k], batches[k] maps each, in
+// that order in the caller's buffers).
+int transform_segs(bool inverse, bool real, int L, int nseg, const int *spins, const int *batches, int sampling,
+                   int precision, const void *in, void *out, void *workspace, size_t ws_bytes, void *stream) {
+    if (nseg < 1 || nseg > kMaxSegs || !spins || !batches) return SHT_ERR_INVALID_ARG;
+    int batch = 0;
+    for (int k = 0; k < nseg; ++k) {
+        if (batches[k] < 1) return SHT_ERR_INVALID_ARG;
+        batch += batches[k];
+        if (batch > SHT_BATCH_MAX) return SHT_ERR_INVALID_ARG;
+        const int rc = check_args(L, spins[k], batches[k], sampling, precision);
+        if (rc != SHT_OK) return rc;
+        if (real && spins[k] != 0) return SHT_ERR_INVALID_ARG;
+    }
+    int rc = real ? check_buffers_real(inverse, L, batch, precision, in, out, workspace, ws_bytes)
+                  : check_buffers(L, batch, precision, in, out, workspace, ws_bytes);
+    if (rc != SHT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    DeviceState *ds = nullptr;
+    Plan *plan = nullptr;
+    Seg seg[kMaxSegs];
+    for (int k = 0; k < nseg; ++k) {
+        SpinPlan *sp;
+        rc = prepare(L, spins[k], st, &ds, &plan, &sp);
+        if (rc != SHT_OK) return rc;
+        seg[k] = Seg{spins[k], batches[k], sp};
+    }
+    const bool bf = precision == SHT_BF16X3;
+    if (precision == SHT_FP64) {
+        return inverse ? run_inverse<double>(L, nseg, seg, false, real, plan->f64, plan->rec, ds, in, out,
+                                             workspace, st)
+                       : run_forward<double>(L, nseg, seg, false, real, plan->f64, plan->rec, ds, in, out,
+                                             workspace, st);
+    }
+    return inverse ? run_inverse<float>(L, nseg, seg, bf, real, plan->f32, plan->rec, ds, in, out, workspace, st)
+                   : run_forward<float>(L, nseg, seg, bf, real, plan->f32, plan->rec, ds, in, out, workspace, st);
 }
 
 int transform(bool inverse, bool real, int L, int spin, int batch, int sampling, int precision, const void *in,
               void *out, void *workspace, size_t ws_bytes, void *stream) {
-    int rc = check_args(L, spin, batch, sampling, precision);
-    if (rc != SHT_OK) return rc;
-    if (real && spin != 0) return SHT_ERR_INVALID_ARG;
-    rc = real ? check_buffers_real(inverse, L, batch, precision, in, out, workspace, ws_bytes)
-              : check_buffers(L, batch, precision, in, out, workspace, ws_bytes);
-    if (rc != SHT_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    DeviceState *ds;
-    Plan *plan;
-    SpinPlan *sp;
-    rc = prepare(L, spin, st, &ds, &plan, &sp);
-    if (rc != SHT_OK) return rc;
-    const bool bf = precision == SHT_BF16X3;
-    if (precision == SHT_FP64) {
-        return inverse ? run_inverse<double>(L, spin, batch, false, real, plan->f64, plan->rec, ds, sp, in, out,
-                                             workspace, st)
-                       : run_forward<double>(L, spin, batch, false, real, plan->f64, plan->rec, ds, sp, in, out,
-                                             workspace, st);
-    }
-    return inverse ? run_inverse<float>(L, spin, batch, bf, real, plan->f32, plan->rec, ds, sp, in, out, workspace,
-                                        st)
-                   : run_forward<float>(L, spin, batch, bf, real, plan->f32, plan->rec, ds, sp, in, out, workspace,
-                                        st);
+    return transform_segs(inverse, real, L, 1, &spin, &batch, sampling, precision, in, out, workspace, ws_bytes,
+                          stream);
 }
 
 // ---- the inverse that allocates nothing (sht_inverse_noalloc) ----
@@ -413,9 +479,7 @@ int sht_inverse_noalloc(int L, int spin, int batch, int sampling, int precision,
     if (!flm || !map) return SHT_ERR_INVALID_ARG;
     const size_t ca = 2 * elem_bytes(precision);
     if (misaligned(flm, ca) || misaligned(map, ca)) return SHT_ERR_ALIGNMENT;
-    size_t ra, rb;
-    regions(L, batch, precision, ra, rb);
-    if (ra + rb > (size_t)SHT_NOALLOC_SCRATCH_BYTES) return SHT_ERR_WORKSPACE;
+    if (workspace_total(L, batch, precision) > (size_t)SHT_NOALLOC_SCRATCH_BYTES) return SHT_ERR_WORKSPACE;
     int dev = 0;
     SHT_HIP(hipGetDevice(&dev), "hipGetDevice");
     void *ws = nullptr;
@@ -427,20 +491,19 @@ int sht_inverse_noalloc(int L, int spin, int batch, int sampling, int precision,
     rc = find_plans(dev, L, spin, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
+    const Seg one{spin, batch, sp};
     t_noalloc = true;
     rc = precision == SHT_FP64
-             ? run_inverse<double>(L, spin, batch, false, false, plan->f64, plan->rec, ds, sp, flm, map, ws, st)
-             : run_inverse<float>(L, spin, batch, precision == SHT_BF16X3, false, plan->f32, plan->rec, ds, sp, flm,
-                                  map, ws, st);
+             ? run_inverse<double>(L, 1, &one, false, false, plan->f64, plan->rec, ds, flm, map, ws, st)
+             : run_inverse<float>(L, 1, &one, precision == SHT_BF16X3, false, plan->f32, plan->rec, ds, flm, map, ws,
+                                  st);
     t_noalloc = false;
     return rc;
 }
 
 size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precision) {
     if (check_args(L, spin, batch, sampling, precision) != SHT_OK) return 0;
-    size_t ra, rb;
-    regions(L, batch, precision, ra, rb);
-    return ra + rb;
+    return workspace_total(L, batch, precision);
 }
 
 int sht_inverse(int L, int spin, int batch, int sampling, int precision, const void *flm, void *map,
@@ -451,6 +514,18 @@ int sht_inverse(int L, int spin, int batch, int sampling, int precision, const v
 int sht_forward(int L, int spin, int batch, int sampling, int precision, const void *map, void *flm,
                 void *workspace, size_t ws_bytes, void *stream) {
     return transform(false, false, L, spin, batch, sampling, precision, map, flm, workspace, ws_bytes, stream);
+}
+
+int sht_inverse_multi(int L, int nseg, const int *spins, const int *batches, int sampling, int precision,
+                      const void *flm, void *map, void *workspace, size_t ws_bytes, void *stream) {
+    return transform_segs(true, false, L, nseg, spins, batches, sampling, precision, flm, map, workspace, ws_bytes,
+                          stream);
+}
+
+int sht_forward_multi(int L, int nseg, const int *spins, const int *batches, int sampling, int precision,
+                      const void *map, void *flm, void *workspace, size_t ws_bytes, void *stream) {
+    return transform_segs(false, false, L, nseg, spins, batches, sampling, precision, map, flm, workspace, ws_bytes,
+                          stream);
 }
 
 int sht_inverse_real(int L, int batch, int sampling, int precision, const void *flm, void *map, void *workspace,
@@ -482,7 +557,7 @@ int sht_forward_triangular(int L, int spin, int batch, int sampling, int precisi
     void *A = (void *)w;         // phi-stage output, later the torus coefficients
     void *Bq = (void *)(w + ra); // the same rows over t
     const FftTables<double> &ft = plan->f64;
-    SHT_HIP(launch_phi_fwd<double>(ft, batch, map, A, st), "phi forward");
+    SHT_HIP(launch_phi_fwd<double>(ft, batch, map, A, nullptr, st), "phi forward");
     SHT_HIP(launch_transpose<double>(batch, L, ft.N, A, Bq, st), "transpose");
     SHT_HIP(launch_theta_dft<double>(ft, spin, batch, Bq, A, st), "theta dft");
     SHT_HIP(launch_tri_solve(L, spin, batch, A, flm, ds->E, *sp, plan->rec, st), "triangular solve");
@@ -508,7 +583,7 @@ int sht_forward_lstsq(int L, int spin, int batch, int sampling, int precision, c
     void *A = (void *)w;         // phi-stage output, later the torus coefficients
     void *Bq = (void *)(w + ra); // the same rows over t
     const FftTables<double> &ft = plan->f64;
-    SHT_HIP(launch_phi_fwd<double>(ft, batch, map, A, st), "phi forward");
+    SHT_HIP(launch_phi_fwd<double>(ft, batch, map, A, nullptr, st), "phi forward");
     SHT_HIP(launch_transpose<double>(batch, L, ft.N, A, Bq, st), "transpose");
     SHT_HIP(launch_theta_dft<double>(ft, spin, batch, Bq, A, st), "theta dft");
     SHT_HIP(launch_tri_lstsq(L, spin, batch, A, flm, ds->E, *sp, plan->rec, st), "least-squares solve");
@@ -601,7 +676,7 @@ int sht_tune(int L, int spin, int batch, int precision, void *workspace, size_t 
     if (misaligned(workspace, 256)) return SHT_ERR_ALIGNMENT;
     size_t ra, rb;
     regions(L, batch, precision, ra, rb);
-    if (ws_bytes < ra + rb) return SHT_ERR_WORKSPACE;
+    if (ws_bytes < workspace_total(L, batch, precision)) return SHT_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     DeviceState *ds;
     Plan *plan;
@@ -630,13 +705,14 @@ int sht_tune(int L, int spin, int batch, int precision, void *workspace, size_t 
         float ms = 0.0f;
         for (int rep = 0; rep < 3 && rc == SHT_OK; ++rep) {  // rep 0 warms up
             hipError_t e = hipEventRecord(e0, st);
+            const Seg one{spin, batch, sp};
             for (int mode = 0; mode < 2 && e == hipSuccess; ++mode) {
                 if (f64)
-                    e = launch_contract<double>(mode, L, spin, C, (const double *)w, (double *)(w + ra), ds->E, *sp,
-                                                plan->rec, st);
+                    e = contract<double>(mode, false, L, 4, 1, &one, (const double *)w, (double *)(w + ra), ds,
+                                         plan->rec, st);
                 else
-                    e = contract<float>(mode, bf, L, spin, C, (const float *)w, (float *)(w + ra), ds, sp,
-                                        plan->rec, st);
+                    e = contract<float>(mode, bf, L, 4, 1, &one, (const float *)w, (float *)(w + ra), ds, plan->rec,
+                                        st);
             }
             if (e == hipSuccess) e = hipEventRecord(e1, st);
             if (e == hipSuccess) e = hipEventSynchronize(e1);

@@ -139,18 +139,25 @@ template <int CTILE> struct Slabs<kPBF, CTILE, false> {
     alignas(16) unsigned short Xl[2][GM][CTILE][TK + 4];
 };
 
+// Column blocks of one launch: block y takes columns [c0[y], c0[y] + CTILE)
+// clipped to cend[y] (the end of its spin's columns), with that spin's
+// factor table, |s| and (table mode) cached table.  One launch can so serve
+// the maps of several spins at one L.
+constexpr int kMaxColBlocks = 32;
+
 template <typename T> struct Args {
-    int L, s, C;          // C columns (4 per map; 2 per map for real signals)
+    int L, C;             // C columns in all (4 per map; 2 per map for real signals)
     int njt, ncb;         // j tiles, column blocks
     const T *X;           // [L][C][L]
     T *Y;                 // [L][C][L]
     EdgeTable E;
     const double2 *jtab;  // [L][L] j-side step factors at [k][j] (jti or jtf)
-    const T *wtab;        // [L][L] spin factor at [k][j] (wi or wf)
     const double2 *fab;   // [L][L] order-side l-recursion factors
     const double *cl;     // [L] sqrt((2l+1)/4pi)
-    const T *mtab;        // table mode: M_m(m', l) at [m][l][m'] (plan's cached table)
     const int *sched;     // workgroup order: (group << 8) | j tile, longest K loop first
+    const T *wtab[kMaxColBlocks];  // [L][L] spin factor at [k][j] (wi or wf) of block y's spin
+    const T *mtab[kMaxColBlocks];  // table mode: M_m(m', l) at [m][l][m'] (plan's cached table)
+    int c0[kMaxColBlocks], cend[kMaxColBlocks], asg[kMaxColBlocks];
 };
 
 // TAB: the producers copy the slab of M from the plan's cached table instead
@@ -174,14 +181,14 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
     __shared__ Slabs<P, CTILE, KP> sm;
     __shared__ double fam[2][GM][TK], fbm[2][GM][TK];
 
-    const int L = a.L, s = a.s, Cn = a.C;
-    const int asg = s < 0 ? -s : s;
+    const int L = a.L, Cn = a.C;
     // Workgroup x takes the x-th (order group, j tile) pair of the plan's
     // schedule, longest K loop first, so the short ones fill the tail; the
     // column block is blockIdx.y.
     const int code = a.sched[blockIdx.x];
     const int mg = code >> 8, jt = code & 255, cb = (int)blockIdx.y;
-    const int m0 = mg * GM, j0 = jt * TJ, c0 = cb * CTILE;
+    const int m0 = mg * GM, j0 = jt * TJ, c0 = a.c0[cb], cend = a.cend[cb], asg = a.asg[cb];
+    const T *wtab = a.wtab[cb], *mtab = a.mtab[cb];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool producer = tid >= NC;
 
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                     const bool ok = chunk < nchunks && j < L && m < L && k >= 0 && k < L;
                     size_t idx = 0;
                     if (ok) idx = MODE == kInverse ? ((size_t)m * L + k) * L + j : ((size_t)m * L + j) * L + k;
-                    dst[g][kk] = ok ? a.mtab[idx] : T(0);
+                    dst[g][kk] = ok ? mtab[idx] : T(0);
                 }
             }
         };
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         const __amdgpu_buffer_rsrc_t jrs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(a.jtab - (size_t)kTabPad * L), (short)0, prow * L * (int)sizeof(double2), kBufWord3);
         const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(a.wtab - (size_t)kTabPad * L), (short)0, prow * L * (int)sizeof(T), kBufWord3);
+            (void *)(wtab - (size_t)kTabPad * L), (short)0, prow * L * (int)sizeof(T), kBufWord3);
         const unsigned jvo = jo * (unsigned)sizeof(double2), wvo = jo * (unsigned)sizeof(T);
         // padded row of the next step to load, in processing order
         const int krow0 = kbase_of(0) + (MODE == kInverse ? 0 : TK - 1) + kTabPad;
@@ -536,7 +543,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         }
         xg[i] = g;
         xkk[i] = kk;
-        xok[i] = (m0 + g) < L && (c0 + c) < Cn;
+        xok[i] = (m0 + g) < L && (c0 + c) < cend;
         xoff[i] = (g * Cn + c0 + c) * L + kk;
         xsl[i] = (g * CTILE + c) * XROW + kk;
     }
@@ -756,16 +763,16 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                 for (int r = 0; r < 4; ++r) {
                     const int c = c0 + ci * 16 + Mfma<T>::row(lane, r);
                     const int jj = j0 + wave * WJ + ji * 16 + (lane & 15);
-                    if (c < Cn && jj < L) yrow[c * L + jj] = acc[g][ci][ji][r];
+                    if (c < cend && jj < L) yrow[c * L + jj] = acc[g][ci][ji][r];
                 }
     }
 }
 
 template <int P, int MODE, int CTILE>
-hipError_t launch_one(Args<typename Prec<P>::T> a, int nsched, hipStream_t st) {
-    if (nsched == 0) return hipSuccess;
+hipError_t launch_one(Args<typename Prec<P>::T> a, int nsched, bool tab, hipStream_t st) {
+    if (nsched == 0 || a.ncb == 0) return hipSuccess;
     const dim3 grid(nsched, a.ncb);
-    if (a.mtab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true>), grid, dim3(NT), 0, st, a);
+    if (tab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true>), grid, dim3(NT), 0, st, a);
     else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false>), grid, dim3(NT), 0, st, a);
     return hipGetLastError();
 }
@@ -818,7 +825,11 @@ __global__ void k_mtable(int L, EdgeTable E, const double *ri, const double2 *fa
 std::mutex g_tile_mu;
 std::map<std::tuple<int, int, int, int>, int> g_tiles;
 
-int contract_tile(int L, int C, int P) {
+// (several spins: the cost is summed over their column ranges; a pinned tile
+// is looked up under the total column count)
+int contract_tile(int L, int nseg, const ContractSeg *seg, int P) {
+    int C = 0;
+    for (int k = 0; k < nseg; ++k) C += seg[k].ncol;
     int dev = 0;
     (void)hipGetDevice(&dev);
     {
@@ -829,7 +840,8 @@ int contract_tile(int L, int C, int P) {
     int best = 16;
     long best_cost = -1;
     for (int t = 16; t <= 64; t *= 2) {
-        const long cost = (long)((C + t - 1) / t) * (t + 24);
+        long cost = 0;
+        for (int k = 0; k < nseg; ++k) cost += (long)((seg[k].ncol + t - 1) / t) * (t + 24);
         if (best_cost < 0 || cost < best_cost) {
             best = t;
             best_cost = cost;
@@ -839,49 +851,72 @@ int contract_tile(int L, int C, int P) {
 }
 
 template <int P>
-hipError_t launch_prec(int mode, int L, int s, int C, const typename Prec<P>::T *X, typename Prec<P>::T *Y,
-                       const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
+hipError_t launch_prec(int mode, int L, int nseg, const ContractSeg *seg, const typename Prec<P>::T *X,
+                       typename Prec<P>::T *Y, const EdgeTable &E, const RecTables &rt, hipStream_t st) {
     using T = typename Prec<P>::T;
     Args<T> a;
     a.L = L;
-    a.s = s;
-    a.C = C;
+    a.C = 0;
+    for (int k = 0; k < nseg; ++k) a.C += seg[k].ncol;
     a.njt = (L + Prec<P>::TJ - 1) / Prec<P>::TJ;
     a.X = X;
     a.Y = Y;
     a.E = E;
     a.jtab = mode == kInverse ? rt.jti : rt.jtf;
-    if constexpr (P == kP64) a.wtab = mode == kInverse ? sp.wi : sp.wf;
-    else a.wtab = mode == kInverse ? sp.wi32 : sp.wf32;
     a.fab = rt.fab;
     a.cl = rt.cl;
-    if constexpr (P == kP64) a.mtab = sp.mtab64;
-    else a.mtab = sp.mtab32;
     const int cls = Prec<P>::TJ == 64 ? 0 : 1;
     a.sched = rt.sched[mode][cls];
     const int ns = rt.nsched[mode][cls];
-    const int ct = contract_tile(L, C, P);
-    a.ncb = (a.C + ct - 1) / ct;
+    const int ct = contract_tile(L, nseg, seg, P);
+    // column blocks, spin by spin; table mode only when every spin has its table
+    bool tab = true;
+    int nb = 0, c = 0;
+    for (int k = 0; k < nseg; ++k) {
+        const SpinPlan &sp = *seg[k].sp;
+        const T *w, *mt;
+        if constexpr (P == kP64) {
+            w = mode == kInverse ? sp.wi : sp.wf;
+            mt = sp.mtab64;
+        } else {
+            w = mode == kInverse ? sp.wi32 : sp.wf32;
+            mt = sp.mtab32;
+        }
+        tab = tab && mt != nullptr;
+        for (int c0 = 0; c0 < seg[k].ncol; c0 += ct) {
+            if (nb == kMaxColBlocks) return hipErrorInvalidValue;
+            a.c0[nb] = c + c0;
+            a.cend[nb] = c + seg[k].ncol;
+            a.asg[nb] = sp.spin < 0 ? -sp.spin : sp.spin;
+            a.wtab[nb] = w;
+            a.mtab[nb] = mt;
+            ++nb;
+        }
+        c += seg[k].ncol;
+    }
+    a.ncb = nb;
     if (ct == 16)
-        return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, st) : launch_one<P, kForward, 16>(a, ns, st);
+        return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, tab, st)
+                                : launch_one<P, kForward, 16>(a, ns, tab, st);
     if (ct == 32)
-        return mode == kInverse ? launch_one<P, kInverse, 32>(a, ns, st) : launch_one<P, kForward, 32>(a, ns, st);
-    return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, st) : launch_one<P, kForward, 64>(a, ns, st);
+        return mode == kInverse ? launch_one<P, kInverse, 32>(a, ns, tab, st)
+                                : launch_one<P, kForward, 32>(a, ns, tab, st);
+    return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, tab, st) : launch_one<P, kForward, 64>(a, ns, tab, st);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_contract(int mode, int L, int s, int C, const T *X, T *Y, const EdgeTable &E,
-                           const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
+hipError_t launch_contract(int mode, int L, int nseg, const ContractSeg *seg, const T *X, T *Y, const EdgeTable &E,
+                           const RecTables &rt, hipStream_t st) {
     constexpr int P = sizeof(T) == 8 ? kP64 : kP32;
-    return launch_prec<P>(mode, L, s, C, X, Y, E, sp, rt, st);
+    return launch_prec<P>(mode, L, nseg, seg, X, Y, E, rt, st);
 }
 
-template hipError_t launch_contract<double>(int, int, int, int, const double *, double *, const EdgeTable &,
-                                            const SpinPlan &, const RecTables &, hipStream_t);
-template hipError_t launch_contract<float>(int, int, int, int, const float *, float *, const EdgeTable &,
-                                           const SpinPlan &, const RecTables &, hipStream_t);
+template hipError_t launch_contract<double>(int, int, int, const ContractSeg *, const double *, double *,
+                                            const EdgeTable &, const RecTables &, hipStream_t);
+template hipError_t launch_contract<float>(int, int, int, const ContractSeg *, const float *, float *,
+                                           const EdgeTable &, const RecTables &, hipStream_t);
 
 int build_contract_schedules(int L, RecTables &rt) {
     static_assert(Prec<kP64>::TJ == 64 && Prec<kP32>::TJ == 128 && Prec<kPBF>::TJ == 128, "tile classes");
@@ -928,9 +963,9 @@ hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const Re
     return hipGetLastError();
 }
 
-hipError_t launch_contract_bf16x3(int mode, int L, int s, int C, const float *X, float *Y, const EdgeTable &E,
-                                  const SpinPlan &sp, const RecTables &rt, hipStream_t st) {
-    return launch_prec<kPBF>(mode, L, s, C, X, Y, E, sp, rt, st);
+hipError_t launch_contract_bf16x3(int mode, int L, int nseg, const ContractSeg *seg, const float *X, float *Y,
+                                  const EdgeTable &E, const RecTables &rt, hipStream_t st) {
+    return launch_prec<kPBF>(mode, L, nseg, seg, X, Y, E, rt, st);
 }
 
 int contract_precision_class(bool fp64, bool bf16x3) { return fp64 ? kP64 : (bf16x3 ? kPBF : kP32); }
@@ -944,6 +979,9 @@ void set_contract_tile(int L, int C, int pclass, int ctile) {
     else g_tiles[key] = ctile;
 }
 
-int get_contract_tile(int L, int C, int pclass) { return contract_tile(L, C, pclass); }
+int get_contract_tile(int L, int C, int pclass) {
+    const ContractSeg one{C, nullptr};
+    return contract_tile(L, 1, &one, pclass);
+}
 
 }  // namespace sht

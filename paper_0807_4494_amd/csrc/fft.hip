@@ -24,10 +24,20 @@ namespace sht {
 
 namespace {
 
-constexpr int kMaxRowThreads = 512;  // M / 16 threads per row, M <= 8192
+constexpr int kMaxRowThreads = 512;
 
-// Threads per row: each thread owns 16 of the M points in every pass.
-inline int row_threads(int M) { return M / 16 < 64 ? 64 : M / 16; }
+// Threads per row: M / 16 (each thread owns 16 of the M points in every
+// pass), at least one wave, at most kMaxRowThreads (M = 16384: two groups of
+// 16 points per thread).
+__host__ __device__ constexpr int row_threads(int M) {
+    return M / 16 < 64 ? 64 : (M / 16 > kMaxRowThreads ? kMaxRowThreads : M / 16);
+}
+
+// Rows whose M-point buffer (with its pad slots) exceeds the LDS of a CU
+// (FP64 at M = 16384) run as two M/2-point halves (convolve_split below).
+template <typename T, int LOGM> __host__ __device__ constexpr bool split_rows() {
+    return rows_split(1 << LOGM, 2 * (int)sizeof(T));
+}
 
 // Workgroups are dealt to the 8 XCDs round-robin; this maps workgroup i to
 // the work item it takes so that each XCD runs one contiguous range of items
@@ -209,7 +219,7 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
     constexpr int LOGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
     constexpr int M = 1 << LOGM;
     constexpr int nb = M >> LOGR;
-    constexpr int nt = (M / 16) < 64 ? 64 : (M / 16);  // threads per row
+    constexpr int nt = row_threads(M);                  // threads per row
     constexpr int NP = (nb + nt - 1) / nt;               // butterflies per thread
     constexpr int logNs = LOGNS;
     constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
@@ -341,6 +351,75 @@ __device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typena
         [&st](int k, C x, A a) { st(k, conj(x), a); });
 }
 
+// The same convolution for rows whose M-point buffer does not fit in LDS,
+// as two independent M/2-point cyclic convolutions (decimation in frequency
+// of the forward transform, in time of the inverse).  With w = e^{-2 pi i/M}
+// and the input vanishing from M/2 on,
+//   X[2k]   = FFT_{M/2}(x)[k],          X[2k+1] = FFT_{M/2}(x w^n)[k],
+//   y[n]    = a[n] + w^{-n} b[n]  (n < M/2),
+//   a = IDFT_{M/2}(X_even H_even),       b = IDFT_{M/2}(X_odd H_odd)
+// (unnormalised inverse sums; H carries 1/M).  LDS holds one M/2-point
+// buffer; the workgroup's global scratch slot holds the input (xs: ld may
+// read the LDS buffer the halves overwrite) and a (as) between the halves.
+// Visibility of the slot across the workgroup's threads comes from the
+// barriers that close every pass.  Same ld / pre / st contract as convolve.
+template <int LOGH, typename T, typename Ld, typename Pre, typename St>
+__device__ __forceinline__ void convolve_split(typename CT<T>::type *buf, typename CT<T>::type *xs,
+                                               typename CT<T>::type *as, const typename CT<T>::type *H,
+                                               const typename CT<T>::type *twM,
+                                               const typename CT<T>::type *ptwh, Ld ld, Pre pre, St st) {
+    using C = typename CT<T>::type;
+    using A = decltype(pre(0));
+    constexpr int MH = 1 << LOGH;
+    for (int n = threadIdx.x; n < MH; n += blockDim.x) xs[n] = ld(n);
+    __syncthreads();
+    const C *xin = xs, *asr = as;
+    // even half: a = IDFT(FFT(x) H[2k])
+    fft_passes<LOGH, 0, 0, T, false, false>(
+        buf, ptwh, [xin](int n) { return xin[n]; }, [H](int k) { return H[2 * k]; },
+        [buf](int k, C x, C hk) { buf[pad(k)] = conj(cmul(x, hk)); });
+    fft_passes<LOGH, 0, 0, T, false, false>(buf, ptwh, LdsLd<C>{buf}, NoPre{},
+                                            [as](int k, C x, NoAux) { as[k] = conj(x); });
+    // odd half, combined with a on the way out
+    fft_passes<LOGH, 0, 0, T, false, false>(
+        buf, ptwh, [xin, twM](int n) { return cmul(xin[n], twM[n]); }, [H](int k) { return H[2 * k + 1]; },
+        [buf](int k, C x, C hk) { buf[pad(k)] = conj(cmul(x, hk)); });
+    // (a[n] and w^n are read in the store phase: held ahead with the
+    // caller's per-output values they would not fit in registers)
+    fft_passes<LOGH, 0, 0, T, false, false>(
+        buf, ptwh, LdsLd<C>{buf}, pre,
+        [&st, asr, twM](int n, C x, A u) { st(n, cadd(asr[n], cmulc(conj(x), twM[n])), u); });
+}
+
+// One row convolution of a kernel instantiated at LOGM: in LDS, or split
+// with the workgroup's scratch slot (M complex values at scr + blockIdx.x M).
+template <int LOGM, typename T, typename Ld, typename Pre, typename St>
+__device__ __forceinline__ void row_convolve(const FftTables<T> &ft, typename CT<T>::type *buf,
+                                             const typename CT<T>::type *H, typename CT<T>::type *scr, Ld ld,
+                                             Pre pre, St st) {
+    if constexpr (split_rows<T, LOGM>()) {
+        constexpr int MH = 1 << (LOGM - 1);
+        typename CT<T>::type *slot = scr + (size_t)blockIdx.x * (2 * MH);
+        convolve_split<LOGM - 1, T>(buf, slot, slot + MH, H, ft.tw, ft.ptwh, ld, pre, st);
+    } else {
+        convolve<LOGM, T>(buf, H, ft.ptw, ld, pre, st);
+    }
+}
+
+// The work items of a row kernel: one per workgroup (taken through
+// xcd_item), or for split rows a loop over items, gridDim.x workgroups each
+// with its own scratch slot.
+template <bool SPLIT, typename F> __device__ __forceinline__ void for_items(int nitems, F body) {
+    if constexpr (SPLIT) {
+        for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+            body(it);
+            __syncthreads();
+        }
+    } else {
+        body(xcd_item((int)blockIdx.x, (int)gridDim.x));
+    }
+}
+
 // Clamped load p[min(n, N-1)]: the chirp-z functors read unconditionally and
 // select zero afterwards, so that the loads of a pass issue together instead
 // of one branch (and one wait) per point.
@@ -364,17 +443,17 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N)
 // HALF (real spin-0 signals): only mu >= 0, from the 2-column panels, pairs
 // (2i, 2i+1), rings of L orders.
 template <typename T, int LOGM, bool HALF>
-__global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B,
+__global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B, int Cn, int coff,
                                                            const T *__restrict__ R,
-                                                           typename CT<T>::type *__restrict__ G) {
+                                                           typename CT<T>::type *__restrict__ G,
+                                                           typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
     const int npair = HALF ? (L + 1) / 2 : L;
-    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+    for_items<split_rows<T, LOGM>()>(npair * B, [&](int item) {
     const int pair = item % npair, b = item / npair;
-    const int Cn = (HALF ? 2 : 4) * B;
     const T sgn_s = (s & 1) ? T(-1) : T(1);
     struct Row {
         const T *re, *im;
@@ -383,7 +462,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     auto row_of = [&](int mu) {
         const int m = mu < 0 ? -mu : mu, neg = mu < 0;
         Row r;
-        r.re = R + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
+        r.re = R + ((size_t)m * Cn + coff + (size_t)(2 * neg) * B + b) * L;
         r.im = r.re + (size_t)B * L;
         r.phase = -(mu + s);  // i^{-(mu+s)}
         r.neg = neg;
@@ -412,7 +491,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     auto st = [&](int t, C y, C c) {
         if (t < N) buf[pad(t)] = cmul(y, c);
     };
-    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, pre, st);
+    row_convolve<LOGM, T>(ft, buf, ft.h_ip, scr, ld, pre, st);
     // columns mu and mu+1 of the rings G[b][t][.] (row length N, or L for HALF)
     const int rl = HALF ? L : N;
     C *Ga = G + (size_t)b * L * rl + (HALF ? mua : mua + h);
@@ -423,18 +502,21 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
         g[0] = C{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
         if (two) g[1] = C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y};
     }
+    });
 }
 
 // Inverse phi stage.  Row (b, t): f(theta_t, phi_p) = sum_mu g_mu(theta_t) e^{i mu phi_p}.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft,
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int rows,
                                                          const typename CT<T>::type *__restrict__ G,
-                                                         typename CT<T>::type *__restrict__ map) {
+                                                         typename CT<T>::type *__restrict__ map,
+                                                         typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int N = ft.N;
-    const size_t row = blockIdx.x;
+    for_items<split_rows<T, LOGM>()>(rows, [&](int item) {
+    const size_t row = split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x;
     const C *in = G + row * N;
     C *out = map + row * N;
     const C *cha = ft.cha, *chb = ft.chb;
@@ -446,19 +528,22 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft,
     auto st = [&](int p, C y, C c) {
         if (p < N) out[p] = cmul(y, c);
     };
-    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, pre, st);
+    row_convolve<LOGM, T>(ft, buf, ft.h_ip, scr, ld, pre, st);
+    });
 }
 
 // Forward phi stage.  Row (b, t): Q_mu(t) = N^-1 sum_p f(theta_t, phi_p) e^{-i mu phi_p}.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int rows,
                                                          const typename CT<T>::type *__restrict__ map,
-                                                         typename CT<T>::type *__restrict__ Q) {
+                                                         typename CT<T>::type *__restrict__ Q,
+                                                         typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int N = ft.N;
-    const size_t row = blockIdx.x;
+    for_items<split_rows<T, LOGM>()>(rows, [&](int item) {
+    const size_t row = split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x;
     const C *in = map + row * N;
     C *out = Q + row * N;
     const C *cha = ft.cha, *chb = ft.chb;
@@ -474,7 +559,8 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
             out[k] = C{z.x * invN, z.y * invN};
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st);
+    row_convolve<LOGM, T>(ft, buf, ft.h_fd, scr, ld, pre, st);
+    });
 }
 
 // Forward theta stage, two orders per block.  Column mu of the phi-stage rings
@@ -500,15 +586,15 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft,
 // HALF (real spin-0 signals): only mu >= 0, rings of L orders, pairs
 // (2i, 2i+1), 2-column panels.
 template <typename T, int LOGM, bool HALF>
-__global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B,
+__global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B, int Cn, int coff,
                                                            const typename CT<T>::type *__restrict__ Q,
-                                                           T *__restrict__ X) {
+                                                           T *__restrict__ X, typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
     const int npair = HALF ? (L + 1) / 2 : L;
-    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+    for_items<split_rows<T, LOGM>()>(npair * B, [&](int item) {
     const int pair = item % npair, b = item / npair;
     const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
@@ -538,16 +624,15 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
         const C z = cmulc(y, c);
         buf[pad(k)] = k < N ? C{z.x * invN, z.y * invN} : C{T(0), T(0)};
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st_mid);
+    row_convolve<LOGM, T>(ft, buf, ft.h_fd, scr, ld, pre, st_mid);
     // Y(m') at buf[m' + h], |m'| <= h
-    convolve<LOGM, T>(buf, ft.h_fk, ft.ptw, LdsLd<C>{buf}, NoPre{},
-                      [buf, N](int k, C y, NoAux) { if (k < N) buf[pad(k)] = y; });
-    const int Cn = (HALF ? 2 : 4) * B;
+    row_convolve<LOGM, T>(ft, buf, ft.h_fk, scr, LdsLd<C>{buf}, NoPre{},
+                          [buf, N](int k, C y, NoAux) { if (k < N) buf[pad(k)] = y; });
     const T twopi = T(6.283185307179586476925286766559);
     const T pi2 = T(9.8696044010893586188344909998762);
     auto store = [&](int mu, int odd, const C *Qr) {
         const int m = mu < 0 ? -mu : mu, neg = mu < 0;
-        T *Xre = X + ((size_t)m * Cn + (size_t)(2 * neg) * B + b) * L;
+        T *Xre = X + ((size_t)m * Cn + coff + (size_t)(2 * neg) * B + b) * L;
         T *Xim = Xre + (size_t)B * L;
         const T sg = odd ? T(-1) : T(1);
         // top-order term of an odd row: -2 i pi^2 (-1)^{h-1} Q(L-1) / N
@@ -569,6 +654,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     };
     store(mua, oddA, Qa);
     if (two) store(mua + 1, !oddA, Qb);
+    });
 }
 
 // Real spin-0 maps, two rings per transform (rows r and r+1 of the [B*L]
@@ -579,12 +665,13 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
 template <typename T, int LOGM>
 __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft, int rows,
                                                               const typename CT<T>::type *__restrict__ G,
-                                                              T *__restrict__ map) {
+                                                              T *__restrict__ map, typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const size_t r0 = 2 * (size_t)blockIdx.x;
+    for_items<split_rows<T, LOGM>()>((rows + 1) / 2, [&](int item) {
+    const size_t r0 = 2 * (split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x);
     const bool two = r0 + 1 < (size_t)rows;
     const C *ina = G + r0 * L, *inb = two ? ina + L : ina;
     T *outa = map + r0 * N, *outb = outa + N;
@@ -610,7 +697,8 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft
             if (two) outb[p] = z.y;
         }
     };
-    convolve<LOGM, T>(buf, ft.h_ip, ft.ptw, ld, pre, st);
+    row_convolve<LOGM, T>(ft, buf, ft.h_ip, scr, ld, pre, st);
+    });
 }
 
 // Forward phi stage of two real rings r, r+1 at once, keeping the orders
@@ -620,12 +708,14 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft
 template <typename T, int LOGM>
 __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft, int rows,
                                                               const T *__restrict__ map,
-                                                              typename CT<T>::type *__restrict__ Q) {
+                                                              typename CT<T>::type *__restrict__ Q,
+                                                              typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
-    const size_t r0 = 2 * (size_t)blockIdx.x;
+    for_items<split_rows<T, LOGM>()>((rows + 1) / 2, [&](int item) {
+    const size_t r0 = 2 * (split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x);
     const bool two = r0 + 1 < (size_t)rows;
     const T *ina = map + r0 * N, *inb = two ? ina + N : ina;
     C *outa = Q + r0 * L, *outb = outa + L;
@@ -645,12 +735,13 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft
             buf[pad(k)] = C{z.x * invN, z.y * invN};
         }
     };
-    convolve<LOGM, T>(buf, ft.h_fd, ft.ptw, ld, pre, st);
+    row_convolve<LOGM, T>(ft, buf, ft.h_fd, scr, ld, pre, st);
     for (int m = threadIdx.x; m < L; m += blockDim.x) {
         const C zp = buf[pad(h + m)], zm = buf[pad(h - m)];
         outa[m] = C{T(0.5) * (zp.x + zm.x), T(0.5) * (zp.y - zm.y)};
         if (two) outb[m] = C{T(0.5) * (zp.y + zm.y), T(0.5) * (zm.x - zp.x)};
     }
+    });
 }
 
 // Theta DFT alone, for the paper's own forward transform (per-order
@@ -723,8 +814,20 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_fft_rows(FftTables<T> ft, ty
                      [row, scale](int k, C x, NoAux) { row[k] = C{x.x * scale, x.y * scale}; });
 }
 
+template <typename T> bool split_host(const FftTables<T> &ft) { return rows_split(ft.M, 2 * (int)sizeof(T)); }
+
+// LDS of a row kernel: the M-point buffer with one pad slot per 16 points
+// (half of it for split rows).
 template <typename T> size_t lds_bytes(const FftTables<T> &ft) {
-    return (size_t)(ft.M + ft.M / 16) * sizeof(typename CT<T>::type);
+    const size_t m = split_host(ft) ? (size_t)ft.M / 2 : (size_t)ft.M;
+    return (m + m / 16) * sizeof(typename CT<T>::type);
+}
+
+// Launch shape of a row kernel over n items: one workgroup per item, or for
+// split rows at most kSplitSlots workgroups looping over the items.
+template <typename T> dim3 row_grid(const FftTables<T> &ft, int n) {
+    if (split_host(ft)) return dim3((unsigned)(n < kSplitSlots ? n : kSplitSlots));
+    return dim3((unsigned)n);
 }
 
 // Raises a kernel's dynamic-LDS limit once per (device, kernel, size), so a
@@ -747,7 +850,7 @@ template <typename K> hipError_t set_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
-// Calls f(std::integral_constant<int, LOGM>) for the plan's log2 M (3 .. 13).
+// Calls f(std::integral_constant<int, LOGM>) for the plan's log2 M (3 .. 14).
 template <typename F> hipError_t with_logm(int logM, F f) {
     switch (logM) {
         case 3: return f(std::integral_constant<int, 3>{});
@@ -761,108 +864,117 @@ template <typename F> hipError_t with_logm(int logM, F f) {
         case 11: return f(std::integral_constant<int, 11>{});
         case 12: return f(std::integral_constant<int, 12>{});
         case 13: return f(std::integral_constant<int, 13>{});
+        case 14: return f(std::integral_constant<int, 14>{});
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, bool half, const T *R, void *G, hipStream_t st) {
+hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const T *R, void *G,
+                            void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
-        typename CT<T>::type *g = (typename CT<T>::type *)G;
+        typename CT<T>::type *g = (typename CT<T>::type *)G, *w = (typename CT<T>::type *)scr;
         if (half) {
             hipError_t e = set_lds(k_theta_inv<T, LM, true>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_inv<T, LM, true>), dim3((ft.L + 1) / 2 * B), dim3(row_threads(ft.M)), lds,
-                               st, ft, s, B, R, g);
+            hipLaunchKernelGGL((k_theta_inv<T, LM, true>), row_grid(ft, (ft.L + 1) / 2 * B), dim3(row_threads(ft.M)),
+                               lds, st, ft, s, B, Cn, coff, R, g, w);
         } else {
             hipError_t e = set_lds(k_theta_inv<T, LM, false>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_inv<T, LM, false>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
-                               s, B, R, g);
+            hipLaunchKernelGGL((k_theta_inv<T, LM, false>), row_grid(ft, ft.L * B), dim3(row_threads(ft.M)), lds, st,
+                               ft, s, B, Cn, coff, R, g, w);
         }
         return hipGetLastError();
     });
 }
 
 template <typename T>
-hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, hipStream_t st) {
+hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_inv<T, LM>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_phi_inv<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
-                           (const typename CT<T>::type *)G, (typename CT<T>::type *)map);
+        const int rows = ft.L * B;
+        hipLaunchKernelGGL((k_phi_inv<T, LM>), row_grid(ft, rows), dim3(row_threads(ft.M)), lds, st, ft, rows,
+                           (const typename CT<T>::type *)G, (typename CT<T>::type *)map, (typename CT<T>::type *)scr);
         return hipGetLastError();
     });
 }
 
 template <typename T>
-hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st) {
+hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_fwd<T, LM>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_phi_fwd<T, LM>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
-                           (const typename CT<T>::type *)map, (typename CT<T>::type *)Q);
+        const int rows = ft.L * B;
+        hipLaunchKernelGGL((k_phi_fwd<T, LM>), row_grid(ft, rows), dim3(row_threads(ft.M)), lds, st, ft, rows,
+                           (const typename CT<T>::type *)map, (typename CT<T>::type *)Q, (typename CT<T>::type *)scr);
         return hipGetLastError();
     });
 }
 
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, bool half, const void *Q, T *X, hipStream_t st) {
+hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const void *Q, T *X,
+                            void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
         const typename CT<T>::type *q = (const typename CT<T>::type *)Q;
+        typename CT<T>::type *w = (typename CT<T>::type *)scr;
         if (half) {
             hipError_t e = set_lds(k_theta_fwd<T, LM, true>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_fwd<T, LM, true>), dim3((ft.L + 1) / 2 * B), dim3(row_threads(ft.M)), lds,
-                               st, ft, s, B, q, X);
+            hipLaunchKernelGGL((k_theta_fwd<T, LM, true>), row_grid(ft, (ft.L + 1) / 2 * B), dim3(row_threads(ft.M)),
+                               lds, st, ft, s, B, Cn, coff, q, X, w);
         } else {
             hipError_t e = set_lds(k_theta_fwd<T, LM, false>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_fwd<T, LM, false>), dim3(ft.L * B), dim3(row_threads(ft.M)), lds, st, ft,
-                               s, B, q, X);
+            hipLaunchKernelGGL((k_theta_fwd<T, LM, false>), row_grid(ft, ft.L * B), dim3(row_threads(ft.M)), lds, st,
+                               ft, s, B, Cn, coff, q, X, w);
         }
         return hipGetLastError();
     });
 }
 
 template <typename T>
-hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, hipStream_t st) {
+hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_inv_real<T, LM>, lds);
         if (e != hipSuccess) return e;
         const int rows = ft.L * B;
-        hipLaunchKernelGGL((k_phi_inv_real<T, LM>), dim3((rows + 1) / 2), dim3(row_threads(ft.M)), lds, st, ft,
-                           rows, (const typename CT<T>::type *)G, map);
+        hipLaunchKernelGGL((k_phi_inv_real<T, LM>), row_grid(ft, (rows + 1) / 2), dim3(row_threads(ft.M)), lds, st,
+                           ft, rows, (const typename CT<T>::type *)G, map, (typename CT<T>::type *)scr);
         return hipGetLastError();
     });
 }
 
 template <typename T>
-hipError_t launch_phi_fwd_real(const FftTables<T> &ft, int B, const T *map, void *Q, hipStream_t st) {
+hipError_t launch_phi_fwd_real(const FftTables<T> &ft, int B, const T *map, void *Q, void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_fwd_real<T, LM>, lds);
         if (e != hipSuccess) return e;
         const int rows = ft.L * B;
-        hipLaunchKernelGGL((k_phi_fwd_real<T, LM>), dim3((rows + 1) / 2), dim3(row_threads(ft.M)), lds, st, ft,
-                           rows, map, (typename CT<T>::type *)Q);
+        hipLaunchKernelGGL((k_phi_fwd_real<T, LM>), row_grid(ft, (rows + 1) / 2), dim3(row_threads(ft.M)), lds, st,
+                           ft, rows, map, (typename CT<T>::type *)Q, (typename CT<T>::type *)scr);
         return hipGetLastError();
     });
 }
 
+// (the triangular forward's theta DFT and the plan's in-place FFT run only
+// at sizes whose rows fit in LDS)
 template <typename T>
 hipError_t launch_theta_dft(const FftTables<T> &ft, int s, int B, const void *Q, void *F, hipStream_t st) {
+    if (split_host(ft)) return hipErrorInvalidValue;
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
@@ -877,6 +989,7 @@ hipError_t launch_theta_dft(const FftTables<T> &ft, int s, int B, const void *Q,
 template <typename T>
 hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf, int rows, double scale,
                               hipStream_t st) {
+    if (split_host(ft)) return hipErrorInvalidValue;
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
@@ -907,19 +1020,26 @@ template <typename T> hipError_t prepare_row_kernels(const FftTables<T> &ft) {
         if (e == hipSuccess) e = set_lds(k_theta_fwd<T, LM, false>, lds);
         if (e == hipSuccess) e = set_lds(k_phi_inv_real<T, LM>, lds);
         if (e == hipSuccess) e = set_lds(k_phi_fwd_real<T, LM>, lds);
-        if (e == hipSuccess) e = set_lds(k_theta_dft<T, LM>, lds);
+        if (e == hipSuccess && !split_host(ft)) e = set_lds(k_theta_dft<T, LM>, lds);
         return e;
     });
 }
 
+template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft) {
+    return split_host(ft) ? (size_t)kSplitSlots * ft.M * sizeof(typename CT<T>::type) : 0;
+}
+
 #define SHT_INST(T)                                                                                      \
-    template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, bool, const T *, void *, hipStream_t); \
-    template hipError_t launch_phi_inv_real<T>(const FftTables<T> &, int, const void *, T *, hipStream_t);  \
-    template hipError_t launch_phi_fwd_real<T>(const FftTables<T> &, int, const T *, void *, hipStream_t);  \
-    template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
-    template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, const void *, void *, hipStream_t);     \
+    template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, int, int, bool, const T *, void *, \
+                                            void *, hipStream_t);                                        \
+    template hipError_t launch_phi_inv_real<T>(const FftTables<T> &, int, const void *, T *, void *, hipStream_t); \
+    template hipError_t launch_phi_fwd_real<T>(const FftTables<T> &, int, const T *, void *, void *, hipStream_t); \
+    template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, const void *, void *, void *, hipStream_t); \
+    template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, const void *, void *, void *, hipStream_t); \
     template hipError_t launch_theta_dft<T>(const FftTables<T> &, int, int, const void *, void *, hipStream_t); \
-    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, bool, const void *, T *, hipStream_t); \
+    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, int, int, bool, const void *, T *, \
+                                            void *, hipStream_t);                                        \
+    template size_t split_scratch_bytes<T>(const FftTables<T> &);                                        \
     template hipError_t launch_transpose<T>(int, int, int, const void *, void *, hipStream_t);                \
     template hipError_t launch_fft_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \
                                                   hipStream_t);                                          \

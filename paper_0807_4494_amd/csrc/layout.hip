@@ -1,6 +1,7 @@
 // Layout kernels between the caller's coefficient array flm[b][l*l + l + m]
 // and the order-major panels the contraction streams, [m >= 0][c][l] with
-// column c = q*B + b:
+// Cn columns per order, of which this launch's maps (one spin) own
+// c = coff + q*B + b:
 //   q = 0, 1   Re, Im of f_{l, m}
 //   q = 2, 3   Re, Im of (-1)^l f_{l, -m}   (m > 0; zero for m = 0)
 // The (-1)^l factor realises d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
@@ -24,8 +25,8 @@ namespace {
 constexpr int TL = 32;  // tile edge
 
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, const typename CT<T>::type *__restrict__ flm,
-                                                  T *__restrict__ P) {
+__global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, int coff,
+                                                  const typename CT<T>::type *__restrict__ flm, T *__restrict__ P) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][l_local][m_local]
     const int l0 = blockIdx.x * TL, m0 = blockIdx.y * TL, b = blockIdx.z;
@@ -57,11 +58,10 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, const ty
     __syncthreads();
     // write: x runs over l (contiguous in the panel)
     constexpr int NQ = HALF ? 2 : 4;
-    const int Cn = NQ * B;
     for (int mi = ty; mi < TL; mi += 8) {
         const int m = m0 + mi, l = l0 + tx;
         if (m >= L || l >= L || l < m) continue;
-        for (int q = 0; q < NQ; ++q) P[((size_t)m * Cn + (size_t)q * B + b) * L + l] = tile[q][tx][mi];
+        for (int q = 0; q < NQ; ++q) P[((size_t)m * Cn + coff + (size_t)q * B + b) * L + l] = tile[q][tx][mi];
     }
 }
 
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, const ty
 //   f_{l, m}  = (-1)^s i^{m+s}              (R0 + i R1)
 //   f_{l,-m}  = (-1)^s i^{s-m} (-1)^l       (R2 + i R3)      (m > 0)
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, const T *__restrict__ R,
+__global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, int Cn, int coff, const T *__restrict__ R,
                                                    typename CT<T>::type *__restrict__ flm) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][m_local][l_local]
@@ -78,14 +78,13 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, const T
     if (l0 + TL - 1 < m0) return;
     const int as = s < 0 ? -s : s;
     constexpr int NQ = HALF ? 2 : 4;
-    const int Cn = NQ * B;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // read: x runs over l
     for (int mi = ty; mi < TL; mi += 8) {
         const int m = m0 + mi, l = l0 + tx;
         T v[4] = {0, 0, 0, 0};
         if (m < L && l < L && l >= m && l >= as) {
-            for (int q = 0; q < NQ; ++q) v[q] = R[((size_t)m * Cn + (size_t)q * B + b) * L + l];
+            for (int q = 0; q < NQ; ++q) v[q] = R[((size_t)m * Cn + coff + (size_t)q * B + b) * L + l];
         }
         for (int q = 0; q < 4; ++q) tile[q][mi][tx] = v[q];
     }
@@ -162,26 +161,28 @@ template hipError_t launch_spin_pair<double>(int, int, int, const void *, void *
 template hipError_t launch_spin_pair<float>(int, int, int, const void *, void *, hipStream_t);
 
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, bool half, const void *flm, T *P, hipStream_t st) {
+hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, bool half, const void *flm, T *P,
+                            hipStream_t st) {
     dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
     const typename CT<T>::type *f = (const typename CT<T>::type *)flm;
-    if (half) hipLaunchKernelGGL((k_layout_in<T, true>), grid, dim3(256), 0, st, L, s, B, f, P);
-    else hipLaunchKernelGGL((k_layout_in<T, false>), grid, dim3(256), 0, st, L, s, B, f, P);
+    if (half) hipLaunchKernelGGL((k_layout_in<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, f, P);
+    else hipLaunchKernelGGL((k_layout_in<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, f, P);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, bool half, const T *R, void *flm, hipStream_t st) {
+hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, bool half, const T *R, void *flm,
+                             hipStream_t st) {
     dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
     typename CT<T>::type *f = (typename CT<T>::type *)flm;
-    if (half) hipLaunchKernelGGL((k_layout_out<T, true>), grid, dim3(256), 0, st, L, s, B, R, f);
-    else hipLaunchKernelGGL((k_layout_out<T, false>), grid, dim3(256), 0, st, L, s, B, R, f);
+    if (half) hipLaunchKernelGGL((k_layout_out<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, R, f);
+    else hipLaunchKernelGGL((k_layout_out<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, R, f);
     return hipGetLastError();
 }
 
-template hipError_t launch_layout_in<double>(int, int, int, bool, const void *, double *, hipStream_t);
-template hipError_t launch_layout_in<float>(int, int, int, bool, const void *, float *, hipStream_t);
-template hipError_t launch_layout_out<double>(int, int, int, bool, const double *, void *, hipStream_t);
-template hipError_t launch_layout_out<float>(int, int, int, bool, const float *, void *, hipStream_t);
+template hipError_t launch_layout_in<double>(int, int, int, int, int, bool, const void *, double *, hipStream_t);
+template hipError_t launch_layout_in<float>(int, int, int, int, int, bool, const void *, float *, hipStream_t);
+template hipError_t launch_layout_out<double>(int, int, int, int, int, bool, const double *, void *, hipStream_t);
+template hipError_t launch_layout_out<float>(int, int, int, int, int, bool, const float *, void *, hipStream_t);
 
 }  // namespace sht

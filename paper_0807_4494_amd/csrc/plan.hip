@@ -209,6 +209,25 @@ __global__ void k_fill_pass_tw(cplx64 *ptw, int off, int logNs, int logR) {
     ptw[off + i] = cplx64{c, s};
 }
 
+// Plain DFT of one length-M row per block row, out[k] = scale sum_n in[n]
+// w^{nk} with w = e^{-2 pi i/M} taken from the plan's table at nk mod M: the
+// spectra of plans whose M-point FFT does not fit in LDS (built once).
+__global__ void k_dft_rows(const cplx64 *in, cplx64 *out, const cplx64 *tw, int M, double scale) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const cplx64 *x = in + (size_t)blockIdx.y * M;
+    double re = 0.0, im = 0.0;
+    int idx = 0;  // n k mod M
+    for (int n = 0; n < M; ++n) {
+        const cplx64 a = x[n], w = tw[idx];
+        re += a.x * w.x - a.y * w.y;
+        im += a.x * w.y + a.y * w.x;
+        idx += k;
+        if (idx >= M) idx -= M;
+    }
+    out[(size_t)blockIdx.y * M + k] = cplx64{re * scale, im * scale};
+}
+
 template <typename T> __global__ void k_convert_table(typename CT<T>::type *dst, const cplx64 *src, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -232,10 +251,35 @@ hipError_t launch_fft_tables<double>(FftTables<double> &ft, FftTables<double> *,
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_ip, M, N, L, N, N, 0);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fd, M, N, L, N, N, 1);
     hipLaunchKernelGGL(k_fill_kernel_seq, dim3((M + th - 1) / th), dim3(th), 0, st, ft.h_fk, M, N, L, N, N, 2);
+    if (ft.ptwh) {
+        // pass twiddles of the M/2-point halves of split rows
+        const int lh = ft.logM - 1;
+        for (int p = 1; p < fft_npass(lh); ++p) {
+            const int lns = fft_pass_logns(lh, p), lr = fft_pass_lr(lh, p);
+            const int n = 1 << (lns + lr);
+            hipLaunchKernelGGL(k_fill_pass_tw, dim3((n + th - 1) / th), dim3(th), 0, st, ft.ptwh,
+                               fft_pass_offset(lh, p), lns, lr);
+        }
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // spectra: forward FFT in place (natural order), scaled by 1/M (the inverse transform's normalisation)
+    // spectra: forward DFT (natural order), scaled by 1/M (the inverse transform's normalisation)
     const double inv = 1.0 / (double)M;
+    if (rows_split(M, (int)sizeof(cplx64))) {
+        // the three kernel rows are contiguous (h_ip, h_fd, h_fk): transform
+        // them out of a temporary copy
+        cplx64 *tmp = nullptr;
+        if ((e = hipMalloc((void **)&tmp, 3 * (size_t)M * sizeof(cplx64))) != hipSuccess) return e;
+        e = hipMemcpyAsync(tmp, ft.h_ip, 3 * (size_t)M * sizeof(cplx64), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_dft_rows, dim3((M + th - 1) / th, 3), dim3(th), 0, st, tmp, ft.h_ip, ft.tw, M,
+                               inv);
+            e = hipGetLastError();
+        }
+        const hipError_t es = hipStreamSynchronize(st);
+        const hipError_t ef = hipFree(tmp);
+        return e != hipSuccess ? e : (es != hipSuccess ? es : ef);
+    }
     if ((e = launch_fft_inplace<double>(ft, ft.h_ip, 1, inv, st)) != hipSuccess) return e;
     if ((e = launch_fft_inplace<double>(ft, ft.h_fd, 1, inv, st)) != hipSuccess) return e;
     if ((e = launch_fft_inplace<double>(ft, ft.h_fk, 1, inv, st)) != hipSuccess) return e;

@@ -55,7 +55,18 @@ template <typename T> struct FftTables {
     C *h_ip = nullptr;    // spectra (natural order, 1/M folded in) of the chirp-z kernels:
     C *h_fd = nullptr;    //   inverse DFT, forward DFT,
     C *h_fk = nullptr;    //   and the forward quadrature's real kernel K
+    C *ptwh = nullptr;    // pass twiddles of an M/2-point FFT (rows split in two halves;
+                          //   allocated when M > 8192)
 };
+
+// Rows whose M-point buffer exceeds the LDS (FP64 at M = 16384) run as two
+// halves with a global scratch slot of M complex values per workgroup; a
+// launch uses at most kSplitSlots workgroups.
+constexpr int kSplitSlots = 256;
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS of one CU
+__host__ __device__ constexpr bool rows_split(int M, int cbytes) {
+    return (size_t)(M + M / 16) * (size_t)cbytes > kLdsBytes;
+}
 
 // Per-L reciprocal square roots of the two Wigner recursions (FP64):
 //   ri[l*L + j] = 1/sqrt((l+1)^2 - j^2)        (l-recursion, j <= l; else 0)
@@ -118,31 +129,40 @@ hipError_t launch_spin_tables(const EdgeTable &E, const RecTables &rt, SpinPlan 
 hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
-// layout.hip
+// layout.hip.  The panels have Cn columns per order; the B maps of one
+// launch (one spin) own columns coff + q*B + b.
 // half: real spin-0 signals, orders m >= 0 only (2 columns per map)
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, bool half, const void *flm, T *P, hipStream_t st);
+hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, bool half, const void *flm, T *P,
+                            hipStream_t st);
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, bool half, const T *R, void *flm, hipStream_t st);
+hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, bool half, const T *R, void *flm,
+                             hipStream_t st);
 
 // {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m}) for spin pairs f_{-s} = conj(f_s)
 template <typename T>
 hipError_t launch_spin_pair(int L, int s, int B, const void *in, void *out, hipStream_t st);
 
-// fft.hip: row transforms
+// fft.hip: row transforms.  scr: split-row scratch of split_scratch_bytes(ft)
+// bytes (unused, may be NULL, when that is 0)
+template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft);
+// The theta stages of B maps of one spin whose contraction columns are
+// coff + q*B + b of Cn; G / Q point at the first of those maps' rings.
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, bool half, const T *R, void *G, hipStream_t st);
+hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const T *R, void *G,
+                            void *scr, hipStream_t st);
 template <typename T>
-hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, hipStream_t st);
+hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, void *scr, hipStream_t st);
 template <typename T>
-hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, hipStream_t st);
+hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, void *scr, hipStream_t st);
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, bool half, const void *Q, T *X, hipStream_t st);
+hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const void *Q, T *X,
+                            void *scr, hipStream_t st);
 // real maps (spin 0): phi synthesis from orders m >= 0, phi analysis keeping m >= 0
 template <typename T>
-hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, hipStream_t st);
+hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, void *scr, hipStream_t st);
 template <typename T>
-hipError_t launch_phi_fwd_real(const FftTables<T> &ft, int B, const T *map, void *Q, hipStream_t st);
+hipError_t launch_phi_fwd_real(const FftTables<T> &ft, int B, const T *map, void *Q, void *scr, hipStream_t st);
 // theta DFT of the extended rows alone, F[b][mu][m'] for m' in [0, L)
 template <typename T>
 hipError_t launch_theta_dft(const FftTables<T> &ft, int s, int B, const void *Q, void *F, hipStream_t st);
@@ -159,11 +179,17 @@ hipError_t launch_fft_inplace(const FftTables<T> &ft, typename CT<T>::type *buf,
 
 // contract.hip
 enum ContractMode { kInverse = 0, kForward = 1 };
-// C columns: 4 per map for complex signals (Re, Im of f_{l,m} and of
-// (-1)^l f_{l,-m}), 2 per map for real spin-0 signals (m >= 0 only)
+// One launch contracts the columns of several spins at one L: segment k owns
+// the next ncol columns and contracts them with its spin's factors.  Columns:
+// 4 per map for complex signals (Re, Im of f_{l,m} and of (-1)^l f_{l,-m}),
+// 2 per map for real spin-0 signals (m >= 0 only).
+struct ContractSeg {
+    int ncol;
+    const SpinPlan *sp;
+};
 template <typename T>
-hipError_t launch_contract(int mode, int L, int s, int C, const T *X, T *Y, const EdgeTable &E,
-                           const SpinPlan &sp, const RecTables &rt, hipStream_t st);
+hipError_t launch_contract(int mode, int L, int nseg, const ContractSeg *seg, const T *X, T *Y, const EdgeTable &E,
+                           const RecTables &rt, hipStream_t st);
 hipError_t launch_mtable(int L, int precision_fp64, const EdgeTable &E, const RecTables &rt, SpinPlan &sp,
                          hipStream_t st);
 // fills rt.sched / rt.nsched for L (host sort, synchronous copy); 0 on success
@@ -181,8 +207,8 @@ int contract_precision_class(bool fp64, bool bf16x3);
 void set_contract_tile(int L, int C, int pclass, int ctile);
 int get_contract_tile(int L, int C, int pclass);
 
-hipError_t launch_contract_bf16x3(int mode, int L, int s, int C, const float *X, float *Y,
-                                  const EdgeTable &E, const SpinPlan &sp, const RecTables &rt, hipStream_t st);
+hipError_t launch_contract_bf16x3(int mode, int L, int nseg, const ContractSeg *seg, const float *X, float *Y,
+                                  const EdgeTable &E, const RecTables &rt, hipStream_t st);
 
 // tri.hip: the paper's per-order triangular systems (FP64, L <= SHT_TRI_L_MAX)
 hipError_t launch_tri_solve(int L, int s, int B, const void *F, void *flm, const EdgeTable &E,

@@ -108,6 +108,51 @@ def inverse(flm: torch.Tensor, L: int, spin: int = 0, precision="fp64", out: Opt
     return out[0] if single else out
 
 
+def _segments(spins, batches):
+    import ctypes
+    spins, batches = [int(x) for x in spins], [int(x) for x in batches]
+    if len(spins) != len(batches) or not spins:
+        raise ValueError("spins and batches must be non-empty and of equal length")
+    n = len(spins)
+    return n, (ctypes.c_int * n)(*spins), (ctypes.c_int * n)(*batches), sum(batches)
+
+
+def inverse_multi(flm: torch.Tensor, L: int, spins, batches, precision="fp32", out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Inverse transform of maps of several spins at one L in one call
+    (``sht_inverse_multi``): ``flm`` [sum(batches), L*L] holds segment k's
+    ``batches[k]`` maps of spin ``spins[k]``, segment after segment; the
+    result is each map's :func:`inverse` at its spin."""
+    p = _prec(precision)
+    nseg, sp, bt, B = _segments(spins, batches)
+    if not flm.is_cuda or flm.dim() != 2 or tuple(flm.shape) != (B, L * L):
+        raise ValueError(f"flm must be a GPU tensor [{B}, {L * L}]")
+    f = flm.to(io_dtype(p)).contiguous()
+    out = _out(out, (B, L, 2 * L - 1), io_dtype(p), f.device)
+    ws, nbytes = _workspace(L, 0, B, p, f.device, workspace)
+    rc = N.load().sht_inverse_multi(L, nseg, sp, bt, N.SHT_SAMPLING_MW, p, f.data_ptr(), out.data_ptr(),
+                                    ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(f.device))
+    N.check(rc, "sht_inverse_multi")
+    return out
+
+
+def forward_multi(fmap: torch.Tensor, L: int, spins, batches, precision="fp32", out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Forward transform of maps of several spins at one L in one call
+    (``sht_forward_multi``), segment layout as for :func:`inverse_multi`."""
+    p = _prec(precision)
+    nseg, sp, bt, B = _segments(spins, batches)
+    if not fmap.is_cuda or tuple(fmap.shape) != (B, L, 2 * L - 1):
+        raise ValueError(f"map must be a GPU tensor [{B}, {L}, {2 * L - 1}]")
+    g = fmap.to(io_dtype(p)).contiguous()
+    out = _out(out, (B, L * L), io_dtype(p), g.device)
+    ws, nbytes = _workspace(L, 0, B, p, g.device, workspace)
+    rc = N.load().sht_forward_multi(L, nseg, sp, bt, N.SHT_SAMPLING_MW, p, g.data_ptr(), out.data_ptr(),
+                                    ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(g.device))
+    N.check(rc, "sht_forward_multi")
+    return out
+
+
 def inverse_noalloc(flm: torch.Tensor, L: int, spin: int, precision, out: torch.Tensor) -> torch.Tensor:
     """Inverse spin SHT through ``sht_inverse_noalloc``: no device memory is
     allocated (the library's static scratch is the workspace), so ``out``

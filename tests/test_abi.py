@@ -147,13 +147,19 @@ def test_error_metrics_argument_checks_run_before_any_hip_call():
 
 def test_workspace_size_formula():
     N, lib = _lib()
-    for L, B, p in [(32, 1, 0), (1024, 16, 1), (2048, 4, 1), (255, 3, 0)]:
+    for L, B, p in [(32, 1, 0), (1024, 16, 1), (2048, 4, 1), (255, 3, 0), (2048, 2, 0), (4096, 1, 1),
+                    (4096, 2, 0), (2049, 1, 0)]:
         T = 8 if p == 0 else 4
         C, Nn = 4 * B, 2 * L - 1
         al = lambda x: (x + 255) // 256 * 256
         ra = al(max(L * C * L * T, B * L * Nn * 2 * T))
         rb = ra
-        assert lib.sht_workspace_bytes(L, 0, B, 0, p) == ra + rb
+        # FFT rows whose M-point LDS buffer (M + M/16 complex) exceeds 160 KiB
+        # (FP64 beyond L = 2048) add 256 scratch slots of M complex values
+        M = 1 << max(3, (4 * L - 4).bit_length())
+        rc = al(256 * M * 2 * T) if (M + M // 16) * 2 * T > 160 * 1024 else 0
+        assert (rc > 0) == (p == 0 and L > 2048)
+        assert lib.sht_workspace_bytes(L, 0, B, 0, p) == ra + rb + rc
     assert lib.sht_workspace_bytes(8, 9, 1, 0, 0) == 0
     assert lib.sht_workspace_bytes(8, 0, 1, 3, 0) == 0
 
@@ -171,3 +177,21 @@ def test_noalloc_argument_checks_run_before_any_hip_call():
     assert call(1024, 0, 16, 0, 1, fake, fake, None) == N.SHT_ERR_WORKSPACE
     assert lib.sht_workspace_bytes(512, 0, 8, 0, 1) <= N.SHT_NOALLOC_SCRATCH_BYTES
     assert lib.sht_workspace_bytes(512, 0, 9, 0, 1) > N.SHT_NOALLOC_SCRATCH_BYTES
+
+
+def test_multi_argument_checks_run_before_any_hip_call():
+    N, lib = _lib()
+    fake = ctypes.c_void_p(1 << 20)
+    big = 1 << 40
+    arr = lambda *v: (ctypes.c_int * len(v))(*v)
+    call = lib.sht_inverse_multi
+    assert call(8, 0, arr(0), arr(1), 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 9, arr(*[0] * 9), arr(*[1] * 9), 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 2, arr(0, 8), arr(1, 1), 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG  # |s| >= L
+    assert call(8, 2, arr(0, 1), arr(1, 0), 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG  # empty segment
+    assert call(8, 2, arr(0, 1), arr(40, 25), 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG  # > 64 maps
+    assert call(8, 1, None, arr(1), 0, 0, fake, fake, fake, big, None) == N.SHT_ERR_INVALID_ARG
+    assert call(8, 2, arr(0, 1), arr(1, 1), 0, 7, fake, fake, fake, big, None) == N.SHT_ERR_UNSUPPORTED
+    need = lib.sht_workspace_bytes(8, 0, 5, 0, 0)
+    assert lib.sht_forward_multi(8, 2, arr(0, 1), arr(2, 3), 0, 0, fake, fake, fake, need - 1, None) == \
+        N.SHT_ERR_WORKSPACE

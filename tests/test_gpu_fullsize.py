@@ -106,3 +106,58 @@ def test_round_trip_full_size(name, prec):
         back = sht.forward(sht.inverse(flm, wl.L, s, prec), wl.L, s, prec)
         err = float(torch.linalg.vector_norm(back - flm) / torch.linalg.vector_norm(flm))
         assert err <= TOL[prec], (name, s, prec, err)
+
+
+# ---- the largest band-limit the library accepts (SHT_L_MAX = 4096) ----
+# FFT rows of M = 16384 points: in LDS for FP32, as two M/2-point halves with
+# global scratch for FP64 (their buffer exceeds a CU's LDS).  The oracle takes
+# about an hour per map there, so the checks are a closed form at low degree
+# and the round trip.
+
+L_MAX = 4096
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_low_degree_content_at_the_largest_band_limit(prec):
+    """A map with harmonics of degree <= 6 only, synthesised at L = 4096:
+    sampled pixels equal the direct sum of Eq. (ssh_wigner) harmonics (Wigner
+    sum in 40-digit arithmetic), and the forward returns the coefficients."""
+    from closed_forms import sylm_wigner
+    sht = _sht()
+    dev = _dev()
+    L, s, lmax = L_MAX, 2, 6
+    print(f"[L=4096 low degree] s={s} {prec}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(sht_synth.SEED_BASE + 9400))
+    flm = np.zeros(L * L, complex)
+    terms = [(l, m) for l in range(abs(s), lmax + 1) for m in range(-l, l + 1)]
+    for l, m in terms:
+        flm[l * l + l + m] = rng.standard_normal() + 1j * rng.standard_normal()
+    x = torch.from_numpy(flm[None]).to(dev, sht.io_dtype(prec))
+    fmap = sht.inverse(x, L, s, prec)
+    back = sht.forward(fmap, L, s, prec)
+    torch.cuda.synchronize()
+    N = 2 * L - 1
+    pix_t = rng.integers(0, L, 48)
+    pix_t[:2] = (0, L - 1)                     # the first ring and theta = pi
+    pix_p = rng.integers(0, N, 48)
+    got = fmap[0, torch.from_numpy(pix_t).to(dev), torch.from_numpy(pix_p).to(dev)].cpu().numpy()
+    ref = np.array([sum(flm[l * l + l + m] * sylm_wigner(l, m, s, np.pi * (2 * t + 1) / N, np.pi * (2 * p + 1) / N)
+                        for l, m in terms) for t, p in zip(pix_t, pix_p)])
+    assert _rel(ref, got) <= TOL[prec], _rel(ref, got)
+    assert _rel(flm, back[0].cpu().numpy()) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_round_trip_at_the_largest_band_limit(prec):
+    """Gaussian coefficients over every degree below L = 4096 (C_l =
+    1/(l+1)^2, spin 2): the forward of the inverse returns them."""
+    sht = _sht()
+    dev = _dev()
+    L, s = L_MAX, 2
+    print(f"[L=4096 round trip] s={s} {prec}", flush=True)
+    flm = sht_synth.gaussian_flm(L, s, sht_synth.SEED_BASE + 9500, "inv_lp1_sq")
+    x = torch.from_numpy(flm[None]).to(dev, sht.io_dtype(prec))
+    back = sht.forward(sht.inverse(x, L, s, prec), L, s, prec)
+    err = float(torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x))
+    print(f"[L=4096 round trip] {prec}: rel l2 {err:.3e}", flush=True)
+    assert err <= TOL[prec]
