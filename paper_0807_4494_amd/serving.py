@@ -7,18 +7,26 @@ benchmark.  The loop
 * admits arrived requests in arrival order while their device-memory footprint
   fits in a fixed budget and a stream slot is free (admission by HBM
   footprint);
-* groups the waiting requests that share (L, spin) with the oldest one into a
-  single batched call (up to the library's batch limit), so one launch
-  sequence serves all of them;
+* groups the waiting requests that share the oldest one's L into one call,
+  whatever their spins (``sht_inverse_multi`` / ``sht_forward_multi``: one
+  contraction launch serves every spin segment of the group), up to the
+  library's batch and segment limits; ``by_spin=True`` restricts a group to
+  one (L, spin);
 * runs each group on its own HIP stream, so groups admitted while others are
   still on the GPU overlap with them on the device;
 * frees a group's memory and slot when its completion event fires, and times
-  every request from its arrival to that event.
+  every request from its arrival to that event;
+* drops a waiting request whose ``timeout_s`` has passed (status
+  ``"timeout"``) and honours ``cancel(rid)``: a waiting request is removed, an
+  in-flight one finishes on the device but is reported ``"cancelled"``;
+* marks every request of a group whose launch or completion fails as
+  ``"failed"`` and keeps serving the others.
 
 Plans (Wigner seed and spin tables, FFT tables) are built for every (L, spin)
-before the loop starts and stay resident.  The scheduling logic
-(``Scheduler``) is pure Python and runs without a GPU; ``GpuServer`` drives
-the library through its C ABI on torch streams.
+before the loop starts and stay resident.  The loop itself (``Server``,
+``Scheduler``) is pure Python over an executor interface: ``GpuExecutor``
+drives the library through its C ABI on torch streams, and the CPU tests
+drive the same loop with a simulated executor (timing, failures).
 """
 
 from __future__ import annotations
@@ -26,10 +34,12 @@ from __future__ import annotations
 import collections
 import dataclasses
 import math
+import threading
 import time
 from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
 
 BATCH_MAX = 64   # the library's per-call batch limit
+SEG_MAX = 8      # spin segments per call (SHT_MULTI_SEG_MAX)
 
 
 def footprint_bytes(L: int, batch: int, workspace: int, cbytes: int = 8) -> int:
@@ -41,31 +51,44 @@ def footprint_bytes(L: int, batch: int, workspace: int, cbytes: int = 8) -> int:
 
 @dataclasses.dataclass
 class Group:
+    """One call: ``segments`` [(spin, maps)] in call order, ``requests`` in
+    the same order (segment 0's requests first)."""
     L: int
-    spin: int
     requests: list
+    segments: List[Tuple[int, int]]
     batch: int
     nbytes: int
     admitted_s: float = 0.0
 
+    @property
+    def spin(self) -> Optional[int]:
+        return self.segments[0][0] if len(self.segments) == 1 else None
+
+    @property
+    def shape(self) -> tuple:
+        return (self.L, tuple(self.segments))
+
 
 class Scheduler:
-    """FIFO admission with same-(L, spin) grouping under a memory budget.
+    """FIFO admission with same-L grouping under a memory budget.
 
     ``workspace(L, spin, batch)`` gives the library's workspace size for one
     batched call.  ``next_group`` takes the oldest waiting request and every
-    later waiting request with the same (L, spin) that still fits the batch
-    limit and the free memory; it returns None when the oldest request does not
-    fit (head-of-line order is kept, so no request starves).
+    later waiting request with the same L (and the same spin if
+    ``by_spin``) that still fits the batch limit, the segment limit and the
+    free memory; it returns None when the oldest request does not fit
+    (head-of-line order is kept, so no request starves).
     """
 
     def __init__(self, budget_bytes: int, workspace: Callable[[int, int, int], int],
-                 max_batch: int = BATCH_MAX, cbytes: int = 8):
+                 max_batch: int = BATCH_MAX, cbytes: int = 8, by_spin: bool = False, max_segments: int = SEG_MAX):
         self.budget = int(budget_bytes)
         self.used = 0
         self.workspace = workspace
         self.max_batch = max_batch
         self.cbytes = cbytes
+        self.by_spin = by_spin
+        self.max_segments = max_segments
         self.waiting: collections.deque = collections.deque()
 
     def arrive(self, req) -> None:
@@ -89,23 +112,49 @@ class Scheduler:
         if need > free:
             return None
         members = [head]
+        spins = [head.spin]
         for req in list(self.waiting)[1:]:
-            if (req.L, req.spin) != (head.L, head.spin) or batch + req.batch > self.max_batch:
+            if req.L != head.L or batch + req.batch > self.max_batch:
+                continue
+            if self.by_spin and req.spin != head.spin:
+                continue
+            if req.spin not in spins and len(spins) >= self.max_segments:
                 continue
             more = self.group_bytes(head.L, head.spin, batch + req.batch)
             if more > free:
                 continue
             members.append(req)
+            if req.spin not in spins:
+                spins.append(req.spin)
             batch += req.batch
             need = more
         for req in members:
             self.waiting.remove(req)
         self.used += need
-        return Group(head.L, head.spin, members, batch, need)
+        ordered = [r for s in spins for r in members if r.spin == s]
+        segments = [(s, sum(r.batch for r in members if r.spin == s)) for s in spins]
+        return Group(head.L, ordered, segments, batch, need)
 
     def release(self, group: Group) -> None:
         self.used -= group.nbytes
         assert self.used >= 0
+
+    def expire(self, now_s: float, arrival: Callable = lambda r: r.arrival_s) -> list:
+        """Remove and return the waiting requests whose deadline
+        (``arrival(r)`` + ``timeout_s``, when the request has one) has passed."""
+        gone = [r for r in self.waiting
+                if getattr(r, "timeout_s", None) is not None and now_s > arrival(r) + r.timeout_s]
+        for r in gone:
+            self.waiting.remove(r)
+        return gone
+
+    def cancel(self, rid: int):
+        """Remove a waiting request; returns it, or None if it is not waiting."""
+        for r in self.waiting:
+            if r.rid == rid:
+                self.waiting.remove(r)
+                return r
+        return None
 
 
 @dataclasses.dataclass
@@ -117,6 +166,8 @@ class Result:
     arrival_s: float
     done_s: float
     group_size: int
+    status: str = "ok"        # ok, timeout, cancelled, failed
+    segments: int = 1         # spin segments of the request's call
 
     @property
     def latency_s(self) -> float:
@@ -132,27 +183,163 @@ def percentile(xs: Sequence[float], q: float) -> float:
     return ys[k]
 
 
-class GpuServer:
-    """Runs a request stream on one GPU (see the module docstring).
+class Server:
+    """The serving loop over an executor (see the module docstring).
+
+    The executor provides ``workspace(L, spin, batch)``, ``cbytes``,
+    ``begin()`` (start of a run; its clock starts at 0), ``now()`` (seconds
+    on that clock), ``idle()`` (nothing progressed: wait a little),
+    ``launch(group, slot, keep)`` -> (handle, kept outputs) (raises on a
+    failed launch), ``poll(handle)`` -> None while running, else
+    ("ok", completion time) or ("failed", message), and ``end()``.
+    """
+
+    def __init__(self, executor, streams: int = 4, budget_bytes: int = 16 << 30, by_spin: bool = False):
+        self.ex = executor
+        self.nstreams = streams
+        self.budget = budget_bytes
+        self.by_spin = by_spin
+        self._cancel_lock = threading.Lock()
+        self._cancel: set = set()
+
+    def cancel(self, rid: int) -> None:
+        """Ask for request ``rid`` to be cancelled (thread-safe; takes effect
+        at the loop's next turn)."""
+        with self._cancel_lock:
+            self._cancel.add(rid)
+
+    def run(self, requests: Sequence, keep: Optional[Iterable[int]] = None, closed_loop: bool = False,
+            on_tick: Optional[Callable[[float], None]] = None):
+        """Serve ``requests`` (each with rid, arrival_s, L, spin, batch, seed
+        and optionally timeout_s).  Arrival times are honoured on the
+        executor's clock from the start of the call (all arrive at once with
+        ``closed_loop``).  ``on_tick(now)`` runs at every turn of the loop.
+        Returns (results, kept, stats): per-request results, the device
+        outputs of the ``keep`` rids (as the executor returns them), and
+        summary statistics over the requests served."""
+        keep = set(keep or ())
+        ex = self.ex
+        reqs = sorted(requests, key=lambda r: (0.0 if closed_loop else r.arrival_s, r.rid))
+        sched = Scheduler(self.budget, ex.workspace, cbytes=ex.cbytes, by_spin=self.by_spin)
+        free = list(range(self.nstreams))
+        inflight = []   # (group, slot, handle)
+        results: List[Result] = []
+        kept_all = {}
+        cancelled_inflight: set = set()
+        ex.begin()
+        i = 0
+        peak_used = 0
+        max_inflight = 0
+
+        def arrival(req):
+            return 0.0 if closed_loop else req.arrival_s
+
+        def finish(grp, t, status):
+            for req in grp.requests:
+                st = "cancelled" if req.rid in cancelled_inflight else status
+                results.append(Result(req.rid, req.L, req.spin, req.batch, arrival(req), t,
+                                      len(grp.requests), st, len(grp.segments)))
+                if st != "ok":
+                    kept_all.pop(req.rid, None)
+
+        while i < len(reqs) or sched.waiting or inflight:
+            now = ex.now()
+            if on_tick is not None:
+                on_tick(now)
+            while i < len(reqs) and (closed_loop or reqs[i].arrival_s <= now):
+                sched.arrive(reqs[i])
+                i += 1
+            progressed = False
+            for req in sched.expire(now, arrival):
+                results.append(Result(req.rid, req.L, req.spin, req.batch, arrival(req), now, 0, "timeout"))
+                progressed = True
+            with self._cancel_lock:
+                pending, self._cancel = self._cancel, set()
+            for rid in pending:
+                req = sched.cancel(rid)
+                if req is not None:
+                    results.append(Result(req.rid, req.L, req.spin, req.batch, arrival(req), now, 0, "cancelled"))
+                    progressed = True
+                elif any(r.rid == rid for g, _, _ in inflight for r in g.requests):
+                    cancelled_inflight.add(rid)
+                elif not any(r.rid == rid for r in results) and any(r.rid == rid for r in reqs[i:]):
+                    # not arrived yet: cancelled on arrival
+                    with self._cancel_lock:
+                        self._cancel.add(rid)
+            still = []
+            for grp, si, h in inflight:
+                try:
+                    st = ex.poll(h)
+                except Exception as e:       # a failed completion fails its group only
+                    st = ("failed", str(e))
+                if st is None:
+                    still.append((grp, si, h))
+                    continue
+                status, t = st[0], (st[1] if st[0] == "ok" else now)
+                finish(grp, t, "ok" if status == "ok" else "failed")
+                sched.release(grp)
+                free.append(si)
+                progressed = True
+            inflight = still
+            while free:
+                grp = sched.next_group()
+                if grp is None:
+                    break
+                si = free.pop(0)
+                grp.admitted_s = now
+                try:
+                    h, kept = ex.launch(grp, si, keep)
+                except Exception:            # a failed launch fails its group only
+                    finish(grp, now, "failed")
+                    sched.release(grp)
+                    free.append(si)
+                    progressed = True
+                    continue
+                kept_all.update(kept)
+                inflight.append((grp, si, h))
+                peak_used = max(peak_used, sched.used)
+                max_inflight = max(max_inflight, len(inflight))
+                progressed = True
+            if not progressed:
+                ex.idle()
+        ex.end()
+        ok = [r for r in results if r.status == "ok"]
+        makespan = max((r.done_s for r in ok), default=0.0)
+        lat = [r.latency_s for r in ok]
+        maps = sum(r.batch for r in ok)
+        counts = collections.Counter(r.status for r in results)
+        stats = {"requests": len(ok), "maps": maps, "makespan_s": makespan,
+                 "transforms_per_s": maps / makespan if makespan > 0 else float("nan"),
+                 "requests_per_s": len(ok) / makespan if makespan > 0 else float("nan"),
+                 "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+                 "mean_group_size": sum(r.group_size for r in ok) / max(1, len(ok)),
+                 "mean_segments": sum(r.segments for r in ok) / max(1, len(ok)),
+                 "peak_admitted_bytes": peak_used, "max_inflight_groups": max_inflight,
+                 "budget_bytes": self.budget, "streams": self.nstreams,
+                 "timeouts": counts.get("timeout", 0), "cancelled": counts.get("cancelled", 0),
+                 "failed": counts.get("failed", 0)}
+        return results, kept_all, stats
+
+
+class GpuExecutor:
+    """Runs groups through the library on torch streams of one GPU.
 
     ``precision`` is the library precision of every call ("fp32", "bf16x3" or
-    "fp64"); ``streams`` the number of concurrent groups; ``budget_bytes`` the
-    admission budget.  Inputs are drawn on the device from each request's seed
+    "fp64").  Inputs are drawn on the device from each request's seed
     (complex Gaussian, variance C_l = 1/(l+1)^2, zero for l < |spin|) inside
     the request's own buffers when its group is admitted.
 
     ``graphs`` > 0 keeps up to that many captured transforms (``sht.Graph``,
-    one per (L, spin, batch) shape, each at most ``graph_bytes`` of device
-    memory): a shape seen for the ``graph_after``-th time is captured (the
-    least used idle graph makes room), and later groups of a cached shape
-    replay its graph instead of launching the stages one by one, unless that
-    graph is still in flight.  Graph buffers are outside the
-    admission budget (the budget still reserves each request's own
-    footprint).
+    one per single-spin (L, spin, batch) group shape, each at most
+    ``graph_bytes`` of device memory): a shape seen for the ``graph_after``-th
+    time is captured (the least used idle graph makes room), and later groups
+    of a cached shape replay its graph instead of launching the stages one by
+    one, unless that graph is still in flight.  Graph buffers are outside the
+    admission budget.  Groups of several spins always launch eagerly.
     """
 
-    def __init__(self, precision: str = "fp32", streams: int = 4, budget_bytes: int = 16 << 30,
-                 device: int = 0, graphs: int = 0, graph_bytes: int = 1 << 30, graph_after: int = 3):
+    def __init__(self, precision: str = "fp32", streams: int = 4, device: int = 0, graphs: int = 0,
+                 graph_bytes: int = 1 << 30, graph_after: int = 3, poll_s: float = 20e-6):
         import torch
         from . import sht
         self.torch = torch
@@ -160,10 +347,10 @@ class GpuServer:
         self.precision = precision
         self.dev = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
-        self.budget = budget_bytes
         self.cdtype = sht.io_dtype(precision)
         self.cbytes = 16 if precision == "fp64" else 8
-        self._ws_cache: Dict[Tuple[int, int, int], int] = {}
+        self.poll_s = poll_s
+        self._ws_cache: Dict[Tuple[int, int], int] = {}
         self._scale: Dict[Tuple[int, int], "torch.Tensor"] = {}
         self.graph_cap = graphs
         self.graph_bytes = graph_bytes
@@ -174,9 +361,9 @@ class GpuServer:
         self.graph_captures = 0
 
     def workspace(self, L: int, spin: int, batch: int) -> int:
-        key = (L, spin, batch)
+        key = (L, batch)     # the workspace does not depend on the spin
         if key not in self._ws_cache:
-            self._ws_cache[key] = self.sht.workspace_bytes(L, spin, batch, self.precision)
+            self._ws_cache[key] = self.sht.workspace_bytes(L, 0, batch, self.precision)
         return self._ws_cache[key]
 
     def warm(self, keys: Iterable[Tuple[int, int]]) -> None:
@@ -204,9 +391,34 @@ class GpuServer:
         out.copy_(torch.randn(out.shape, generator=g, device=self.dev, dtype=self.cdtype))
         out.mul_(self._spectrum(req.L, req.spin))
 
+    # ---- the clock: seconds since begin() on the host, completion times
+    # from GPU events against a reference event recorded at begin() ----
+    def begin(self) -> None:
+        torch = self.torch
+        torch.cuda.synchronize(self.dev)
+        self._ref = torch.cuda.Event(enable_timing=True)
+        self._ref.record(self.streams[0])
+        self._t0 = time.perf_counter()
+        self._g0 = (self.graph_launches, self.graph_captures)
+
+    def now(self) -> float:
+        return time.perf_counter() - self._t0
+
+    def idle(self) -> None:
+        time.sleep(self.poll_s)
+
+    def end(self) -> None:
+        self.torch.cuda.synchronize(self.dev)
+
+    def poll(self, handle):
+        done = handle[0]
+        if not done.query():
+            return None
+        return ("ok", self._ref.elapsed_time(done) / 1e3)
+
     def _graph_for(self, L: int, s: int, B: int):
         """The cached graph of this shape if it is idle (capturing it on the
-        shape's second sighting), else None."""
+        shape's graph_after-th sighting), else None."""
         key = (L, s, B)
         self._seen[key] = self._seen.get(key, 0) + 1
         ent = self._graphs.get(key)
@@ -235,12 +447,17 @@ class GpuServer:
             g.close()
         self._graphs.clear()
 
-    def _launch(self, group: Group, stream, keep: Optional[set]):
+    def launch(self, group: Group, slot: int, keep: set):
         torch = self.torch
-        L, s, B = group.L, group.spin, group.batch
-        ent = self._graph_for(L, s, B) if self.graph_cap > 0 else None
+        stream = self.streams[slot]
+        L, B = group.L, group.batch
+        single = len(group.segments) == 1
+        ent = self._graph_for(L, group.segments[0][0], B) if (self.graph_cap > 0 and single) else None
         if ent is not None:
             g = ent[0]
+            # the graph's buffers were made on the creating stream: order
+            # this stream after it before writing them
+            stream.wait_stream(torch.cuda.current_stream(self.dev))
             with torch.cuda.stream(stream):
                 off = 0
                 slices = []
@@ -250,108 +467,69 @@ class GpuServer:
                     off += req.batch
                 g.launch(stream)
                 kept = {}
-                if keep:
-                    for req, o in slices:
-                        if req.rid in keep:
-                            sl = slice(o, o + req.batch)
-                            kept[req.rid] = (g.flm_in[sl].clone(), g.map[sl].clone(), g.flm_out[sl].clone())
+                for req, o in slices:
+                    if req.rid in keep:
+                        sl = slice(o, o + req.batch)
+                        kept[req.rid] = (g.flm_in[sl].clone(), g.map[sl].clone(), g.flm_out[sl].clone())
                 done = torch.cuda.Event(enable_timing=True)
                 done.record(stream)
             ent[1] = done
             self.graph_launches += 1
-            return done, (), kept
+            return (done, ()), kept
         with torch.cuda.stream(stream):
             flm = torch.empty((B, L * L), dtype=self.cdtype, device=self.dev)
             fmap = torch.empty((B, L, 2 * L - 1), dtype=self.cdtype, device=self.dev)
             back = torch.empty_like(flm)
-            ws = torch.empty(self.workspace(L, s, B), dtype=torch.uint8, device=self.dev)
+            ws = torch.empty(self.workspace(L, 0, B), dtype=torch.uint8, device=self.dev)
             off = 0
             slices = []
             for req in group.requests:
                 self.fill_input(req, flm[off:off + req.batch])
                 slices.append((req, off))
                 off += req.batch
-            self.sht.inverse(flm, L, s, self.precision, out=fmap, workspace=ws)
-            self.sht.forward(fmap, L, s, self.precision, out=back, workspace=ws)
+            spins = [s for s, _ in group.segments]
+            batches = [n for _, n in group.segments]
+            if single:
+                self.sht.inverse(flm, L, spins[0], self.precision, out=fmap, workspace=ws)
+                self.sht.forward(fmap, L, spins[0], self.precision, out=back, workspace=ws)
+            else:
+                self.sht.inverse_multi(flm, L, spins, batches, self.precision, out=fmap, workspace=ws)
+                self.sht.forward_multi(fmap, L, spins, batches, self.precision, out=back, workspace=ws)
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
         kept = {}
-        if keep:
+        with torch.cuda.stream(stream):
+            # copies, so that the group's buffers are freed with the group
             for req, o in slices:
                 if req.rid in keep:
-                    kept[req.rid] = (flm[o:o + req.batch], fmap[o:o + req.batch], back[o:o + req.batch])
-        return done, (flm, fmap, back, ws), kept
+                    sl = slice(o, o + req.batch)
+                    kept[req.rid] = (flm[sl].clone(), fmap[sl].clone(), back[sl].clone())
+        return (done, (flm, fmap, back, ws)), kept
 
-    def run(self, requests: Sequence, keep: Optional[Iterable[int]] = None, closed_loop: bool = False,
-            poll_s: float = 20e-6):
-        """Serve ``requests`` (each with rid, arrival_s, L, spin, batch, seed).
 
-        Arrival times are honoured in real time from the start of the call
-        (all arrive at once with ``closed_loop``).  Returns (results, kept,
-        stats): per-request results, the device outputs of the ``keep`` rids
-        as (flm, map, back) views, and summary statistics.
-        """
-        torch = self.torch
-        keep = set(keep or ())
-        g_launch0, g_capture0 = self.graph_launches, self.graph_captures
-        reqs = sorted(requests, key=lambda r: (0.0 if closed_loop else r.arrival_s, r.rid))
-        sched = Scheduler(self.budget, self.workspace, cbytes=self.cbytes)
-        free = list(range(len(self.streams)))
-        inflight = []   # (group, stream index, done event, buffers)
-        results: List[Result] = []
-        kept_all = {}
-        torch.cuda.synchronize(self.dev)
-        ref = torch.cuda.Event(enable_timing=True)
-        ref.record(self.streams[0])
-        t0 = time.perf_counter()
-        i = 0
-        peak_used = 0
-        max_inflight = 0
-        while i < len(reqs) or sched.waiting or inflight:
-            now = time.perf_counter() - t0
-            while i < len(reqs) and (closed_loop or reqs[i].arrival_s <= now):
-                sched.arrive(reqs[i])
-                i += 1
-            progressed = False
-            still = []
-            for grp, si, done, bufs in inflight:
-                if done.query():
-                    t_done = ref.elapsed_time(done) / 1e3
-                    for req in grp.requests:
-                        arr = 0.0 if closed_loop else req.arrival_s
-                        results.append(Result(req.rid, req.L, req.spin, req.batch, arr, t_done,
-                                              len(grp.requests)))
-                    sched.release(grp)
-                    free.append(si)
-                    progressed = True
-                else:
-                    still.append((grp, si, done, bufs))
-            inflight = still
-            while free:
-                grp = sched.next_group()
-                if grp is None:
-                    break
-                si = free.pop(0)
-                grp.admitted_s = time.perf_counter() - t0
-                done, bufs, kept = self._launch(grp, self.streams[si], keep)
-                kept_all.update(kept)
-                inflight.append((grp, si, done, bufs))
-                peak_used = max(peak_used, sched.used)
-                max_inflight = max(max_inflight, len(inflight))
-                progressed = True
-            if not progressed:
-                time.sleep(poll_s)
-        torch.cuda.synchronize(self.dev)
-        makespan = max(r.done_s for r in results) if results else 0.0
-        lat = [r.latency_s for r in results]
-        maps = sum(r.batch for r in results)
-        stats = {"requests": len(results), "maps": maps, "makespan_s": makespan,
-                 "transforms_per_s": maps / makespan if makespan > 0 else float("nan"),
-                 "requests_per_s": len(results) / makespan if makespan > 0 else float("nan"),
-                 "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
-                 "mean_group_size": sum(r.group_size for r in results) / max(1, len(results)),
-                 "peak_admitted_bytes": peak_used, "max_inflight_groups": max_inflight,
-                 "budget_bytes": self.budget, "streams": len(self.streams),
-                 "graph_launches": self.graph_launches - g_launch0,
-                 "graph_captures": self.graph_captures - g_capture0}
-        return results, kept_all, stats
+class GpuServer(Server):
+    """The serving loop on one GPU (``Server`` over a ``GpuExecutor``).
+
+    ``by_spin`` (default False) groups by (L, spin) instead of by L.  The
+    remaining arguments are the executor's.
+    """
+
+    def __init__(self, precision: str = "fp32", streams: int = 4, budget_bytes: int = 16 << 30,
+                 device: int = 0, graphs: int = 0, graph_bytes: int = 1 << 30, graph_after: int = 3,
+                 by_spin: bool = False):
+        ex = GpuExecutor(precision, streams, device, graphs, graph_bytes, graph_after)
+        super().__init__(ex, streams, budget_bytes, by_spin)
+        self.precision = precision
+
+    def warm(self, keys) -> None:
+        self.ex.warm(keys)
+
+    def close_graphs(self) -> None:
+        self.ex.close_graphs()
+
+    def run(self, requests, keep=None, closed_loop=False, on_tick=None):
+        g0 = (self.ex.graph_launches, self.ex.graph_captures)
+        res, kept, stats = super().run(requests, keep, closed_loop, on_tick)
+        stats["graph_launches"] = self.ex.graph_launches - g0[0]
+        stats["graph_captures"] = self.ex.graph_captures - g0[1]
+        return res, kept, stats

@@ -26,7 +26,8 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("prec,graphs", [("fp32", 0), ("fp64", 0), ("fp32", 8)])
 def test_result_alone_equals_result_in_the_mix(prec, graphs):
-    server = _server(precision=prec, streams=4, budget_bytes=2 << 30, graphs=graphs, graph_after=1)
+    server = _server(precision=prec, streams=4, budget_bytes=2 << 30, graphs=graphs, graph_after=1,
+                     by_spin=bool(graphs))
     if graphs:
         # a narrow shape mix, so shapes repeat and the captured transforms replay
         reqs = sht_synth.trace(n_requests=150, rate_per_s=4000.0, L_lo=64, L_hi=96, batch_hi=1,
@@ -58,4 +59,54 @@ def test_result_alone_equals_result_in_the_mix(prec, graphs):
         assert _rel(back_one, back_mix) <= tol
         assert _rel(flm_one, back_mix) <= tol                # inverse then forward returns f_lm
     print(f"[serving mix] {bitwise} of {len(keep)} sampled requests bitwise equal alone and in the mix", flush=True)
+    server.close_graphs()
+
+
+def _check_alone_vs_mix(server, reqs, keep, kept, tol):
+    bitwise = 0
+    for rid in keep:
+        req = reqs[rid]
+        _, alone, _ = server.run([dataclasses.replace(req, arrival_s=0.0)], keep=[rid], closed_loop=True)
+        flm_mix, map_mix, back_mix = kept[rid]
+        flm_one, map_one, back_one = alone[rid]
+        assert torch.equal(flm_mix, flm_one)                 # same seeded input
+        bitwise += int(torch.equal(map_one, map_mix) and torch.equal(back_one, back_mix))
+        assert _rel(map_one, map_mix) <= tol, (req, _rel(map_one, map_mix))
+        assert _rel(back_one, back_mix) <= tol, req
+        assert _rel(flm_one, back_mix) <= tol, req           # inverse then forward returns f_lm
+        del alone
+    return bitwise
+
+
+@pytest.mark.parametrize("prec,graphs", [("fp32", 0), ("fp64", 0), ("fp32", 16)])
+def test_full_range_mix(prec, graphs):
+    """The serving configuration's own ranges: L log-uniform in [64, 2048]
+    (multiples of 32), spins {0, +-1, +-2}, 1..32 maps per request.  50
+    sampled requests, 10 of them at L >= 1024, give the same result alone and
+    in the mix (same-L groups of several spins in one call; with graphs, one
+    spin per group and captured transforms where they fit), and each is a
+    round trip within the precision's bar."""
+    server = _server(precision=prec, streams=4, budget_bytes=48 << 30, graphs=graphs, graph_after=1,
+                     by_spin=bool(graphs))
+    reqs = sht_synth.trace(n_requests=240, rate_per_s=2000.0, L_lo=64, L_hi=2048, batch_hi=32,
+                           spins=(0, 1, -1, 2, -2), seed=sht_synth.SEED_BASE + 4300 + (7 if prec == "fp64" else 0))
+    server.warm((r.L, r.spin) for r in reqs)
+    big = [r.rid for r in reqs if r.L >= 1024][:10]
+    rest = [r.rid for r in reqs if r.rid not in big][::5][:40]
+    keep = sorted(big + rest)
+    assert len(big) == 10 and len(keep) == 50
+    print(f"[serving full range] {len(reqs)} requests {prec} graphs={graphs}", flush=True)
+    res, kept, stats = server.run(reqs, keep=keep, closed_loop=True)
+    print(f"[serving full range] groups: mean size {stats['mean_group_size']:.2f}, "
+          f"segments {stats['mean_segments']:.2f}, graph launches {stats.get('graph_launches')}", flush=True)
+    assert stats["requests"] == len(reqs) and all(r.status == "ok" for r in res)
+    assert stats["max_inflight_groups"] > 1 and stats["mean_group_size"] > 1.0
+    if not graphs:
+        assert stats["mean_segments"] > 1.0      # groups really carried several spins
+    else:
+        assert stats["graph_launches"] > 0
+    tol = 1e-5 if prec == "fp32" else 1e-10
+    bitwise = _check_alone_vs_mix(server, reqs, keep, kept, tol)
+    print(f"[serving full range] {bitwise} of {len(keep)} sampled requests bitwise equal alone and in the mix",
+          flush=True)
     server.close_graphs()
