@@ -4,8 +4,11 @@
 Workload (default): L = 1024, spins {0, +2, -2}, 16 maps per spin, complex
 Gaussian coefficients with C_l = 1/(l+1)^2 (sht_synth workload
 "L1024_s0pm2_b16").  One step = inverse then forward transform of every map of
-every spin (48 maps), inputs resident in HBM.  A "transform" is one map taken
-through inverse and forward, so value = 48 / step time.
+every spin (48 maps), inputs resident in HBM; one call per spin and direction
+(``--multi-spin``: the three spins through one ``sht_inverse_multi`` /
+``sht_forward_multi`` call per direction; the other pattern is timed too).  A
+"transform" is one map taken through inverse and forward, so value = 48 /
+step time.
 
 Prints one JSON line (rank 0):
   metric, value (transforms/s), ms_per_step, dtype, config,
@@ -15,9 +18,12 @@ Prints one JSON line (rank 0):
              contraction_flops / stage_bytes below; traffic = HBM bytes per
              launch from the committed counter summary (null if stale),
   cpu_baseline  the CPU oracle timed on a bounded sample (one map through
-             inverse + forward) on this host,
+             inverse + forward at L = 32, 256 and the workload's L) on this
+             host, with the threads it used,
   fp64_path, bf16x3_path  the same workload on the all-FP64 path and with the
-             BF16x3 contraction, for comparison,
+             BF16x3 contraction, each with its own roofline,
+  large_config  the largest single-GPU configuration (L = 2048, 4 maps, spin 0)
+             in FP32, BF16x3 and FP64, each with roofline and stages,
   stages     per-launch time and roofline fraction of every stage.
 """
 
@@ -99,20 +105,38 @@ def recorded_traffic(kernel: str, workload: str, prec: str):
     return None
 
 
-def run_steps(sht, torch, wl, prec, flm, steps, warmup, trace):
+def run_steps(sht, torch, wl, prec, flm, steps, warmup, trace, multi=True):
+    """Time ``steps`` steps (after ``warmup``): every map of every spin
+    through inverse then forward.  ``multi``: the spins in one multi-spin
+    call per direction (one contraction launch for all of them), else one
+    call per spin.  Returns (ms per step, per-stage (total ms, launches) or
+    None, {spin: forward result})."""
     L, B = wl.L, wl.batch
     dev = flm[wl.spins[0]].device
     dt = sht.io_dtype(prec)
-    maps = {s: torch.empty((B, L, 2 * L - 1), dtype=dt, device=dev) for s in wl.spins}
-    back = {s: torch.empty((B, L * L), dtype=dt, device=dev) for s in wl.spins}
-    ws = torch.empty(max(sht.workspace_bytes(L, s, B, prec) for s in wl.spins), dtype=torch.uint8, device=dev)
+    spins = list(wl.spins)
+    multi = multi and len(spins) > 1
+    if multi:
+        x = torch.cat([flm[s] for s in spins])
+        maps = torch.empty((len(spins) * B, L, 2 * L - 1), dtype=dt, device=dev)
+        backs = torch.empty((len(spins) * B, L * L), dtype=dt, device=dev)
+        ws = torch.empty(sht.workspace_bytes(L, 0, len(spins) * B, prec), dtype=torch.uint8, device=dev)
+        batches = [B] * len(spins)
 
-    def step():
-        for s in wl.spins:
-            sht.inverse(flm[s], L, s, prec, out=maps[s], workspace=ws)
-            sht.forward(maps[s], L, s, prec, out=back[s], workspace=ws)
+        def step():
+            sht.inverse_multi(x, L, spins, batches, prec, out=maps, workspace=ws)
+            sht.forward_multi(maps, L, spins, batches, prec, out=backs, workspace=ws)
+    else:
+        maps = {s: torch.empty((B, L, 2 * L - 1), dtype=dt, device=dev) for s in spins}
+        back = {s: torch.empty((B, L * L), dtype=dt, device=dev) for s in spins}
+        ws = torch.empty(max(sht.workspace_bytes(L, s, B, prec) for s in spins), dtype=torch.uint8, device=dev)
 
-    for s in wl.spins:
+        def step():
+            for s in spins:
+                sht.inverse(flm[s], L, s, prec, out=maps[s], workspace=ws)
+                sht.forward(maps[s], L, s, prec, out=back[s], workspace=ws)
+
+    for s in spins:
         sht.plan_warmup(L, s, prec)
     for _ in range(warmup):
         step()
@@ -129,28 +153,140 @@ def run_steps(sht, torch, wl, prec, flm, steps, warmup, trace):
     if trace:
         stages = sht.trace_read()
         sht.trace_enable(False)
+    if multi:
+        back = {s: backs[k * B:(k + 1) * B] for k, s in enumerate(spins)}
     return (t1 - t0) / steps * 1e3, stages, back
 
 
-def cpu_baseline(wl, seconds_hint: float = 30.0) -> dict:
-    """The oracle (never tuned) on one map of the workload: inverse + forward."""
+def finite(x):
+    """JSON-safe number: non-finite values (an exploded unstable solve) as strings."""
+    return x if math.isfinite(x) else str(x)
+
+
+def analyse(stages, wl, prec, steps, ms):
+    """Rooflines of one timed run from its per-stage trace: the dominant
+    kernel's achieved rate against its peak, every stage's per-launch time and
+    fraction of its own roofline, and the end-to-end fraction (the sum of
+    every launch's own bound over the measured step; the stages run one after
+    another).  Algorithmic units per step: contraction flops of every map of
+    every spin (x3 for BF16x3), stage bytes of every map."""
+    L, B, ns = wl.L, wl.batch, len(wl.spins)
+    cbytes = 16 if prec == "fp64" else 8
+    mult, pkey = MFMA_COST[prec]
+    per_step = {}
+    for k in stages:
+        if k.startswith("contract"):
+            per_step[k] = mult * sum(contraction_flops(L, s, B) for s in wl.spins)
+        else:
+            per_step[k] = stage_bytes(k, L, B * ns, cbytes)
+    stage_roof = {}
+    t_roof = 0.0
+    for k, (tot_ms, n) in stages.items():
+        if n == 0:
+            continue
+        t = tot_ms / 1e3                       # seconds over all timed steps
+        units = per_step[k] * steps
+        if k.startswith("contract"):
+            rate = units / t / 1e12
+            stage_roof[k] = {"ms": round(tot_ms / n, 4), "launches_per_step": n // steps,
+                             "TFLOP/s": round(rate, 2), "frac": round(rate / PEAK[pkey], 4)}
+            t_roof += per_step[k] / (PEAK[pkey] * 1e12)
+        else:
+            rate = units / t / 1e9
+            stage_roof[k] = {"ms": round(tot_ms / n, 4), "launches_per_step": n // steps,
+                             "GB/s": round(rate, 1), "frac": round(rate / PEAK["hbm_GBs"], 4)}
+            t_roof += per_step[k] / (PEAK["hbm_GBs"] * 1e9)
+    # the dominant kernel by time per step: the contraction kernel serves two
+    # stages (inverse and forward launches), every other stage is its own
+    groups = {"k_contract": ("contract_inv", "contract_fwd")}
+    groups.update({k: (k,) for k in stages if not k.startswith("contract")})
+    dominant = max(groups, key=lambda g: sum(stages[k][0] for k in groups[g]))
+    members = groups[dominant]
+    n_launch = sum(stages[k][1] for k in members)
+    t = sum(stages[k][0] for k in members) / 1e3
+    units = sum(per_step[k] for k in members) * steps
+    if dominant == "k_contract":
+        achieved = units / t / 1e12
+        roof = {"bound": "mfma", "kernel": "k_contract (inverse + forward launches)",
+                "achieved": round(achieved, 3), "peak": PEAK[pkey], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK[pkey], 4),
+                "traffic": recorded_traffic("k_contract", wl.name, prec),
+                "launches": n_launch, "avg_launch_ms": round(t * 1e3 / n_launch, 4)}
+    else:
+        achieved = units / t / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK["hbm_GBs"],
+                "unit": "GB/s", "frac": round(achieved / PEAK["hbm_GBs"], 4),
+                "traffic": recorded_traffic(dominant, wl.name, prec),
+                "launches": n_launch, "avg_launch_ms": round(t * 1e3 / n_launch, 4)}
+    end_to_end = {"roofline_ms_per_step": round(t_roof * 1e3, 4), "measured_ms_per_step": round(ms, 4),
+                  "frac": round(t_roof * 1e3 / ms, 4)}
+    return roof, stage_roof, end_to_end
+
+
+def round_trip(sht, flm, back, spins):
+    """The five error measures of Section 4.2 (on the device), worst spin each."""
+    rt = {}
+    for s in spins:
+        for k, v in sht.error_metrics(flm[s], back[s].to(flm[s].dtype)).items():
+            rt[k] = max(rt.get(k, 0.0), v)
+    return rt
+
+
+def leg(sht, torch, wl, prec, host_flm, steps, warmup, multi=True):
+    """One precision on one workload: throughput, round trip and rooflines."""
+    dev = torch.device("cuda", 0)
+    flm = {s: torch.from_numpy(host_flm[s]).to(dev, sht.io_dtype(prec)) for s in wl.spins}
+    ms, stages, back = run_steps(sht, torch, wl, prec, flm, steps, warmup, trace=True, multi=multi)
+    roof, stage_roof, e2e = analyse(stages, wl, prec, steps, ms)
+    rt = round_trip(sht, flm, back, wl.spins)
+    return {"value": round(len(wl.spins) * wl.batch / (ms / 1e3), 2), "unit": "transforms/s",
+            "ms_per_step": round(ms, 4), "steps": steps, "round_trip_rel_l2": float(f"{rt['rel_rms']:.4g}"),
+            "roofline": roof, "stages": stage_roof, "end_to_end_roofline": e2e}
+
+
+def cpu_baseline(wl) -> dict:
+    """The oracle (never tuned) on one map through inverse + forward, at L = 32
+    and 256 (median of 3) and at the workload's L (one run), on this host.
+    ``value`` is the workload-L rate; ``cores`` the threads the oracle's
+    libraries (BLAS, OpenMP) ran with; ``cpu_time_per_wall`` the process CPU
+    time over the wall time of the workload-L sample (how many of them it
+    kept busy)."""
     import numpy as np
     import oracle
+    import sht_synth
 
+    def once(L, s, spec, seed, f=None):
+        if f is None:
+            f = sht_synth.gaussian_flm(L, s, seed, spec)
+        w0, c0 = time.perf_counter(), time.process_time()
+        back = oracle.forward(oracle.inverse(f, L, s), L, s)
+        return time.perf_counter() - w0, time.process_time() - c0, oracle.rel_l2(f, back)
+
+    samples = {}
+    for L, s, spec in ((32, 0, "flat"), (256, 2, "inv_l_lp1")):
+        runs = [once(L, s, spec, sht_synth.SEED_BASE + 8200 + L + k) for k in range(3)]
+        dt = sorted(r[0] for r in runs)[1]
+        samples[f"L{L}_s{s}"] = {"transforms_per_s": round(1.0 / dt, 3), "s_per_map": round(dt, 4),
+                                 "round_trip_rel_l2": float(f"{runs[0][2]:.2g}")}
     s = wl.spins[-1]
-    flm = wl.flm(s)[:1]
-    t0 = time.perf_counter()
-    fmap = oracle.inverse_batch(flm, wl.L, s)
-    back = oracle.forward_batch(fmap, wl.L, s)
-    dt = time.perf_counter() - t0
-    err = oracle.rel_l2(flm, back)
-    omp = os.environ.get("OMP_NUM_THREADS")
-    cores = os.cpu_count() or 1
-    if omp and omp.isdigit():
-        cores = min(cores, int(omp))
-    return {"value": 1.0 / dt, "unit": "transforms/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 map, L={wl.L}, spin {s}, inverse + forward (numpy FP64 + C Risbo); "
-                      f"{dt:.1f} s; oracle round trip rel_l2 {err:.1e}"}
+    dt, cpu, err = once(wl.L, s, wl.spec, 0, f=wl.flm(s)[0])
+    samples[f"L{wl.L}_s{s}"] = {"transforms_per_s": round(1.0 / dt, 4), "s_per_map": round(dt, 2),
+                                "round_trip_rel_l2": float(f"{err:.2g}")}
+    threads = {}
+    try:
+        import threadpoolctl
+        for d in threadpoolctl.threadpool_info():
+            threads[d.get("user_api", "?")] = d.get("num_threads")
+    except ImportError:
+        pass
+    cores = max([v for v in threads.values() if isinstance(v, int)] or [1])
+    return {"value": round(1.0 / dt, 4), "unit": "transforms/s", "cores": cores, "kind": "oracle",
+            "blas_threads": threads.get("blas"), "openmp_threads": threads.get("openmp"),
+            "host_cpu_count": os.cpu_count(), "cpu_time_per_wall": round(cpu / dt, 2),
+            "sample": f"1 map each at L=32 (s=0), L=256 (s=2) and L={wl.L} (s={s}), inverse + forward "
+                      f"(numpy FP64 + C Risbo); value = the L={wl.L} rate ({dt:.1f} s per map); L=2048 takes "
+                      "about 7 minutes per map and is left out",
+            "samples": samples}
 
 
 def serving(n_requests: int, fractions, precision: str = "fp32", budget_gb: float = 16.0, graphs: int = 32) -> dict:
@@ -176,6 +312,7 @@ def serving(n_requests: int, fractions, precision: str = "fp32", budget_gb: floa
     out = {"requests": n_requests, "precision": precision, "budget_GB": budget_gb, "streams": sat["streams"],
            "graph_cache": graphs,
            "mix": "L log-uniform [64, 2048] step 32, spin {0, +-1, +-2}, batch 1..32, C_l = 1/(l+1)^2",
+           "grouping": "same-L requests of any spins in one multi-spin call",
            "saturation": {"requests_per_s": round(x, 2), "transforms_per_s": round(sat["transforms_per_s"], 1),
                           "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3),
                           "graph_launches": sat["graph_launches"], "graph_captures": sat["graph_captures"],
@@ -187,6 +324,7 @@ def serving(n_requests: int, fractions, precision: str = "fp32", budget_gb: floa
                                    "p99_ms": round(st["p99_ms"], 3),
                                    "transforms_per_s": round(st["transforms_per_s"], 1),
                                    "mean_group_size": round(st["mean_group_size"], 3),
+                                   "mean_spin_segments": round(st["mean_segments"], 3),
                                    "max_inflight_groups": st["max_inflight_groups"],
                                    "graph_launches": st["graph_launches"], "graph_captures": st["graph_captures"],
                                    **contraction_rate(res, st["makespan_s"])}
@@ -300,27 +438,47 @@ def real_test_functions(L: int, n: int):
     return np.stack(fs)
 
 
-def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict:
+def residual_structure(f, g, L: int) -> dict:
+    """Where the errors of a recovered coefficient set sit, by distance
+    d = l - |m| from the diagonal l = |m| (Section 4.2's residual figure):
+    the fraction of coefficients off by more than 1e-6, the median error near
+    the diagonal (d < 4) and far from it (d >= L/2), and the median d of the
+    coefficients off by more than 1e-6."""
+    import numpy as np
+    l_of = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
+    m_of = np.arange(L * L) - l_of * l_of - l_of
+    d = l_of - np.abs(m_of)
+    r = np.abs(np.asarray(g) - np.asarray(f))
+    r[~np.isfinite(r)] = np.inf
+    bad = r > 1e-6
+    return {"max": finite(float(r.max())), "frac_off_by_1e-6": round(float(bad.mean()), 4),
+            "median_near_diagonal": finite(float(f"{np.median(r[d < 4]):.3g}")),
+            "median_far_from_diagonal": finite(float(f"{np.median(r[d >= L // 2]):.3g}")),
+            "median_distance_of_bad": float(np.median(d[bad])) if bad.any() else None}
+
+
+def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), tri_max: int = 512, n_funcs: int = 5) -> dict:
     """The stability test of Section 4.2 on the GPU path: real spin-0 test
     functions with Re, Im ~ U[-1, 1] (f_{l,-m} = (-1)^m conj(f_lm), f_l0
     real), inverse then forward, the five error measures computed on the
     device and averaged over the functions.  Forwards: the quadrature (FP64
     and FP32) at every L, the paper's triangular systems and their all-rows
-    least-squares variant (FP64, up to L = 128)."""
+    least-squares variant (FP64, up to ``tri_max``).  Plus the residual
+    experiment: where the triangular forward's errors sit for one function
+    at L = 16, 32, 64, 128."""
     import numpy as np
     import torch
 
     import paper_0807_4494_amd as sht
-    import sht_synth
 
     dev = torch.device("cuda", 0)
     out = {"protocol": f"real spin-0 U[-1,1] test functions, {n_funcs} per L, inverse then forward; "
-                       "each measure averaged over the functions",
+                       "each measure averaged over the functions (an exploded solve reads 'inf' or 'nan')",
            "quadrature_fp64": {}, "quadrature_fp32": {}, "triangular_fp64": {}, "lstsq_fp64": {}}
     for L in Ls:
         flm = torch.from_numpy(real_test_functions(L, n_funcs)).to(dev)
         legs = [("quadrature_fp64", "fp64", None), ("quadrature_fp32", "fp32", None)]
-        if L <= 128:
+        if L <= tri_max:
             legs.append(("triangular_fp64", "fp64", "tri"))
             legs.append(("lstsq_fp64", "fp64", "lstsq"))
         for name, prec, kind in legs:
@@ -336,7 +494,14 @@ def stability(Ls=(8, 16, 32, 64, 128, 256, 512, 1024), n_funcs: int = 5) -> dict
             for k in range(n_funcs):
                 for key, v in sht.error_metrics(f_in[k], back[k].to(f_in.dtype)).items():
                     acc[key] = acc.get(key, 0.0) + v / n_funcs
-            out[name][str(L)] = {k: float(f"{v:.3g}") for k, v in acc.items()}
+            out[name][str(L)] = {k: finite(float(f"{v:.3g}")) for k, v in acc.items()}
+    rs = {}
+    for L in (16, 32, 64, 128):
+        f = real_test_functions(L, 1)[0]
+        fmap = sht.inverse(torch.from_numpy(f[None]).to(dev), L, 0, "fp64")
+        g = sht.forward_triangular(fmap, L, 0)[0].cpu().numpy()
+        rs[str(L)] = residual_structure(f, g, L)
+    out["triangular_residual_structure"] = rs
     return out
 
 
@@ -359,6 +524,10 @@ def main() -> int:
     ap.add_argument("--no-stability", action="store_true", help="skip the Section 4.2 stability leg")
     ap.add_argument("--tables", action="store_true",
                     help="also time the cached-table design (an L^3 table per spin, 4 GiB each in FP32 at L=1024)")
+    ap.add_argument("--multi-spin", action="store_true",
+                    help="one multi-spin call per direction (default: one call per spin and direction)")
+    ap.add_argument("--no-compare-calls", action="store_true", help="skip timing the other call pattern")
+    ap.add_argument("--no-large", action="store_true", help="skip the L=2048, 4-map configuration")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rates", default="0.7,0.5,0.9",
                     help="comma-separated fractions of the saturation rate (the first is the headline latency)")
@@ -381,86 +550,24 @@ def main() -> int:
     wl = {w.name: w for w in sht_synth.WORKLOADS}[args.workload]
     dev = torch.device("cuda", 0)
     prec = args.precision
+    multi = args.multi_spin
     host_flm = {s: wl.flm(s) for s in wl.spins}
     flm = {s: torch.from_numpy(host_flm[s]).to(dev, sht.io_dtype(prec)) for s in wl.spins}
 
-    ms, stages, back = run_steps(sht, torch, wl, prec, flm, args.steps, args.warmup, trace=True)
+    ms, stages, back = run_steps(sht, torch, wl, prec, flm, args.steps, args.warmup, trace=True, multi=multi)
     per_step = len(wl.spins) * wl.batch
     value = per_step / (ms / 1e3)
-
-    # round-trip error of the measured path (inverse then forward returns f_lm)
-    # (the five measures of the paper's stability test, on the device; worst
-    # spin for each)
-    rt_all = {}
-    for s in wl.spins:
-        for k, v in sht.error_metrics(flm[s], back[s].to(flm[s].dtype)).items():
-            rt_all[k] = max(rt_all.get(k, 0.0), v)
-    rt = rt_all["rel_rms"]
-
+    # round-trip error of the measured path (inverse then forward returns
+    # f_lm): the five measures of the paper's stability test, on the device,
+    # worst spin for each
+    rt_all = round_trip(sht, flm, back, wl.spins)
+    roof, stage_roof, end_to_end = analyse(stages, wl, prec, args.steps, ms)
     L, B = wl.L, wl.batch
     cbytes = 16 if prec == "fp64" else 8
-    stages_ms = {k: v[0] / args.steps for k, v in stages.items()}
-    counts = {k: v[1] for k, v in stages.items()}
-    # the dominant kernel by total time per step: the contraction kernel serves
-    # two stages (inverse and forward launches), every other stage is its own
-    groups = {"k_contract": ("contract_inv", "contract_fwd")}
-    groups.update({k: (k,) for k in stages_ms if not k.startswith("contract")})
-    dominant = max(groups, key=lambda g: sum(stages_ms[k] for k in groups[g]))
-    members = groups[dominant]
-    n_launch = sum(counts[k] for k in members)
-    t = sum(stages[k][0] for k in members) / 1e3
-    if dominant == "k_contract":
-        mult, pkey = MFMA_COST[prec]
-        flops = mult * sum(contraction_flops(L, s, B) for s in wl.spins for _ in members) * args.steps
-        achieved = flops / t / 1e12
-        peak = PEAK[pkey]
-        roof = {"bound": "mfma", "kernel": "k_contract (inverse + forward launches)",
-                "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4),
-                "traffic": recorded_traffic("k_contract", wl.name, prec),
-                "launches": n_launch, "avg_launch_ms": round(t * 1e3 / n_launch, 4)}
-    else:
-        by = stage_bytes(dominant, L, B, cbytes) * counts[dominant]
-        achieved = by / t / 1e9
-        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK["hbm_GBs"],
-                "unit": "GB/s", "frac": round(achieved / PEAK["hbm_GBs"], 4),
-                "traffic": recorded_traffic(dominant, wl.name, prec),
-                "launches": n_launch, "avg_launch_ms": round(t * 1e3 / n_launch, 4)}
-
-    # every stage against its own roofline
-    stage_roof = {}
-    for k, tot in stages.items():
-        if tot[1] == 0:
-            continue
-        avg_s = tot[0] / tot[1] / 1e3
-        if k.startswith("contract"):
-            mult, pkey = MFMA_COST[prec]
-            f = mult * sum(contraction_flops(L, s, B) for s in wl.spins) / len(wl.spins)
-            pk = PEAK[pkey]
-            stage_roof[k] = {"ms": round(avg_s * 1e3, 4), "TFLOP/s": round(f / avg_s / 1e12, 2),
-                             "frac": round(f / avg_s / 1e12 / pk, 4)}
-        else:
-            b = stage_bytes(k, L, B, cbytes)
-            stage_roof[k] = {"ms": round(avg_s * 1e3, 4), "GB/s": round(b / avg_s / 1e9, 1),
-                             "frac": round(b / avg_s / 1e9 / PEAK["hbm_GBs"], 4)}
-
-    # end to end: the stages run one after another, so the roofline time of a
-    # step is the sum of every launch's own bound (flops / MFMA peak for the
-    # contraction, algorithmic bytes / HBM peak for the other stages)
-    t_roof = 0.0
-    for k, tot in stages.items():
-        per_launch = tot[1] / args.steps
-        if k.startswith("contract"):
-            mult, pkey = MFMA_COST[prec]
-            t_roof += sum(mult * contraction_flops(L, s, B) for s in wl.spins) / (PEAK[pkey] * 1e12) \
-                * per_launch / len(wl.spins)
-        else:
-            t_roof += stage_bytes(k, L, B, cbytes) / (PEAK["hbm_GBs"] * 1e9) * per_launch
-    end_to_end = {"roofline_ms_per_step": round(t_roof * 1e3, 4), "measured_ms_per_step": round(ms, 4),
-                  "frac": round(t_roof * 1e3 / ms, 4)}
+    spins_txt = ",".join(f"{s:+d}" if s else "0" for s in wl.spins)
 
     out = {
-        "metric": "spin SHT fwd+inv transforms/sec at L=1024 batch 16",
+        "metric": f"spin SHT fwd+inv transforms/sec at L={L} batch {B} (spins {spins_txt})",
         "value": round(value, 2),
         "unit": "transforms/s",
         "n_gpus": 1,
@@ -474,28 +581,33 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl.name, "L": L, "batch": B, "spins": list(wl.spins),
                    "spectrum": SPECTRA.get(wl.spec, wl.spec), "precision": prec,
-                   "maps_per_step": per_step, "wigner_recursion": "f64"},
+                   "maps_per_step": per_step, "wigner_recursion": "f64",
+                   "calls": "one multi-spin call per direction" if multi and len(wl.spins) > 1
+                   else "one call per spin and direction"},
         "roofline": roof,
-        "round_trip_rel_l2": rt,
+        "round_trip_rel_l2": rt_all["rel_rms"],
         "round_trip_metrics": {k: float(f"{v:.4g}") for k, v in rt_all.items()},
         "stages": stage_roof,
         "end_to_end_roofline": end_to_end,
     }
+    if len(wl.spins) > 1 and not args.no_compare_calls:
+        # the other call pattern, for comparison
+        n_c = max(2, min(args.steps, 10))
+        ms_c, _, _ = run_steps(sht, torch, wl, prec, flm, n_c, 1, trace=False, multi=not multi)
+        out["other_call_pattern"] = {"calls": "one call per spin and direction" if multi
+                                     else "one multi-spin call per direction",
+                                     "value": round(per_step / (ms_c / 1e3), 2), "ms_per_step": round(ms_c, 4)}
     if not args.no_fp64 and prec != "fp64":
-        flm64 = {s: torch.from_numpy(host_flm[s]).to(dev, torch.complex128) for s in wl.spins}
-        n64 = max(2, min(args.steps, 5))
-        ms64, st64, back64 = run_steps(sht, torch, wl, "fp64", flm64, n64, 1, trace=False)
-        rt64 = max(float(torch.linalg.vector_norm(back64[s] - flm64[s]) / torch.linalg.vector_norm(flm64[s]))
-                   for s in wl.spins)
-        out["fp64_path"] = {"value": round(per_step / (ms64 / 1e3), 2), "ms_per_step": round(ms64, 4),
-                            "steps": n64, "round_trip_rel_l2": rt64}
+        out["fp64_path"] = leg(sht, torch, wl, "fp64", host_flm, max(2, min(args.steps, 5)), 1, multi)
     if not args.no_bf16x3 and prec == "fp32":
-        n3 = max(2, min(args.steps, 10))
-        ms3, _, back3 = run_steps(sht, torch, wl, "bf16x3", flm, n3, 1, trace=False)
-        rt3 = max(float(torch.linalg.vector_norm(back3[s] - flm[s]) / torch.linalg.vector_norm(flm[s]))
-                  for s in wl.spins)
-        out["bf16x3_path"] = {"value": round(per_step / (ms3 / 1e3), 2), "ms_per_step": round(ms3, 4),
-                              "steps": n3, "round_trip_rel_l2": rt3}
+        out["bf16x3_path"] = leg(sht, torch, wl, "bf16x3", host_flm, max(2, min(args.steps, 10)), 1, multi)
+    if not args.no_large and wl.name != "L2048_s0_b4":
+        big = {w.name: w for w in sht_synth.WORKLOADS}["L2048_s0_b4"]
+        big_flm = {s: big.flm(s) for s in big.spins}
+        out["large_config"] = {
+            "workload": big.name, "L": big.L, "batch": big.batch, "spins": list(big.spins),
+            "spectrum": SPECTRA.get(big.spec, big.spec),
+            **{p: leg(sht, torch, big, p, big_flm, n, 1) for p, n in (("fp32", 5), ("bf16x3", 5), ("fp64", 3))}}
     if not args.no_real and prec != "fp64":
         # real spin-0 maps (only m >= 0 transformed): the same L and batch
         # coefficients of real signals: the spin-0 maps with f_{l0} made real
@@ -531,7 +643,7 @@ def main() -> int:
         for s in wl.spins:
             sht.plan_tables(L, s, prec, True)
         n_t = max(2, min(args.steps, 10))
-        ms_t, st_t, back_t = run_steps(sht, torch, wl, prec, flm, n_t, 1, trace=True)
+        ms_t, st_t, back_t = run_steps(sht, torch, wl, prec, flm, n_t, 1, trace=True, multi=multi)
         rt_t = max(float(torch.linalg.vector_norm(back_t[s] - flm[s]) / torch.linalg.vector_norm(flm[s]))
                    for s in wl.spins)
         for s in wl.spins:

@@ -62,7 +62,7 @@ extern "C" {
 #define SHT_VERSION 10000          /* 1.0.0 */
 #define SHT_L_MAX 4096
 #define SHT_BATCH_MAX 64
-#define SHT_TRI_L_MAX 128          /* largest L of sht_forward_triangular */
+#define SHT_TRI_L_MAX 512          /* largest L of sht_forward_triangular / _lstsq */
 #define SHT_MULTI_SEG_MAX 8        /* spin segments of one sht_*_multi call */
 
 enum sht_status {

@@ -24,7 +24,7 @@ SHT_ERR_NOT_READY = -8
 
 SHT_SAMPLING_MW = 0
 SHT_FP64, SHT_FP32, SHT_BF16X3 = 0, 1, 2
-SHT_TRI_L_MAX = 128
+SHT_TRI_L_MAX = 512
 SHT_MULTI_SEG_MAX = 8
 SHT_BATCH_MAX = 64
 SHT_L_MAX = 4096

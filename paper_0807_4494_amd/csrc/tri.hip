@@ -12,7 +12,9 @@
 // paper's, including its instability beyond small L (Section 4.2); it is
 // offered for L <= SHT_TRI_L_MAX.
 //
-// One workgroup per order.  Thread j (= m') runs the l-chain of
+// One workgroup per order (beyond L = kTriLdsMaxL a persistent workgroup
+// takes orders in turn and keeps D in its own slot of global scratch: the
+// L x L factor no longer fits in LDS).  Thread j (= m') runs the l-chain of
 // Delta^l_{j |m0|} (chain.h, the same recursion and edge seeds as the
 // contraction) and writes its row of the real factor of D into LDS, stored
 // transposed, Dt[l][j], so that the column a back-substitution step needs is
@@ -20,25 +22,45 @@
 // and applied to the solution.  Maps are solved MB at a time with one
 // accumulator per thread and map: at step l thread l forms
 // x_l = acc_l / D[l][l], publishes it through LDS, and every thread j < l
-// subtracts D[j][l] x_l from its own accumulator.
+// subtracts D[j][l] x_l from its own accumulator.  For spin 0 the system
+// splits into the independent rows and columns of even and of odd l + m'
+// (D vanishes elsewhere, Eq. (wignerd_sym6); Section 3.4.2): a step only
+// updates the rows of its own parity class, so the two classes are solved
+// as separate systems.
 #include "chain.h"
 
 namespace sht {
 
 namespace {
 
-constexpr int MB = 8;  // maps per pass
+constexpr int MB = 8;              // maps per pass
+constexpr int kTriThreads = 512;   // one thread per row: L <= SHT_TRI_L_MAX
+constexpr int kTriLdsMaxL = 128;   // D in LDS up to this L, in a global slot beyond
+constexpr int kTriSlots = 256;     // persistent workgroups (global slots) beyond it
 
-__global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_solve(int L, int s, int B, const cplx64 *__restrict__ F,
-                                                            cplx64 *__restrict__ flm, EdgeTable E,
-                                                            const double *__restrict__ wi,
-                                                            const double *__restrict__ ri,
-                                                            const double2 *__restrict__ fab) {
+// Orders o = blockIdx.x, blockIdx.x + gridDim.x, ... (one per workgroup when
+// the grid has one workgroup per order).
+template <typename F> __device__ __forceinline__ void for_orders(int norders, F body) {
+    for (int o = blockIdx.x; o < norders; o += gridDim.x) {
+        body(o);
+        __syncthreads();
+    }
+}
+
+template <bool GLB>
+__global__ __launch_bounds__(kTriThreads) void k_tri_solve(int L, int s, int B, const cplx64 *__restrict__ F,
+                                                          cplx64 *__restrict__ flm, EdgeTable E,
+                                                          const double *__restrict__ wi,
+                                                          const double *__restrict__ ri,
+                                                          const double2 *__restrict__ fab, double *gscr) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *Dt = reinterpret_cast<double *>(smem_raw);            // [L][L]
-    cplx64 *xs = reinterpret_cast<cplx64 *>(Dt + (size_t)L * L);  // [MB][L]
+    // Dt [L][L]: LDS, or this workgroup's global slot
+    double *Dt = GLB ? gscr + (size_t)blockIdx.x * L * L : reinterpret_cast<double *>(smem_raw);
+    cplx64 *xs = GLB ? reinterpret_cast<cplx64 *>(smem_raw)
+                     : reinterpret_cast<cplx64 *>(Dt + (size_t)L * L);  // [MB][L]
     const int N = 2 * L - 1, h = L - 1;
-    const int m0 = (int)blockIdx.x - h;
+    for_orders(N, [&](int o) {
+    const int m0 = o - h;
     const int am = m0 < 0 ? -m0 : m0;
     const int as = s < 0 ? -s : s;
     const int l0 = am > as ? am : as;
@@ -82,7 +104,7 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_solve(int L, int s, int B
                 for (int q = 0; q < MB; ++q) xs[q * L + l] = cplx64{acc[q].x * inv, acc[q].y * inv};
             }
             __syncthreads();
-            if (j >= l0 && j < l) {
+            if (j >= l0 && j < l && (s != 0 || ((l - j) & 1) == 0)) {
                 const double dj = Dt[(size_t)l * L + j];
 #pragma unroll
                 for (int q = 0; q < MB; ++q) {
@@ -111,6 +133,7 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_solve(int L, int s, int B
         }
         __syncthreads();
     }
+    });
 }
 
 // The stable comparison: for one order, all rows m' = 0 .. L-1 of the same
@@ -124,6 +147,9 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_solve(int L, int s, int B
 // with at most 2-way bank conflicts:
 //   w = D p:    thread j sums Dt[l][j] p_l over l >= max(j, l0)
 //   z = D^T r:  thread l sums Dt[l][j] r_j over j <= l
+// With D in global memory (beyond kTriLdsMaxL) the second product reads a
+// row-major copy Dr[j][l] instead, so that both read consecutive addresses
+// across the threads.
 constexpr int MBL = 4;
 constexpr int NV = 2 * MBL;
 constexpr double kLsqTol = 1e-28;  // on |z|^2, i.e. 1e-14 on |z|
@@ -134,18 +160,22 @@ __device__ inline double wave_sum64(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_lstsq(int L, int s, int B, const cplx64 *__restrict__ F,
-                                                            cplx64 *__restrict__ flm, EdgeTable E,
-                                                            const double *__restrict__ wi,
-                                                            const double *__restrict__ ri,
-                                                            const double2 *__restrict__ fab) {
+template <bool GLB>
+__global__ __launch_bounds__(kTriThreads) void k_tri_lstsq(int L, int s, int B, const cplx64 *__restrict__ F,
+                                                          cplx64 *__restrict__ flm, EdgeTable E,
+                                                          const double *__restrict__ wi,
+                                                          const double *__restrict__ ri,
+                                                          const double2 *__restrict__ fab, double *gscr) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int LP = L + 1;
-    double *Dt = reinterpret_cast<double *>(smem_raw);  // [L][L + 1]
-    double *vs = Dt + (size_t)L * LP;                   // [NV][L]: p, then r, shared by all threads
+    // Dt [L][L + 1] (and, in global memory, Dr [L][L]): LDS, or this workgroup's slot
+    double *Dt = GLB ? gscr + (size_t)blockIdx.x * L * (LP + L) : reinterpret_cast<double *>(smem_raw);
+    double *Dr = GLB ? Dt + (size_t)L * LP : nullptr;
+    double *vs = GLB ? reinterpret_cast<double *>(smem_raw) : Dt + (size_t)L * LP;  // [NV][L]: p, then r
     double *red = vs + (size_t)NV * L;                  // [NV][waves] partial sums
     const int N = 2 * L - 1, h = L - 1;
-    const int m0 = (int)blockIdx.x - h;
+    for_orders(N, [&](int o) {
+    const int m0 = o - h;
     const int am = m0 < 0 ? -m0 : m0;
     const int as = s < 0 ? -s : s;
     const int l0 = am > as ? am : as;
@@ -153,6 +183,9 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_lstsq(int L, int s, int B
 
     // ---- the real factor of D at columns l >= l0, every row j ----
     for (int i = t; i < L * LP; i += blockDim.x) Dt[i] = 0.0;
+    if constexpr (GLB) {
+        for (int i = t; i < L * L; i += blockDim.x) Dr[i] = 0.0;
+    }
     __syncthreads();
     if (t < L) {
         const int j = t;
@@ -164,7 +197,9 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_lstsq(int L, int s, int B
             if (l >= l0) {
                 double d = c.value();
                 if (m0 < 0 && ((l + j) & 1)) d = -d;  // Delta^l_{j,-m} = (-1)^{l+j} Delta^l_{jm}
-                Dt[(size_t)l * LP + j] = wi[(size_t)l * L + j] * d;
+                const double v = wi[(size_t)l * L + j] * d;
+                Dt[(size_t)l * LP + j] = v;
+                if constexpr (GLB) Dr[(size_t)j * L + l] = v;
             }
             if (l + 1 < L) {
                 const double r = ri[(size_t)l * L + j];
@@ -204,9 +239,8 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_lstsq(int L, int s, int B
 #pragma unroll
         for (int k = 0; k < NV; ++k) z[k] = 0.0;
         if (col) {
-            const double *dl = Dt + (size_t)t * LP;
             for (int j = 0; j <= t; ++j) {
-                const double d = dl[j];
+                const double d = GLB ? Dr[(size_t)j * L + t] : Dt[(size_t)t * LP + j];
 #pragma unroll
                 for (int k = 0; k < NV; ++k) z[k] += d * vs[k * L + j];
             }
@@ -302,38 +336,57 @@ __global__ __launch_bounds__(SHT_TRI_L_MAX) void k_tri_lstsq(int L, int s, int B
             }
         }
     }
+    });
 }
 
 }  // namespace
 
-hipError_t launch_tri_lstsq(int L, int s, int B, const void *F, void *flm, const EdgeTable &E, const SpinPlan &sp,
-                            const RecTables &rt, hipStream_t st) {
+// Launch of one of the kernels above: one workgroup per order with D in LDS
+// up to kTriLdsMaxL, else kTriSlots persistent workgroups with D in global
+// slots allocated on the stream (stream-ordered, freed after the launch).
+template <typename K>
+hipError_t tri_launch(K klds, K kglb, int L, size_t lds_small, size_t lds_glb, size_t slot_doubles, int s, int B,
+                      const void *F, void *flm, const EdgeTable &E, const SpinPlan &sp, const RecTables &rt,
+                      hipStream_t st) {
     if (L > SHT_TRI_L_MAX) return hipErrorInvalidValue;
     const int threads = ((L + 63) / 64) * 64;
-    const size_t lds = ((size_t)L * (L + 1) + (size_t)NV * L + (size_t)NV * (threads / 64)) * sizeof(double);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_tri_lstsq, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
+    const int norders = 2 * L - 1;
+    if (L <= kTriLdsMaxL) {
+        if (lds_small > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void *)klds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds_small);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(klds, dim3(norders), dim3(threads), lds_small, st, L, s, B, (const cplx64 *)F,
+                           (cplx64 *)flm, E, sp.wi, rt.ri, rt.fab, (double *)nullptr);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_tri_lstsq, dim3(2 * L - 1), dim3(threads), lds, st, L, s, B, (const cplx64 *)F,
-                       (cplx64 *)flm, E, sp.wi, rt.ri, rt.fab);
-    return hipGetLastError();
+    const int grid = norders < kTriSlots ? norders : kTriSlots;
+    double *scr = nullptr;
+    hipError_t e = hipMallocAsync((void **)&scr, (size_t)grid * slot_doubles * sizeof(double), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kglb, dim3(grid), dim3(threads), lds_glb, st, L, s, B, (const cplx64 *)F, (cplx64 *)flm, E,
+                       sp.wi, rt.ri, rt.fab, scr);
+    e = hipGetLastError();
+    const hipError_t ef = hipFreeAsync(scr, st);
+    return e != hipSuccess ? e : ef;
+}
+
+hipError_t launch_tri_lstsq(int L, int s, int B, const void *F, void *flm, const EdgeTable &E, const SpinPlan &sp,
+                            const RecTables &rt, hipStream_t st) {
+    const int nw = (L + 63) / 64;
+    const size_t vecs = ((size_t)NV * L + (size_t)NV * nw) * sizeof(double);
+    const size_t lds_small = (size_t)L * (L + 1) * sizeof(double) + vecs;
+    return tri_launch(k_tri_lstsq<false>, k_tri_lstsq<true>, L, lds_small, vecs, (size_t)L * (2 * L + 1), s, B, F,
+                      flm, E, sp, rt, st);
 }
 
 hipError_t launch_tri_solve(int L, int s, int B, const void *F, void *flm, const EdgeTable &E, const SpinPlan &sp,
                             const RecTables &rt, hipStream_t st) {
-    if (L > SHT_TRI_L_MAX) return hipErrorInvalidValue;
-    const size_t lds = (size_t)L * L * sizeof(double) + (size_t)MB * L * sizeof(cplx64);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_tri_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    const int threads = ((L + 63) / 64) * 64;
-    hipLaunchKernelGGL(k_tri_solve, dim3(2 * L - 1), dim3(threads), lds, st, L, s, B, (const cplx64 *)F,
-                       (cplx64 *)flm, E, sp.wi, rt.ri, rt.fab);
-    return hipGetLastError();
+    const size_t xs = (size_t)MB * L * sizeof(cplx64);
+    const size_t lds_small = (size_t)L * L * sizeof(double) + xs;
+    return tri_launch(k_tri_solve<false>, k_tri_solve<true>, L, lds_small, xs, (size_t)L * L, s, B, F, flm, E, sp,
+                      rt, st);
 }
 
 }  // namespace sht

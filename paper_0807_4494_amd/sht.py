@@ -275,7 +275,7 @@ def _forward_tri(fmap, L, spin, out, workspace, entry):
 def forward_triangular(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch.Tensor] = None,
                        workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The paper's own forward transform (per-order triangular systems), FP64,
-    L <= 128.  Ill conditioned beyond small L; see :func:`forward`."""
+    L <= 512.  Ill conditioned beyond small L; see :func:`forward`."""
     return _forward_tri(fmap, L, spin, out, workspace, "sht_forward_triangular")
 
 
@@ -283,7 +283,7 @@ def forward_lstsq(fmap: torch.Tensor, L: int, spin: int = 0, out: Optional[torch
                   workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """All rows of the per-order systems, least squares (the stable
     comparison to :func:`forward_triangular`; not the paper's method), FP64,
-    L <= 128."""
+    L <= 512."""
     return _forward_tri(fmap, L, spin, out, workspace, "sht_forward_lstsq")
 
 

@@ -162,7 +162,7 @@ def test_triangular_forward_matches_oracle(L, s):
     B = 3
     flm = np.stack([sht_synth.gaussian_flm(L, s, 600 + 17 * L + b) for b in range(B)])
     fmap = oracle.inverse_batch(flm, L, s)
-    ref = np.stack([T.forward_triangular(fmap[b], L, s, split_spin0=False) for b in range(B)])
+    ref = np.stack([T.forward_triangular(fmap[b], L, s, split_spin0=(s == 0)) for b in range(B)])
     got = sht.forward_triangular(to_dev(fmap, "fp64"), L, s).cpu().numpy()
     assert rel(ref, got) < 1e-10, rel(ref, got)
     assert rel(flm, got) < 1e-9
@@ -188,6 +188,88 @@ def test_least_squares_forward_matches_oracle(L, s):
     got = sht.forward_lstsq(to_dev(noisy, "fp64"), L, s).cpu().numpy()
     ref = np.stack([T.forward_lstsq(noisy[b], L, s) for b in range(2)])
     assert rel(ref, got) < 1e-10, rel(ref, got)
+
+
+@pytest.mark.parametrize("L,s", [(64, 0), (128, 2), (160, -1)])
+def test_least_squares_forward_matches_oracle_at_larger_band_limits(L, s):
+    """The all-rows systems stay well conditioned as L grows: the GPU solve
+    (D in LDS up to L = 128, in global memory beyond) equals the oracle's
+    dense least squares, and both return the band-limited coefficients."""
+    sht = _sht()
+    print(f"[least squares] L={L} s={s}", flush=True)
+    from oracle import triangular as T
+    flm = sht_synth.gaussian_flm(L, s, 760 + L)[None]
+    fmap = oracle.inverse_batch(flm, L, s)
+    got = sht.forward_lstsq(to_dev(fmap, "fp64"), L, s).cpu().numpy()
+    ref = T.forward_lstsq(fmap[0], L, s)[None]
+    assert rel(ref, got) < 1e-11, rel(ref, got)
+    assert rel(flm, got) < 1e-11
+
+
+def test_triangular_forward_far_from_the_diagonal_beyond_lds():
+    """L = 160 (D in global memory): the paper's solve has lost the
+    coefficients near the diagonal l = |m| (Section 4.2) but still recovers
+    those far from it, l - |m| >= 3L/4, as the oracle's solve does."""
+    sht = _sht()
+    from oracle import triangular as T
+    L = 160
+    f = _real_test_function(L, 31)
+    fmap = sht.inverse(to_dev(f, "fp64"), L, 0, "fp64")
+    g = sht.forward_triangular(fmap, L, 0).cpu().numpy()
+    l_of = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
+    m_of = np.arange(L * L) - l_of * l_of - l_of
+    far = (l_of - np.abs(m_of)) >= 3 * L // 4
+    ref = T.forward_triangular(oracle.inverse(f, L, 0), L, 0)
+    assert np.abs(ref - f)[far].max() < 1e-9
+    assert np.abs(g - f)[far].max() < 1e-9, np.abs(g - f)[far].max()
+    assert np.abs(g - f).max() > 1e-3          # and near the diagonal it is lost
+
+
+def _real_test_function(L, seed):
+    """A real spin-0 test function of Section 4.2: Re, Im of f_lm (m > 0)
+    from U[-1, 1], f_l0 real, f_{l,-m} = (-1)^m conj(f_lm)."""
+    f = sht_synth.uniform_flm(L, 0, seed)
+    for l in range(L):
+        for m in range(1, l + 1):
+            f[l * l + l - m] = (-1) ** m * np.conj(f[l * l + l + m])
+        f[l * l + l] = f[l * l + l].real
+    return f
+
+
+def residual_structure(f, g, L):
+    """Where the errors of a recovered real spin-0 function sit, by distance
+    d = l - |m| from the diagonal: the fraction of coefficients off by more
+    than 1e-6, the median error near the diagonal (d < 4) and far from it
+    (d >= L/2), and the median d of the coefficients off by more than 1e-6."""
+    l_of = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
+    m_of = np.arange(L * L) - l_of * l_of - l_of
+    d = l_of - np.abs(m_of)
+    r = np.abs(np.asarray(g) - np.asarray(f))
+    bad = r > 1e-6
+    return {"max": float(r.max()), "frac_bad": float(bad.mean()),
+            "median_near_diagonal": float(np.median(r[d < 4])), "median_far": float(np.median(r[d >= L // 2])),
+            "median_d_of_bad": float(np.median(d[bad])) if bad.any() else None}
+
+
+def test_residual_structure_of_the_paper_forward():
+    """Section 4.2's residual experiment on the GPU path: one real spin-0
+    U[-1, 1] function through the inverse and the paper's triangular forward.
+    At L = 16 and 32 the coefficients are recovered; at L = 64 the first
+    large errors sit near the diagonal l = |m| while coefficients far from it
+    stay exact; by L = 128 most coefficients are poor."""
+    sht = _sht()
+    rs = {}
+    for L in (16, 32, 64, 128):
+        f = _real_test_function(L, 4400 + L)
+        fmap = sht.inverse(to_dev(f, "fp64"), L, 0, "fp64")
+        g = sht.forward_triangular(fmap, L, 0).cpu().numpy()
+        rs[L] = residual_structure(f, g, L)
+    print(f"[residual structure] {rs}", flush=True)
+    assert rs[16]["max"] < 1e-9
+    assert rs[32]["frac_bad"] < 0.05 and rs[32]["median_far"] < 1e-13
+    assert rs[64]["median_near_diagonal"] > 1e6 * rs[64]["median_far"]
+    assert rs[64]["median_far"] < 1e-12 and rs[64]["median_d_of_bad"] < 64 // 4
+    assert rs[128]["frac_bad"] > 0.5
 
 
 @pytest.mark.parametrize("s", [0, 2, -3])
