@@ -112,7 +112,7 @@ void regions(int L, int batch, int precision, size_t &ra, size_t &rb) {
     const size_t T = elem_bytes(precision);
     const size_t C = 4 * (size_t)batch, N = 2 * (size_t)L - 1;
     const size_t panel = (size_t)L * C * L * T;
-    const size_t grid = (size_t)batch * L * N * 2 * T;
+    const size_t grid = (size_t)batch * L * 2 * (size_t)L * 2 * T;  // rings of ring_len = 2L (>= N)
     ra = align256(panel > grid ? panel : grid);
     rb = ra;
 }
@@ -312,7 +312,7 @@ int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     void *scr = w + ra + rb;  // split-row scratch (L > 2048, FP64)
     const int nq = real ? 2 : 4, Cn = nq * batch;
     const size_t cb = 2 * sizeof(T);                           // bytes per complex
-    const size_t ring = (size_t)L * (real ? L : 2 * L - 1);    // ring entries per map (theta stage output)
+    const size_t ring = (size_t)L * ring_len(L, real);         // ring entries per map (theta stage output)
     for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
         const void *f = (const unsigned char *)flm + (size_t)off * L * L * cb;
         SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st,
@@ -335,7 +335,7 @@ int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     SHT_HIP(traced(SHT_STAGE_PHI_INV, st,
                    [&] {
                        return real ? launch_phi_inv_real<T>(ft, batch, (const void *)P, (T *)map, scr, st)
-                                   : launch_phi_inv<T>(ft, batch, (const void *)P, map, scr, st);
+                                   : launch_phi_inv<T>(ft, batch, ring_len(L, false), (const void *)P, map, scr, st);
                    }),
             "phi inverse");
     return SHT_OK;
@@ -354,11 +354,11 @@ int run_forward(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     void *scr = w + ra + rb;      // split-row scratch (L > 2048, FP64)
     const int nq = real ? 2 : 4, Cn = nq * batch;
     const size_t cb = 2 * sizeof(T);
-    const size_t ring = (size_t)L * (real ? L : 2 * L - 1);
+    const size_t ring = (size_t)L * ring_len(L, real);
     SHT_HIP(traced(SHT_STAGE_PHI_FWD, st,
                    [&] {
                        return real ? launch_phi_fwd_real<T>(ft, batch, (const T *)map, Q, scr, st)
-                                   : launch_phi_fwd<T>(ft, batch, map, Q, scr, st);
+                                   : launch_phi_fwd<T>(ft, batch, ring_len(L, false), map, Q, scr, st);
                    }),
             "phi forward");
     // the theta stage reads its two orders as columns of the rings in place
@@ -557,7 +557,7 @@ int sht_forward_triangular(int L, int spin, int batch, int sampling, int precisi
     void *A = (void *)w;         // phi-stage output, later the torus coefficients
     void *Bq = (void *)(w + ra); // the same rows over t
     const FftTables<double> &ft = plan->f64;
-    SHT_HIP(launch_phi_fwd<double>(ft, batch, map, A, nullptr, st), "phi forward");
+    SHT_HIP(launch_phi_fwd<double>(ft, batch, ft.N, map, A, nullptr, st), "phi forward");
     SHT_HIP(launch_transpose<double>(batch, L, ft.N, A, Bq, st), "transpose");
     SHT_HIP(launch_theta_dft<double>(ft, spin, batch, Bq, A, st), "theta dft");
     SHT_HIP(launch_tri_solve(L, spin, batch, A, flm, ds->E, *sp, plan->rec, st), "triangular solve");
@@ -583,7 +583,7 @@ int sht_forward_lstsq(int L, int spin, int batch, int sampling, int precision, c
     void *A = (void *)w;         // phi-stage output, later the torus coefficients
     void *Bq = (void *)(w + ra); // the same rows over t
     const FftTables<double> &ft = plan->f64;
-    SHT_HIP(launch_phi_fwd<double>(ft, batch, map, A, nullptr, st), "phi forward");
+    SHT_HIP(launch_phi_fwd<double>(ft, batch, ft.N, map, A, nullptr, st), "phi forward");
     SHT_HIP(launch_transpose<double>(batch, L, ft.N, A, Bq, st), "transpose");
     SHT_HIP(launch_theta_dft<double>(ft, spin, batch, Bq, A, st), "theta dft");
     SHT_HIP(launch_tri_lstsq(L, spin, batch, A, flm, ds->E, *sp, plan->rec, st), "least-squares solve");

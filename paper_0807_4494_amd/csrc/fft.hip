@@ -420,6 +420,39 @@ template <bool SPLIT, typename F> __device__ __forceinline__ void for_items(int 
     }
 }
 
+// dst[i] = src[i] for i < n, with 16-byte loads and stores when n allows
+// (src and dst 16-byte aligned then: rows of n values from aligned bases).
+template <typename T> __device__ __forceinline__ void stage_row(T *dst, const T *src, int n) {
+    constexpr int V = 16 / (int)sizeof(T);
+    if (n % V == 0) {
+        typedef T vec __attribute__((ext_vector_type(V)));
+        const vec *s = reinterpret_cast<const vec *>(src);
+        vec *d = reinterpret_cast<vec *>(dst);
+        for (int i = threadIdx.x; i < n / V; i += blockDim.x) d[i] = s[i];
+    } else {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    }
+}
+
+// The two adjacent complex values g[0], g[1] as one aligned piece (16 bytes
+// for complex float; two 16-byte stores for complex double).
+__device__ __forceinline__ void store_pair(cplx32 *g, cplx32 a, cplx32 b) {
+    *reinterpret_cast<float4 *>(g) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void store_pair(cplx64 *g, cplx64 a, cplx64 b) {
+    g[0] = a;
+    g[1] = b;
+}
+__device__ __forceinline__ void load_pair(const cplx32 *g, cplx32 &a, cplx32 &b) {
+    const float4 v = *reinterpret_cast<const float4 *>(g);
+    a = cplx32{v.x, v.y};
+    b = cplx32{v.z, v.w};
+}
+__device__ __forceinline__ void load_pair(const cplx64 *g, cplx64 &a, cplx64 &b) {
+    a = g[0];
+    b = g[1];
+}
+
 // Clamped load p[min(n, N-1)]: the chirp-z functors read unconditionally and
 // select zero afterwards, so that the loads of a pass issue together instead
 // of one branch (and one wait) per point.
@@ -472,9 +505,19 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
     const Row ra = row_of(mua), rb = row_of(two ? mua + 1 : mua);
-    auto coef = [&](const Row &r, int n) -> C {
+    // the four contraction rows (re, im of both orders, m' = 0..L-1) staged
+    // in LDS with 16-byte loads, each read once; the fill of m' < 0 below
+    // reads them back mirrored (the FFT's first pass only overwrites the
+    // buffer after its loads)
+    T *sr = reinterpret_cast<T *>(buf);
+    stage_row(sr, ra.re, L);
+    stage_row(sr + L, ra.im, L);
+    stage_row(sr + 2 * L, rb.re, L);
+    stage_row(sr + 3 * L, rb.im, L);
+    __syncthreads();
+    auto coef = [&](const Row &r, const T *s2, int n) -> C {
         const int mp = n - h, amp = mp < 0 ? -mp : mp;
-        C F{r.re[amp] * sgn_s, r.im[amp] * sgn_s};
+        C F{s2[amp] * sgn_s, s2[L + amp] * sgn_s};
         F = rot_ipow(F, r.phase);
         const int flip = (r.neg && (amp & 1)) ^ (mp < 0 && r.odd);
         return flip ? C{-F.x, -F.y} : F;
@@ -482,7 +525,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
         const int nc = n < N ? n : N - 1;
-        const C Fa = coef(ra, nc), Fb = coef(rb, nc), c = cha[nc];
+        const C Fa = coef(ra, sr, nc), Fb = coef(rb, sr + 2 * L, nc), c = cha[nc];
         const C x = cmul(two ? cadd(Fa, Fb) : Fa, c);
         return n < N ? x : C{T(0), T(0)};
     };
@@ -492,22 +535,24 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
         if (t < N) buf[pad(t)] = cmul(y, c);
     };
     row_convolve<LOGM, T>(ft, buf, ft.h_ip, scr, ld, pre, st);
-    // columns mu and mu+1 of the rings G[b][t][.] (row length N, or L for HALF)
-    const int rl = HALF ? L : N;
+    // columns mu and mu+1 of the rings G[b][t][.] (ring_len: even, and mu
+    // starts at an even column, so a pair is one aligned 16-byte piece)
+    const int rl = ring_len(L, HALF);
     C *Ga = G + (size_t)b * L * rl + (HALF ? mua : mua + h);
     const T sa = ra.odd ? T(-0.5) : T(0.5);
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const C z = buf[pad(t)], zr = buf[pad(N - 1 - t)];
         C *g = Ga + (size_t)t * rl;
-        g[0] = C{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
-        if (two) g[1] = C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y};
+        const C ga{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
+        if (two) store_pair(g, ga, C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y});
+        else g[0] = ga;
     }
     });
 }
 
 // Inverse phi stage.  Row (b, t): f(theta_t, phi_p) = sum_mu g_mu(theta_t) e^{i mu phi_p}.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int rows,
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int rows, int rs,
                                                          const typename CT<T>::type *__restrict__ G,
                                                          typename CT<T>::type *__restrict__ map,
                                                          typename CT<T>::type *scr) {
@@ -517,7 +562,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int
     const int N = ft.N;
     for_items<split_rows<T, LOGM>()>(rows, [&](int item) {
     const size_t row = split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x;
-    const C *in = G + row * N;
+    const C *in = G + row * rs;
     C *out = map + row * N;
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
@@ -534,7 +579,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int
 
 // Forward phi stage.  Row (b, t): Q_mu(t) = N^-1 sum_p f(theta_t, phi_p) e^{-i mu phi_p}.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int rows,
+__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int rows, int rs,
                                                          const typename CT<T>::type *__restrict__ map,
                                                          typename CT<T>::type *__restrict__ Q,
                                                          typename CT<T>::type *scr) {
@@ -545,7 +590,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int
     for_items<split_rows<T, LOGM>()>(rows, [&](int item) {
     const size_t row = split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x;
     const C *in = map + row * N;
-    C *out = Q + row * N;
+    C *out = Q + row * rs;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
@@ -599,22 +644,34 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
     const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
     const int oddA = parity((long long)mua + s);
-    // columns mu and mu+1 of the rings Q[b][t][.] (row length rl), t < L
-    const int rl = HALF ? L : N;
+    // columns mu and mu+1 of the rings Q[b][t][.] (ring_len, even; mu at an
+    // even column), t < L
+    const int rl = ring_len(L, HALF);
     const C *Qa = Q + (size_t)b * L * rl + (HALF ? mua : mua + h);
     const C *Qb = two ? Qa + 1 : Qa;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
+    // the two columns staged in LDS, one aligned 16-byte piece per ring
+    // (each ring read once; the extension reads them back mirrored)
+    C *sa = buf, *sb = buf + L;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        C xa, xb;
+        if (two) load_pair(Qa + (size_t)t * rl, xa, xb);
+        else xa = xb = Qa[(size_t)t * rl];
+        sa[t] = xa;
+        sb[t] = xb;
+    }
+    __syncthreads();
     // extension of one row at n < N; the theta = pi sample (t = L-1) of an
     // odd row is left out
     auto ext = [&](const C *Qr, int odd, int n) -> C {
-        const C x = Qr[(size_t)(n < L ? n : 2 * L - 2 - n) * rl];
+        const C x = Qr[n < L ? n : 2 * L - 2 - n];
         if (odd && n == h) return C{T(0), T(0)};
         return (odd && n >= L) ? C{-x.x, -x.y} : x;
     };
     auto ld = [&](int n) -> C {
         const int nc = n < N ? n : N - 1;
-        const C xa = ext(Qa, oddA, nc), xb = ext(Qb, !oddA, nc), c = chb[nc];
+        const C xa = ext(sa, oddA, nc), xb = ext(sb, !oddA, nc), c = chb[nc];
         const C x = cmulc(two ? cadd(xa, xb) : xa, c);
         return n < N ? x : C{T(0), T(0)};
     };
@@ -673,7 +730,8 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft
     for_items<split_rows<T, LOGM>()>((rows + 1) / 2, [&](int item) {
     const size_t r0 = 2 * (split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x);
     const bool two = r0 + 1 < (size_t)rows;
-    const C *ina = G + r0 * L, *inb = two ? ina + L : ina;
+    const size_t rl = ring_len(L, true);
+    const C *ina = G + r0 * rl, *inb = two ? ina + rl : ina;
     T *outa = map + r0 * N, *outb = outa + N;
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
@@ -718,7 +776,8 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft
     const size_t r0 = 2 * (split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x);
     const bool two = r0 + 1 < (size_t)rows;
     const T *ina = map + r0 * N, *inb = two ? ina + N : ina;
-    C *outa = Q + r0 * L, *outb = outa + L;
+    const size_t rl = ring_len(L, true);
+    C *outa = Q + r0 * rl, *outb = outa + rl;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
     auto ld = [&](int n) -> C {
@@ -892,28 +951,30 @@ hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int co
 }
 
 template <typename T>
-hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, void *scr, hipStream_t st) {
+hipError_t launch_phi_inv(const FftTables<T> &ft, int B, int rs, const void *G, void *map, void *scr,
+                          hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_inv<T, LM>, lds);
         if (e != hipSuccess) return e;
         const int rows = ft.L * B;
-        hipLaunchKernelGGL((k_phi_inv<T, LM>), row_grid(ft, rows), dim3(row_threads(ft.M)), lds, st, ft, rows,
+        hipLaunchKernelGGL((k_phi_inv<T, LM>), row_grid(ft, rows), dim3(row_threads(ft.M)), lds, st, ft, rows, rs,
                            (const typename CT<T>::type *)G, (typename CT<T>::type *)map, (typename CT<T>::type *)scr);
         return hipGetLastError();
     });
 }
 
 template <typename T>
-hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, void *scr, hipStream_t st) {
+hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, int rs, const void *map, void *Q, void *scr,
+                          hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
         hipError_t e = set_lds(k_phi_fwd<T, LM>, lds);
         if (e != hipSuccess) return e;
         const int rows = ft.L * B;
-        hipLaunchKernelGGL((k_phi_fwd<T, LM>), row_grid(ft, rows), dim3(row_threads(ft.M)), lds, st, ft, rows,
+        hipLaunchKernelGGL((k_phi_fwd<T, LM>), row_grid(ft, rows), dim3(row_threads(ft.M)), lds, st, ft, rows, rs,
                            (const typename CT<T>::type *)map, (typename CT<T>::type *)Q, (typename CT<T>::type *)scr);
         return hipGetLastError();
     });
@@ -1034,8 +1095,10 @@ template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft) {
                                             void *, hipStream_t);                                        \
     template hipError_t launch_phi_inv_real<T>(const FftTables<T> &, int, const void *, T *, void *, hipStream_t); \
     template hipError_t launch_phi_fwd_real<T>(const FftTables<T> &, int, const T *, void *, void *, hipStream_t); \
-    template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, const void *, void *, void *, hipStream_t); \
-    template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, const void *, void *, void *, hipStream_t); \
+    template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, int, const void *, void *, void *,    \
+                                          hipStream_t);                                                  \
+    template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, int, const void *, void *, void *,    \
+                                          hipStream_t);                                                  \
     template hipError_t launch_theta_dft<T>(const FftTables<T> &, int, int, const void *, void *, hipStream_t); \
     template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, int, int, bool, const void *, T *, \
                                             void *, hipStream_t);                                        \

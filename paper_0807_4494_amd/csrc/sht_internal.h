@@ -59,6 +59,12 @@ template <typename T> struct FftTables {
                           //   allocated when M > 8192)
 };
 
+// Row length of the rings between the theta and phi stages: 2L complex
+// values per ring for complex maps (the N = 2L - 1 orders and one unused
+// slot, so that every ring starts 16-byte aligned and a pair of orders is one
+// aligned 16-byte piece), L + (L & 1) for real maps (orders m >= 0).
+__host__ __device__ constexpr int ring_len(int L, bool half) { return half ? L + (L & 1) : 2 * L; }
+
 // Rows whose M-point buffer exceeds the LDS (FP64 at M = 16384) run as two
 // halves with a global scratch slot of M complex values per workgroup; a
 // launch uses at most kSplitSlots workgroups.
@@ -151,10 +157,14 @@ template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft);
 template <typename T>
 hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const T *R, void *G,
                             void *scr, hipStream_t st);
+// rs: row stride of the rings G / Q (ring_len(L, false), or N for the
+// triangular forward's rows)
 template <typename T>
-hipError_t launch_phi_inv(const FftTables<T> &ft, int B, const void *G, void *map, void *scr, hipStream_t st);
+hipError_t launch_phi_inv(const FftTables<T> &ft, int B, int rs, const void *G, void *map, void *scr,
+                          hipStream_t st);
 template <typename T>
-hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, const void *map, void *Q, void *scr, hipStream_t st);
+hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, int rs, const void *map, void *Q, void *scr,
+                          hipStream_t st);
 template <typename T>
 hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const void *Q, T *X,
                             void *scr, hipStream_t st);
