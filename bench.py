@@ -4,11 +4,12 @@
 Workload (default): L = 1024, spins {0, +2, -2}, 16 maps per spin, complex
 Gaussian coefficients with C_l = 1/(l+1)^2 (sht_synth workload
 "L1024_s0pm2_b16").  One step = inverse then forward transform of every map of
-every spin (48 maps), inputs resident in HBM; one call per spin and direction
-(``--multi-spin``: the three spins through one ``sht_inverse_multi`` /
-``sht_forward_multi`` call per direction; the other pattern is timed too).  A
-"transform" is one map taken through inverse and forward, so value = 48 /
-step time.
+every spin (48 maps), inputs resident in HBM; the three spins through one
+``sht_inverse_multi`` / ``sht_forward_multi`` call per direction, in which
+spin -2 shares the contraction of spin +2 (one Wigner generation for both,
+Eq. (wignerd_sym6)) (``--per-spin``: one call per spin and direction; the
+other pattern is timed too).  A "transform" is one map taken through inverse
+and forward, so value = 48 / step time.
 
 Prints one JSON line (rank 0):
   metric, value (transforms/s), ms_per_step, dtype, config,
@@ -524,8 +525,8 @@ def main() -> int:
     ap.add_argument("--no-stability", action="store_true", help="skip the Section 4.2 stability leg")
     ap.add_argument("--tables", action="store_true",
                     help="also time the cached-table design (an L^3 table per spin, 4 GiB each in FP32 at L=1024)")
-    ap.add_argument("--multi-spin", action="store_true",
-                    help="one multi-spin call per direction (default: one call per spin and direction)")
+    ap.add_argument("--per-spin", action="store_true",
+                    help="one call per spin and direction (default: one multi-spin call per direction)")
     ap.add_argument("--no-compare-calls", action="store_true", help="skip timing the other call pattern")
     ap.add_argument("--no-large", action="store_true", help="skip the L=2048, 4-map configuration")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -550,7 +551,7 @@ def main() -> int:
     wl = {w.name: w for w in sht_synth.WORKLOADS}[args.workload]
     dev = torch.device("cuda", 0)
     prec = args.precision
-    multi = args.multi_spin
+    multi = not args.per_spin
     host_flm = {s: wl.flm(s) for s in wl.spins}
     flm = {s: torch.from_numpy(host_flm[s]).to(dev, sht.io_dtype(prec)) for s in wl.spins}
 

@@ -116,6 +116,18 @@ int sht_forward(int L, int spin, int batch, int sampling, int precision,
  * is that of sht_inverse / sht_forward at its spin; the O(L^3) contraction of
  * every segment runs in one launch (its column blocks carry their segment's
  * spin factors) and the phi stages in one launch over all maps.
+ *
+ * Spin pairs.  A segment of spin -s that directly follows one of spin s != 0
+ * (not itself so paired) shares that segment's contraction: at theta = pi/2,
+ * Delta^l_{m',s} = (-1)^{l+m'} Delta^l_{m',-s} (Eq. (wignerd_sym6)), so its
+ * columns join the column range of s, contracted with the factors of s, and
+ * the layout and theta stages apply the signs (-1)^l and (-1)^{m'}.  Each
+ * Wigner entry the contraction generates then serves both spins' maps (on
+ * the FP32 path in one 128-column tile: 16 maps of s and 16 of -s).  The
+ * paired maps agree with their own single-spin calls to rounding (the two
+ * spins' factor tables are tabulated separately); every other map's result
+ * is bitwise that of its single-spin call.  Order the segments
+ * {s, -s, ...} to get the sharing.
  *   nseg       1 <= nseg <= SHT_MULTI_SEG_MAX
  *   spins, batches  host arrays of nseg entries: |spins[k]| < L,
  *              batches[k] >= 1, sum of batches <= SHT_BATCH_MAX
@@ -273,16 +285,22 @@ int sht_graph_destroy(sht_graph graph);
 /*
  * Contraction tile shapes.  Each contraction workgroup takes 16, 32 or 64 of
  * the transform's columns (4 x batch for sht_inverse / sht_forward, 2 x batch
- * for the real-signal calls); more column blocks mean the Wigner products are
- * generated once per block, wider blocks waste matrix-core work on empty
- * columns.  By default a call takes the tile t that minimises
- * ceil(columns / t) * (t + 24) (the Wigner generation of a block costs about
- * as much as 24 columns): 16 up to 16 columns, 32 up to 32, 64 up to 64, and
- * 32 or 64 above.
+ * for the real-signal calls), or 128 on the FP32 path; more column blocks
+ * mean the Wigner products are generated once per block, wider blocks waste
+ * matrix-core work on empty columns (the 128-column tile only in 64-column
+ * halves: each half skips its work when it has no columns).  By default a
+ * call takes the tile t that minimises the sum over its column blocks of
+ * (the block's columns rounded up to t, or to 64 for t = 128) + 24 (the
+ * Wigner generation of a block costs about as much as 24 columns); several
+ * spins in one call sum over their column ranges, where a spin -s that
+ * follows s shares the range of s (sht_inverse_multi).  So 16 up to 16
+ * columns, 32 up to 32, 64 up to 64, and 128 for the FP32 ranges of 65 to
+ * 128 columns, e.g. 16 maps of s with 16 of -s.
  *
- * sht_tile_set pins the tile (16, 32 or 64; 0 restores the default) for
- * (current device, L, columns, precision).  SHT_ERR_INVALID_ARG for other
- * tiles, L outside 1..SHT_L_MAX or columns outside 1..4*SHT_BATCH_MAX.
+ * sht_tile_set pins the tile (16, 32 or 64, 128 for SHT_FP32; 0 restores the
+ * default) for (current device, L, columns, precision).  SHT_ERR_INVALID_ARG
+ * for other tiles, L outside 1..SHT_L_MAX or columns outside
+ * 1..4*SHT_BATCH_MAX.
  *
  * sht_tune is the autotuner: it times the contraction kernels of the inverse
  * and the forward of (L, spin, batch, precision) with each tile, using the

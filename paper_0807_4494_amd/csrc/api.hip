@@ -275,19 +275,42 @@ int check_buffers_real(bool inverse, int L, int batch, int precision, const void
 
 // One spin's maps within a call: `B` maps, stored after the maps of the
 // earlier segments; their contraction columns follow those segments' too.
+// flip: the segment follows one of the opposite spin and shares its
+// contraction factors, d^l_{m',s}(pi/2) = (-1)^{l+m'} d^l_{m',-s}(pi/2)
+// (Eq. (wignerd_sym6)); the layout and theta stages apply the signs.
 struct Seg {
     int spin, B;
     const SpinPlan *sp;
+    int flip;
 };
 constexpr int kMaxSegs = SHT_MULTI_SEG_MAX;
 
+// Marks each segment of spin -s that directly follows one of spin s != 0 to
+// share that segment's contraction (one column range, one Wigner
+// generation per column block for both).
+void pair_segments(int nseg, Seg *seg) {
+    for (int k = 0; k < nseg; ++k) seg[k].flip = 0;
+    for (int k = 0; k + 1 < nseg; ++k) {
+        if (seg[k].spin != 0 && !seg[k].flip && seg[k + 1].spin == -seg[k].spin) {
+            seg[k + 1].flip = 1;
+            ++k;
+        }
+    }
+}
+
 // The contraction in the path's own precision, or as BF16x3 on FP32 data,
-// over every segment's columns in one launch.
+// over every segment's columns in one launch (a flipped segment joins the
+// column range of the segment before it).
 template <typename T>
 hipError_t contract(int mode, bool bf16x3, int L, int nq, int nseg, const Seg *seg, const T *X, T *Y,
                     const DeviceState *ds, const RecTables &rec, hipStream_t st) {
     ContractSeg cs[kMaxSegs];
-    for (int k = 0; k < nseg; ++k) cs[k] = ContractSeg{nq * seg[k].B, seg[k].sp};
+    int n = 0;
+    for (int k = 0; k < nseg; ++k) {
+        if (seg[k].flip && n > 0) cs[n - 1].ncol += nq * seg[k].B;
+        else cs[n++] = ContractSeg{nq * seg[k].B, seg[k].sp};
+    }
+    nseg = n;
     if constexpr (sizeof(T) == 4) {
         if (bf16x3) return launch_contract_bf16x3(mode, L, nseg, cs, X, Y, ds->E, rec, st);
     }
@@ -316,7 +339,10 @@ int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
         const void *f = (const unsigned char *)flm + (size_t)off * L * L * cb;
         SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st,
-                       [&] { return launch_layout_in<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, real, f, P, st); }),
+                       [&] {
+                           return launch_layout_in<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, f, P,
+                                                      st);
+                       }),
                 "layout_in");
     }
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
@@ -328,7 +354,8 @@ int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
         void *g = (unsigned char *)P + (size_t)off * ring * cb;
         SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
                        [&] {
-                           return launch_theta_inv<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, real, R, g, scr, st);
+                           return launch_theta_inv<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, R, g,
+                                                      scr, st);
                        }),
                 "theta inverse");
     }
@@ -366,7 +393,8 @@ int run_forward(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
         const void *q = (const unsigned char *)Q + (size_t)off * ring * cb;
         SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
                        [&] {
-                           return launch_theta_fwd<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, real, q, X, scr, st);
+                           return launch_theta_fwd<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, q, X,
+                                                      scr, st);
                        }),
                 "theta forward");
     }
@@ -377,7 +405,10 @@ int run_forward(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
         void *f = (unsigned char *)flm + (size_t)off * L * L * cb;
         SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st,
-                       [&] { return launch_layout_out<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, real, R, f, st); }),
+                       [&] {
+                           return launch_layout_out<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, R, f,
+                                                       st);
+                       }),
                 "layout_out");
     }
     return SHT_OK;
@@ -408,8 +439,9 @@ int transform_segs(bool inverse, bool real, int L, int nseg, const int *spins, c
         SpinPlan *sp;
         rc = prepare(L, spins[k], st, &ds, &plan, &sp);
         if (rc != SHT_OK) return rc;
-        seg[k] = Seg{spins[k], batches[k], sp};
+        seg[k] = Seg{spins[k], batches[k], sp, 0};
     }
+    if (!real) pair_segments(nseg, seg);
     const bool bf = precision == SHT_BF16X3;
     if (precision == SHT_FP64) {
         return inverse ? run_inverse<double>(L, nseg, seg, false, real, plan->f64, plan->rec, ds, in, out,
@@ -491,7 +523,7 @@ int sht_inverse_noalloc(int L, int spin, int batch, int sampling, int precision,
     rc = find_plans(dev, L, spin, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    const Seg one{spin, batch, sp};
+    const Seg one{spin, batch, sp, 0};
     t_noalloc = true;
     rc = precision == SHT_FP64
              ? run_inverse<double>(L, 1, &one, false, false, plan->f64, plan->rec, ds, flm, map, ws, st)
@@ -663,7 +695,8 @@ int sht_error_metrics(int precision, size_t n, const void *ref, const void *val,
 int sht_tile_set(int L, int columns, int precision, int tile) {
     if (L < 1 || L > SHT_L_MAX || columns < 1 || columns > 4 * SHT_BATCH_MAX) return SHT_ERR_INVALID_ARG;
     if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_ERR_UNSUPPORTED;
-    if (tile != 0 && tile != 16 && tile != 32 && tile != 64) return SHT_ERR_INVALID_ARG;
+    const bool wide = tile == 128 && precision == SHT_FP32;  // the 128-column tile is FP32 only
+    if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && !wide) return SHT_ERR_INVALID_ARG;
     set_contract_tile(L, columns, contract_precision_class(precision == SHT_FP64, precision == SHT_BF16X3), tile);
     return SHT_OK;
 }
@@ -696,16 +729,17 @@ int sht_tune(int L, int spin, int batch, int precision, void *workspace, size_t 
         (void)hipEventDestroy(e0);
         return hip_fail(hipErrorOutOfMemory, "tune event");
     }
-    const int tiles[3] = {16, 32, 64};
+    const int tiles[4] = {16, 32, 64, 128};
+    const int ntiles = precision == SHT_FP32 ? 4 : 3;
     int best = 0;
     float best_ms = 0.0f;
     rc = SHT_OK;
-    for (int i = 0; i < 3 && rc == SHT_OK; ++i) {
+    for (int i = 0; i < ntiles && rc == SHT_OK; ++i) {
         set_contract_tile(L, C, pc, tiles[i]);
         float ms = 0.0f;
         for (int rep = 0; rep < 3 && rc == SHT_OK; ++rep) {  // rep 0 warms up
             hipError_t e = hipEventRecord(e0, st);
-            const Seg one{spin, batch, sp};
+            const Seg one{spin, batch, sp, 0};
             for (int mode = 0; mode < 2 && e == hipSuccess; ++mode) {
                 if (f64)
                     e = contract<double>(mode, false, L, 4, 1, &one, (const double *)w, (double *)(w + ra), ds,

@@ -98,17 +98,22 @@ __device__ inline void bf16_split(float v, unsigned short &hi, unsigned short &l
 
 constexpr int GM = 4;    // orders per workgroup
 constexpr int TK = 16;   // K slab
-constexpr int NT = 512;  // threads: 256 consumers + 256 producers
-constexpr int NC = 256;  // consumer threads
 
-// Precision policies.  A workgroup is 8 waves: waves 0-3 consume (MFMA),
-// waves 4-7 produce (FP64 Wigner chains).  TJ output indices j per
-// workgroup, WJ per consumer wave; GM orders m; TK rows of K per slab.
-enum { kP64 = 0, kP32 = 1, kPBF = 2 };
+// Precision policies.  The first NCONS threads of a workgroup consume (MFMA),
+// the NPROD after them produce (FP64 Wigner chains).  TJ output
+// indices j per workgroup, WJ per consumer wave; GM orders m; TK rows of K per
+// slab.  kP32W is the FP32 tile of 128 columns: two consumer waves per SIMD,
+// each with the j block and accumulators of a 64-column tile, over one
+// column half, beside one producer wave, so each Wigner entry generated
+// serves 128 columns for the producer time a 64-column tile spends.
+enum { kP64 = 0, kP32 = 1, kPBF = 2, kP32W = 3 };
 template <int P> struct Prec;
-template <> struct Prec<kP64> { using T = double; static constexpr int TJ = 64, WJ = 16; };
-template <> struct Prec<kP32> { using T = float; static constexpr int TJ = 128, WJ = 32; };
-template <> struct Prec<kPBF> { using T = float; static constexpr int TJ = 128, WJ = 32; };
+template <> struct Prec<kP64> { using T = double; static constexpr int TJ = 64, WJ = 16, NCONS = 256, NPROD = 256; };
+template <> struct Prec<kP32> { using T = float; static constexpr int TJ = 128, WJ = 32, NCONS = 256, NPROD = 256; };
+template <> struct Prec<kPBF> { using T = float; static constexpr int TJ = 128, WJ = 32, NCONS = 256, NPROD = 256; };
+template <> struct Prec<kP32W> { using T = float; static constexpr int TJ = 128, WJ = 32, NCONS = 512, NPROD = 256; };
+template <int P> constexpr int kThreads = Prec<P>::NCONS + Prec<P>::NPROD;
+template <int P> constexpr bool kIsF32 = P == kP32 || P == kP32W;
 
 // LDS slabs.  FP32 / FP64: M slab [k][j] with rows padded by 16 so the four K
 // rows an MFMA fragment spans hit disjoint banks; X slab [c][k] with rows of
@@ -119,14 +124,19 @@ template <> struct Prec<kPBF> { using T = float; static constexpr int TJ = 128, 
 // lane's four k are one aligned 8-byte read), each as hi and lo planes.
 // KP (FP32 forward): M stored [k/2][j][k%2] for K-paired fragments (see the
 // consumers).
+// kP32W: X rows of TK unpadded, filled by LDS-direct loads (each lane's 16
+// bytes land at the next 16-byte slot), with slot q of row c holding k quad
+// q ^ ((c >> 2) & 3): the 16 columns of a fragment read then spread over 64
+// banks.
+template <int P> constexpr int kXRow = P == kP32W ? TK : (kIsF32<P> ? TK + 4 : TK + 1);
 template <int P, int CTILE, bool KP = false> struct Slabs {
     using T = typename Prec<P>::T;
-    static constexpr int XROW = P == kP32 ? TK + 4 : TK + 1;
+    static constexpr int XROW = kXRow<P>;
     T M[2][GM][TK][Prec<P>::TJ + 16];
     alignas(16) T X[2][GM][CTILE][XROW];
 };
-template <int CTILE> struct Slabs<kP32, CTILE, true> {
-    static constexpr int TJ = Prec<kP32>::TJ, XROW = TK + 4;
+template <int P, int CTILE> struct Slabs<P, CTILE, true> {
+    static constexpr int TJ = Prec<P>::TJ, XROW = kXRow<P>;
     alignas(16) float M[2][GM][TK / 2][TJ + 16][2];
     alignas(16) float X[2][GM][CTILE][XROW];
 };
@@ -164,20 +174,25 @@ template <typename T> struct Args {
 // of running the Wigner chains (the measured comparison of a precomputed-Delta
 // design with on-the-fly generation).
 template <int P, int MODE, int CTILE, bool TAB>
-__global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
+__global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>::T> a) {
     using T = typename Prec<P>::T;
     constexpr bool BF = P == kPBF;
     constexpr int TJ = Prec<P>::TJ, WJ = Prec<P>::WJ;
-    constexpr int NPJ = NC / TJ;    // producer threads sharing one j
+    constexpr int NC = Prec<P>::NCONS;        // consumer threads
+    constexpr int NPJ = Prec<P>::NPROD / TJ;  // producer threads sharing one j
     constexpr int NCH = GM / NPJ;   // main chains per producer thread
-    constexpr int NCI = CTILE / 16, NJI = WJ / 16;
+    constexpr int NJW = TJ / WJ;    // consumer waves across the j tile
+    constexpr int CW = CTILE * NJW * 64 / NC;  // columns per consumer wave
+    constexpr int NCI = CW / 16, NJI = WJ / 16;
     constexpr int XPT = GM * CTILE * TK / NC;  // X slab elements per consumer thread
+    static_assert(NCH * NPJ == GM && CW * (NC / 64 / NJW) == CTILE, "tile shape");
     static_assert(XPT % 4 == 0, "X slab quadruples");
     using acc_t = typename Mfma<T>::acc;
 
     // FP32 forward: K-paired MFMA fragments (measured faster there; the
     // inverse keeps the plain layout, where pairing measured slower)
-    constexpr bool KP = P == kP32 && MODE == kForward;
+    constexpr bool KP = kIsF32<P> && MODE == kForward;
+    constexpr bool DX = P == kP32W;  // X slab by LDS-direct loads, swizzled rows
     __shared__ Slabs<P, CTILE, KP> sm;
     __shared__ double fam[2][GM][TK], fbm[2][GM][TK];
 
@@ -324,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         // emissions meet zero rows of X.  (The spin factor is held in the
         // output precision: it multiplies a value rounded to T on emission
         // anyway.)
-        constexpr int PD = TK / 2;
+        constexpr int PD = P == kP32W ? TK / 4 : TK / 2;  // fewer in flight where 3 waves share a SIMD
         const unsigned jo = (unsigned)(jvalid ? j : 0);
         double2 tj[PD];
         T wj[PD];
@@ -407,6 +422,11 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         auto steps = [&](int chunk, int buf, auto inj_tag, auto es_tag) {
             constexpr bool INJ = decltype(inj_tag)::value, ES1 = decltype(es_tag)::value;
             const int kbase = kbase_of(chunk);
+            // the step kk at which chain g reaches its edge (compared with the
+            // unrolled kk, so no per-step constants are kept in registers)
+            int edge[NCH];
+#pragma unroll
+            for (int g = 0; g < NCH; ++g) edge[g] = MODE == kInverse ? l0[g] - 1 - kbase : l0[g] + 1 - kbase;
             if (MODE == kInverse) {
                 // order-side factors of step kk are read from LDS during step
                 // kk-1; a scheduling barrier closes every step, so the reads
@@ -419,8 +439,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                     fb[g] = fbm[buf][sub * NCH + g][0];
                 }
 #pragma unroll
-                for (int kk = 0; kk < TK; ++kk) {
-                    const int l = kbase + kk;
+                for (int kk = 0; kk < TK; ++kk) {  // degree l = kbase + kk
                     const double2 t = tj[kk % PD];
                     const T W = wj[kk % PD];
                     double am[NCH], bm[NCH];
@@ -441,7 +460,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
                         double dn = -(t.x * am[g] * ch[g].d + t.y * bm[g] * ch[g].dp);
-                        if constexpr (INJ) dn += (l + 1 == l0[g]) ? sv[g] : 0.0;
+                        if constexpr (INJ) dn += (kk == edge[g]) ? sv[g] : 0.0;
                         ch[g].dp = ch[g].d;
                         ch[g].d = dn;
                     }
@@ -449,8 +468,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
                 }
             } else {
 #pragma unroll
-                for (int kk = TK - 1; kk >= 0; --kk) {
-                    const int k = kbase + kk;  // m'
+                for (int kk = TK - 1; kk >= 0; --kk) {  // m' = kbase + kk
                     const double2 t = tj[kk % PD];
                     const T W = wj[kk % PD];
                     load_next(tj[kk % PD], wj[kk % PD]);
@@ -461,7 +479,7 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
                         double dn = (twom[g] * ch[g].d - gprev * ch[g].dp) * t.x;
-                        if constexpr (INJ) dn += (k - 1 == l0[g]) ? sv[g] : 0.0;
+                        if constexpr (INJ) dn += (kk == edge[g]) ? sv[g] : 0.0;
                         ch[g].dp = ch[g].d;
                         ch[g].d = dn;
                     }
@@ -516,111 +534,8 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
     }
 
     // ================= consumers: MFMA =================
-    // X slab: element i of this thread is (g, c, kk); 32-bit offsets from the
-    // group's panel base, fixed for the whole K loop.  FP32 / BF16x3: element
-    // 4 q + r is k = 4 kq + r of the q-th (g, c, kq) quadruple, so a thread's
-    // four consecutive elements are four consecutive k of one row (one
-    // 16-byte load when the rows are 16-byte aligned)
-    constexpr bool V4 = P != kP64;
-    constexpr int XROW = Slabs<P, CTILE, KP>::XROW;
-    int xoff[XPT], xsl[XPT], xkk[XPT], xg[XPT];
-    bool xok[XPT];
-#pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-        int g, c, kk;
-        if constexpr (V4) {
-            const int e4 = tid + (i / 4) * NC;  // over [GM][CTILE][TK / 4]
-            g = e4 / (CTILE * TK / 4);
-            const int rem = e4 % (CTILE * TK / 4);
-            c = rem / (TK / 4);
-            kk = 4 * (rem % (TK / 4)) + i % 4;
-        } else {
-            const int e = tid + i * NC;  // over [GM][CTILE][TK]
-            g = e / (CTILE * TK);
-            const int rem = e % (CTILE * TK);
-            c = rem / TK;
-            kk = rem % TK;
-        }
-        xg[i] = g;
-        xkk[i] = kk;
-        xok[i] = (m0 + g) < L && (c0 + c) < cend;
-        xoff[i] = (g * Cn + c0 + c) * L + kk;
-        xsl[i] = (g * CTILE + c) * XROW + kk;
-    }
-    const T *xbase = a.X + (size_t)m0 * Cn * L;
-    bool xall = true;
-#pragma unroll
-    for (int i = 0; i < XPT; ++i) xall = xall && xok[i];
-    xall = __all(xall);  // every (order, column) of the tile exists
-    // the group's panel rows as a buffer resource (used only when xall: then
-    // the GM rows of Cn x L entries all exist)
-    const __amdgpu_buffer_rsrc_t xrsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)xbase, (short)0, xall ? GM * Cn * L * (int)sizeof(T) : 0, kBufWord3);
-    unsigned xvo[P != kP64 ? XPT : 1];
-    if constexpr (P != kP64) {
-#pragma unroll
-        for (int i = 0; i < XPT; ++i) xvo[i] = (unsigned)xoff[i] * (unsigned)sizeof(T);
-    }
-    T xr[XPT];
-    auto load_x = [&](int chunk) {
-        const int kbase = kbase_of(chunk);
-        // whole slab inside the panel rows that exist (inverse: l >= m for
-        // every order of the group): plain loads from a uniform base
-        // (FP64 tiles keep the masked loads: their accumulators leave no
-        // room for the buffer offsets)
-        const bool full = P != kP64 && xall && kbase >= 0 && kbase + TK <= L && (MODE != kInverse || kbase >= m0 + GM - 1);
-        if (full) {
-            // buffer loads: the tile's panel as a resource, the lane offset
-            // (fixed for the whole K loop) and the slab offset (uniform) both
-            // added by the memory unit
-            const unsigned so = (unsigned)kbase * (unsigned)sizeof(T);
-            if constexpr (P != kP64) {
-                if ((L & 3) == 0) {
-                    // rows and slab start 16-byte aligned (kbase is a multiple of TK)
-#pragma unroll
-                    for (int i = 0; i < XPT; i += 4) {
-                        const float4 v = buffer_load_f4(xrsrc, xvo[i], so);
-                        xr[i] = v.x;
-                        xr[i + 1] = v.y;
-                        xr[i + 2] = v.z;
-                        xr[i + 3] = v.w;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < XPT; ++i) xr[i] = buffer_load<T>(xrsrc, xvo[i], so);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < XPT; ++i) {
-                const int k = kbase + xkk[i];
-                bool ok = xok[i] && k >= 0 && k < L;
-                if (MODE == kInverse) ok = ok && k >= m0 + xg[i];
-                xr[i] = ok ? xbase[xoff[i] + kbase] : T(0);
-            }
-        }
-    };
-    auto store_x = [&](int buf) {
-        if constexpr (BF) {
-            unsigned short *xh = &sm.Xh[buf][0][0][0], *xl = &sm.Xl[buf][0][0][0];
-#pragma unroll
-            for (int i = 0; i < XPT; ++i) {
-                unsigned short hi, lo;
-                bf16_split(xr[i], hi, lo);
-                xh[xsl[i]] = hi;
-                xl[xsl[i]] = lo;
-            }
-        } else if constexpr (P == kP32) {
-            float *xt = &sm.X[buf][0][0][0];
-#pragma unroll
-            for (int i = 0; i < XPT; i += 4) *(float4 *)&xt[xsl[i]] = make_float4(xr[i], xr[i + 1], xr[i + 2], xr[i + 3]);
-        } else {
-            T *xt = &sm.X[buf][0][0][0];
-#pragma unroll
-            for (int i = 0; i < XPT; ++i) xt[xsl[i]] = xr[i];
-        }
-    };
-
+    // this wave's j block and column range within the tile
+    const int jw = wave % NJW, cwo = (wave / NJW) * CW;
     acc_t acc[GM][NCI][NJI];
 #pragma unroll
     for (int g = 0; g < GM; ++g)
@@ -631,13 +546,13 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
 
     auto mfma_slab = [&](int chunk, int buf) {
         const int kbase = kbase_of(chunk);
-        const int wj0 = j0 + wave * WJ;  // first j of this consumer wave
-        bool active;
+        const int wj0 = j0 + jw * WJ;  // first j of this consumer wave
+        bool active = c0 + cwo < cend;  // some column of this wave exists
         if (MODE == kInverse) {
             const int start = m0 > wj0 ? m0 : wj0;
-            active = kbase + TK - 1 >= start && wj0 < L;
+            active = active && kbase + TK - 1 >= start && wj0 < L;
         } else {
-            active = kbase <= wj0 + WJ - 1 && wj0 < L;
+            active = active && kbase <= wj0 + WJ - 1 && wj0 < L;
         }
         if (!active) return;
         if constexpr (BF) {
@@ -648,13 +563,13 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             auto ldfrag = [&](int g, int slot) {
 #pragma unroll
                 for (int ci = 0; ci < NCI; ++ci) {
-                    const int c = ci * 16 + (lane & 15);
+                    const int c = cwo + ci * 16 + (lane & 15);
                     ah[slot][ci] = *(const s16x4 *)&sm.Xh[buf][g][c][4 * kg];
                     al[slot][ci] = *(const s16x4 *)&sm.Xl[buf][g][c][4 * kg];
                 }
 #pragma unroll
                 for (int ji = 0; ji < NJI; ++ji) {
-                    const int jj = wave * WJ + ji * 16 + (lane & 15);
+                    const int jj = jw * WJ + ji * 16 + (lane & 15);
                     bh[slot][ji] = *(const s16x4 *)&sm.Mh[buf][g][kg][jj][0];
                     bl[slot][ji] = *(const s16x4 *)&sm.Ml[buf][g][kg][jj][0];
                 }
@@ -683,13 +598,21 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             typedef float f32x2 __attribute__((ext_vector_type(2)));
             constexpr int NPG = GM * 2;
             f32x2 av[2][NCI], bv[2][NJI];
-            const float *xl = &sm.X[buf][0][lane & 15][2 * (lane >> 4)];
-            const float *ml = &sm.M[buf][0][lane >> 4][wave * WJ + (lane & 15)][0];
+            // this lane's X base for pair group h (k = 8h + 2 (lane >> 4) + e);
+            // in the swizzled rows its quad 2h + (lane >> 5) sits at slot
+            // (2h + (lane >> 5)) ^ ((lane >> 2) & 3)
+            const float *xlh[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = DX ? (2 * h + (lane >> 5)) ^ ((lane >> 2) & 3) : 2 * h + (lane >> 5);
+                xlh[h] = &sm.X[buf][0][cwo + (lane & 15)][4 * q + 2 * ((lane >> 4) & 1)];
+            }
+            const float *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)][0];
             constexpr int XR = Slabs<P, CTILE, KP>::XROW, MR = (TJ + 16) * 2;
             auto ldfrag = [&](int idx, int slot) {
                 const int g = idx / 2, h = idx % 2;
 #pragma unroll
-                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = *(const f32x2 *)&xl[(g * CTILE + ci * 16) * XR + 8 * h];
+                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = *(const f32x2 *)&xlh[h][(g * CTILE + ci * 16) * XR];
 #pragma unroll
                 for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = *(const f32x2 *)&ml[(g * (TK / 2) + 4 * h) * MR + ji * 32];
             };
@@ -713,13 +636,20 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             T av[2][NCI], bv[2][NJI];
             // this lane's fragment bases in the slab; every fragment is a
             // constant offset from them
-            const T *xl = &sm.X[buf][0][lane & 15][lane >> 4];
-            const T *ml = &sm.M[buf][0][lane >> 4][wave * WJ + (lane & 15)];
+            // this lane's X base for k quad ks (swizzled rows: slot
+            // ks ^ ((lane >> 2) & 3))
+            const T *xlk[NKS];
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                const int q = DX ? ks ^ ((lane >> 2) & 3) : ks;
+                xlk[ks] = &sm.X[buf][0][cwo + (lane & 15)][4 * q + (lane >> 4)];
+            }
+            const T *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)];
             constexpr int XR = Slabs<P, CTILE, KP>::XROW, MR = TJ + 16;
             auto ldfrag = [&](int idx, int slot) {
                 const int g = idx / NKS, ks = idx % NKS;
 #pragma unroll
-                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = xl[(g * CTILE + ci * 16) * XR + ks * 4];
+                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = xlk[ks][(g * CTILE + ci * 16) * XR];
 #pragma unroll
                 for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = ml[(g * TK + ks * 4) * MR + ji * 16];
             };
@@ -737,16 +667,202 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
         }
     };
 
-    __syncthreads();
-    load_x(0);
-    store_x(0);
-    __syncthreads();
-    for (int chunk = 1; chunk <= nchunks; ++chunk) {
-        const int cur = chunk & 1, prev = cur ^ 1;
-        if (chunk < nchunks) load_x(chunk);
-        mfma_slab(chunk - 1, prev);
-        if (chunk < nchunks) store_x(cur);
+    if constexpr (DX) {
+        // X slab by LDS-direct loads: instruction i of consumer wave w moves
+        // the 64 16-byte slots s = (NSL w + i) 64 + lane of the slab
+        // [g][c][TK] (4 slots a row), i.e. rows (g_i, cb_i + lane / 4) with
+        // cb_i a multiple of 16; slot q' of row c holds the k quad
+        // q' ^ ((c >> 2) & 3) = q' ^ ((lane >> 4) & 3).  A lane's global
+        // offset is then one per-lane part, fixed for the whole K loop, plus
+        // a uniform part per instruction and the uniform slab offset.
+        constexpr int NSL = GM * CTILE * TK / 4 / NC;  // slots per consumer thread
+        static_assert(NSL * NC * 4 == GM * CTILE * TK && TK == 16 && CTILE % 16 == 0, "slot map");
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        const int lrow = lane >> 2, lq = (lane & 3) ^ ((lane >> 4) & 3);
+        const unsigned vlane = (unsigned)((lrow * L + 4 * lq) * (int)sizeof(T));
+        auto slot_g = [&](int i) { return (wv * NSL + i) * 64 / (CTILE * 4); };
+        auto slot_cb = [&](int i) { return ((wv * NSL + i) * 16) % CTILE; };
+        bool rok = true;
+#pragma unroll
+        for (int i = 0; i < NSL; ++i) rok = rok && (m0 + slot_g(i)) < L && (c0 + slot_cb(i) + lrow) < cend;
+        const T *xbase = a.X + (size_t)m0 * Cn * L;
+        // every row this wave moves exists, and the rows are 16-byte aligned
+        const bool wall = __all(rok) && (L & 3) == 0;
+        const __amdgpu_buffer_rsrc_t xrsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)xbase, (short)0, wall ? GM * Cn * L * (int)sizeof(T) : 0, kBufWord3);
+        auto full_slab = [&](int chunk) {
+            const int kbase = kbase_of(chunk);
+            return wall && kbase >= 0 && kbase + TK <= L && (MODE != kInverse || kbase >= m0 + GM - 1);
+        };
+        // whole slab inside rows that exist: straight into LDS
+        auto load_direct = [&](int chunk, int buf) {
+            const unsigned so = (unsigned)kbase_of(chunk) * (unsigned)sizeof(T);
+#pragma unroll
+            for (int i = 0; i < NSL; ++i) {
+                T *dst = &sm.X[buf][0][0][0] + (wv * NSL + i) * 64 * 4;
+                const unsigned si = (unsigned)((slot_g(i) * Cn + c0 + slot_cb(i)) * L * (int)sizeof(T)) + so;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(xrsrc, (__attribute__((address_space(3))) void *)dst, 16,
+                                                         vlane, si, 0, 0);
+            }
+        };
+        // otherwise element by element with the bounds of the panel rows
+        // (inverse: l >= m), through registers
+        auto load_masked = [&](int chunk, int buf) {
+            const int kbase = kbase_of(chunk);
+#pragma unroll
+            for (int i = 0; i < NSL; ++i) {
+                const int sl = (wv * NSL + i) * 64 + lane;
+                const int g = slot_g(i), c = slot_cb(i) + lrow;
+                const bool row = (m0 + g) < L && (c0 + c) < cend;
+                const T *src = xbase + (size_t)(g * Cn + c0 + c) * L;
+                T v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = kbase + 4 * lq + e;
+                    const bool ok = row && k >= 0 && k < L && (MODE != kInverse || k >= m0 + g);
+                    v[e] = ok ? src[k] : T(0);
+                }
+                *(float4 *)(&sm.X[buf][0][0][0] + sl * 4) = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        };
+        // the direct loads must have landed before the barrier publishes them
+        auto wait_direct = [&]() { __builtin_amdgcn_s_waitcnt(0x0F70); };  // vmcnt(0)
+
         __syncthreads();
+        if (full_slab(0)) {
+            load_direct(0, 0);
+            wait_direct();
+        } else {
+            load_masked(0, 0);
+        }
+        __syncthreads();
+        for (int chunk = 1; chunk <= nchunks; ++chunk) {
+            const int cur = chunk & 1, prev = cur ^ 1;
+            const bool more = chunk < nchunks, direct = more && full_slab(chunk);
+            if (direct) load_direct(chunk, cur);
+            mfma_slab(chunk - 1, prev);
+            if (more && !direct) load_masked(chunk, cur);
+            if (direct) wait_direct();
+            __syncthreads();
+        }
+    } else {
+        // X slab: element i of this thread is (g, c, kk); 32-bit offsets from the
+        // group's panel base, fixed for the whole K loop.  FP32 / BF16x3: element
+        // 4 q + r is k = 4 kq + r of the q-th (g, c, kq) quadruple, so a thread's
+        // four consecutive elements are four consecutive k of one row (one
+        // 16-byte load when the rows are 16-byte aligned)
+        constexpr bool V4 = P != kP64;
+        constexpr int XROW = Slabs<P, CTILE, KP>::XROW;
+        int xoff[XPT], xsl[XPT], xkk[XPT], xg[XPT];
+        bool xok[XPT];
+    #pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            int g, c, kk;
+            if constexpr (V4) {
+                const int e4 = tid + (i / 4) * NC;  // over [GM][CTILE][TK / 4]
+                g = e4 / (CTILE * TK / 4);
+                const int rem = e4 % (CTILE * TK / 4);
+                c = rem / (TK / 4);
+                kk = 4 * (rem % (TK / 4)) + i % 4;
+            } else {
+                const int e = tid + i * NC;  // over [GM][CTILE][TK]
+                g = e / (CTILE * TK);
+                const int rem = e % (CTILE * TK);
+                c = rem / TK;
+                kk = rem % TK;
+            }
+            xg[i] = g;
+            xkk[i] = kk;
+            xok[i] = (m0 + g) < L && (c0 + c) < cend;
+            xoff[i] = (g * Cn + c0 + c) * L + kk;
+            xsl[i] = (g * CTILE + c) * XROW + kk;
+        }
+        const T *xbase = a.X + (size_t)m0 * Cn * L;
+        bool xall = true;
+    #pragma unroll
+        for (int i = 0; i < XPT; ++i) xall = xall && xok[i];
+        xall = __all(xall);  // every (order, column) of the tile exists
+        // the group's panel rows as a buffer resource (used only when xall: then
+        // the GM rows of Cn x L entries all exist)
+        const __amdgpu_buffer_rsrc_t xrsrc =
+            __builtin_amdgcn_make_buffer_rsrc((void *)xbase, (short)0, xall ? GM * Cn * L * (int)sizeof(T) : 0, kBufWord3);
+        unsigned xvo[P != kP64 ? XPT : 1];
+        if constexpr (P != kP64) {
+    #pragma unroll
+            for (int i = 0; i < XPT; ++i) xvo[i] = (unsigned)xoff[i] * (unsigned)sizeof(T);
+        }
+        T xr[XPT];
+        auto load_x = [&](int chunk) {
+            const int kbase = kbase_of(chunk);
+            // whole slab inside the panel rows that exist (inverse: l >= m for
+            // every order of the group): plain loads from a uniform base
+            // (FP64 tiles keep the masked loads: their accumulators leave no
+            // room for the buffer offsets)
+            const bool full = P != kP64 && xall && kbase >= 0 && kbase + TK <= L && (MODE != kInverse || kbase >= m0 + GM - 1);
+            if (full) {
+                // buffer loads: the tile's panel as a resource, the lane offset
+                // (fixed for the whole K loop) and the slab offset (uniform) both
+                // added by the memory unit
+                const unsigned so = (unsigned)kbase * (unsigned)sizeof(T);
+                if constexpr (P != kP64) {
+                    if ((L & 3) == 0) {
+                        // rows and slab start 16-byte aligned (kbase is a multiple of TK)
+    #pragma unroll
+                        for (int i = 0; i < XPT; i += 4) {
+                            const float4 v = buffer_load_f4(xrsrc, xvo[i], so);
+                            xr[i] = v.x;
+                            xr[i + 1] = v.y;
+                            xr[i + 2] = v.z;
+                            xr[i + 3] = v.w;
+                        }
+                    } else {
+    #pragma unroll
+                        for (int i = 0; i < XPT; ++i) xr[i] = buffer_load<T>(xrsrc, xvo[i], so);
+                    }
+                }
+            } else {
+    #pragma unroll
+                for (int i = 0; i < XPT; ++i) {
+                    const int k = kbase + xkk[i];
+                    bool ok = xok[i] && k >= 0 && k < L;
+                    if (MODE == kInverse) ok = ok && k >= m0 + xg[i];
+                    xr[i] = ok ? xbase[xoff[i] + kbase] : T(0);
+                }
+            }
+        };
+        auto store_x = [&](int buf) {
+            if constexpr (BF) {
+                unsigned short *xh = &sm.Xh[buf][0][0][0], *xl = &sm.Xl[buf][0][0][0];
+    #pragma unroll
+                for (int i = 0; i < XPT; ++i) {
+                    unsigned short hi, lo;
+                    bf16_split(xr[i], hi, lo);
+                    xh[xsl[i]] = hi;
+                    xl[xsl[i]] = lo;
+                }
+            } else if constexpr (kIsF32<P>) {
+                float *xt = &sm.X[buf][0][0][0];
+    #pragma unroll
+                for (int i = 0; i < XPT; i += 4) *(float4 *)&xt[xsl[i]] = make_float4(xr[i], xr[i + 1], xr[i + 2], xr[i + 3]);
+            } else {
+                T *xt = &sm.X[buf][0][0][0];
+    #pragma unroll
+                for (int i = 0; i < XPT; ++i) xt[xsl[i]] = xr[i];
+            }
+        };
+
+        __syncthreads();
+        load_x(0);
+        store_x(0);
+        __syncthreads();
+        for (int chunk = 1; chunk <= nchunks; ++chunk) {
+            const int cur = chunk & 1, prev = cur ^ 1;
+            if (chunk < nchunks) load_x(chunk);
+            mfma_slab(chunk - 1, prev);
+            if (chunk < nchunks) store_x(cur);
+            __syncthreads();
+        }
+
     }
 
     // ---- write out[c][j] ----
@@ -761,8 +877,8 @@ __global__ __launch_bounds__(NT) void k_contract(Args<typename Prec<P>::T> a) {
             for (int ji = 0; ji < NJI; ++ji)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int c = c0 + ci * 16 + Mfma<T>::row(lane, r);
-                    const int jj = j0 + wave * WJ + ji * 16 + (lane & 15);
+                    const int c = c0 + cwo + ci * 16 + Mfma<T>::row(lane, r);
+                    const int jj = j0 + jw * WJ + ji * 16 + (lane & 15);
                     if (c < cend && jj < L) yrow[c * L + jj] = acc[g][ci][ji][r];
                 }
     }
@@ -772,8 +888,8 @@ template <int P, int MODE, int CTILE>
 hipError_t launch_one(Args<typename Prec<P>::T> a, int nsched, bool tab, hipStream_t st) {
     if (nsched == 0 || a.ncb == 0) return hipSuccess;
     const dim3 grid(nsched, a.ncb);
-    if (tab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true>), grid, dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false>), grid, dim3(NT), 0, st, a);
+    if (tab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true>), grid, dim3(kThreads<P>), 0, st, a);
+    else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false>), grid, dim3(kThreads<P>), 0, st, a);
     return hipGetLastError();
 }
 
@@ -819,9 +935,11 @@ __global__ void k_mtable(int L, EdgeTable E, const double *ri, const double2 *fa
 
 // Column tile of the contraction for (device, L, columns, precision): the
 // choice recorded by set_contract_tile (pinned, or picked by the timing
-// autotuner), else the tile t in {16, 32, 64} that minimises
-// ceil(C / t) (t + 24): every column block pays its columns on the matrix
-// cores plus the Wigner generation, which costs about as much as 24 columns.
+// autotuner), else the tile t in {16, 32, 64} (FP32 also 128) that minimises
+// the sum over column blocks of (its columns rounded up to t, or to 64 in the
+// 128-column tile, whose consumer waves each take 64 columns and skip
+// theirs when absent) + 24: every block pays its columns on the matrix cores
+// plus the Wigner generation, which costs about as much as 24 columns.
 std::mutex g_tile_mu;
 std::map<std::tuple<int, int, int, int>, int> g_tiles;
 
@@ -839,9 +957,15 @@ int contract_tile(int L, int nseg, const ContractSeg *seg, int P) {
     }
     int best = 16;
     long best_cost = -1;
-    for (int t = 16; t <= 64; t *= 2) {
+    const int tmax = P == kP32 ? 128 : 64;
+    for (int t = 16; t <= tmax; t *= 2) {
+        const int gran = t > 64 ? 64 : t;
         long cost = 0;
-        for (int k = 0; k < nseg; ++k) cost += (long)((seg[k].ncol + t - 1) / t) * (t + 24);
+        for (int k = 0; k < nseg; ++k)
+            for (int c = 0; c < seg[k].ncol; c += t) {
+                const int n = seg[k].ncol - c < t ? seg[k].ncol - c : t;
+                cost += (n + gran - 1) / gran * gran + 24;
+            }
         if (best_cost < 0 || cost < best_cost) {
             best = t;
             best_cost = cost;
@@ -851,8 +975,8 @@ int contract_tile(int L, int nseg, const ContractSeg *seg, int P) {
 }
 
 template <int P>
-hipError_t launch_prec(int mode, int L, int nseg, const ContractSeg *seg, const typename Prec<P>::T *X,
-                       typename Prec<P>::T *Y, const EdgeTable &E, const RecTables &rt, hipStream_t st) {
+hipError_t launch_tiled(int mode, int L, int nseg, const ContractSeg *seg, int ct, const typename Prec<P>::T *X,
+                        typename Prec<P>::T *Y, const EdgeTable &E, const RecTables &rt, hipStream_t st) {
     using T = typename Prec<P>::T;
     Args<T> a;
     a.L = L;
@@ -868,7 +992,6 @@ hipError_t launch_prec(int mode, int L, int nseg, const ContractSeg *seg, const 
     const int cls = Prec<P>::TJ == 64 ? 0 : 1;
     a.sched = rt.sched[mode][cls];
     const int ns = rt.nsched[mode][cls];
-    const int ct = contract_tile(L, nseg, seg, P);
     // column blocks, spin by spin; table mode only when every spin has its table
     bool tab = true;
     int nb = 0, c = 0;
@@ -895,13 +1018,29 @@ hipError_t launch_prec(int mode, int L, int nseg, const ContractSeg *seg, const 
         c += seg[k].ncol;
     }
     a.ncb = nb;
-    if (ct == 16)
-        return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, tab, st)
-                                : launch_one<P, kForward, 16>(a, ns, tab, st);
-    if (ct == 32)
-        return mode == kInverse ? launch_one<P, kInverse, 32>(a, ns, tab, st)
-                                : launch_one<P, kForward, 32>(a, ns, tab, st);
-    return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, tab, st) : launch_one<P, kForward, 64>(a, ns, tab, st);
+    if constexpr (P == kP32W) {
+        return mode == kInverse ? launch_one<P, kInverse, 128>(a, ns, tab, st)
+                                : launch_one<P, kForward, 128>(a, ns, tab, st);
+    } else {
+        if (ct == 16)
+            return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, tab, st)
+                                    : launch_one<P, kForward, 16>(a, ns, tab, st);
+        if (ct == 32)
+            return mode == kInverse ? launch_one<P, kInverse, 32>(a, ns, tab, st)
+                                    : launch_one<P, kForward, 32>(a, ns, tab, st);
+        return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, tab, st)
+                                : launch_one<P, kForward, 64>(a, ns, tab, st);
+    }
+}
+
+template <int P>
+hipError_t launch_prec(int mode, int L, int nseg, const ContractSeg *seg, const typename Prec<P>::T *X,
+                       typename Prec<P>::T *Y, const EdgeTable &E, const RecTables &rt, hipStream_t st) {
+    const int ct = contract_tile(L, nseg, seg, P);
+    if constexpr (P == kP32) {
+        if (ct == 128) return launch_tiled<kP32W>(mode, L, nseg, seg, ct, X, Y, E, rt, st);
+    }
+    return launch_tiled<P>(mode, L, nseg, seg, ct, X, Y, E, rt, st);
 }
 
 }  // namespace

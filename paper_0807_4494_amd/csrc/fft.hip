@@ -477,7 +477,7 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N)
 // (2i, 2i+1), rings of L orders.
 template <typename T, int LOGM, bool HALF>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B, int Cn, int coff,
-                                                           const T *__restrict__ R,
+                                                           int flip, const T *__restrict__ R,
                                                            typename CT<T>::type *__restrict__ G,
                                                            typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
@@ -519,8 +519,9 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
         const int mp = n - h, amp = mp < 0 ? -mp : mp;
         C F{s2[amp] * sgn_s, s2[L + amp] * sgn_s};
         F = rot_ipow(F, r.phase);
-        const int flip = (r.neg && (amp & 1)) ^ (mp < 0 && r.odd);
-        return flip ? C{-F.x, -F.y} : F;
+        // (-1)^{m'} for mu < 0 and for factors of spin -s; sigma for m' < 0
+        const int neg = ((r.neg ^ flip) && (amp & 1)) ^ (mp < 0 && r.odd);
+        return neg ? C{-F.x, -F.y} : F;
     };
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
@@ -632,7 +633,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int
 // (2i, 2i+1), 2-column panels.
 template <typename T, int LOGM, bool HALF>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B, int Cn, int coff,
-                                                           const typename CT<T>::type *__restrict__ Q,
+                                                           int flip, const typename CT<T>::type *__restrict__ Q,
                                                            T *__restrict__ X, typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -704,7 +705,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
             const T w = (k == 0 ? T(0.5) : T(1)) * twopi;
             C x{(yp.x + sg * ym.x) * w, (yp.y + sg * ym.y) * w};
             if (k == h) x = cadd(x, top);
-            const T sgn = (neg && (k & 1)) ? T(-1) : T(1);
+            const T sgn = ((neg ^ flip) && (k & 1)) ? T(-1) : T(1);
             Xre[k] = x.x * sgn;
             Xim[k] = x.y * sgn;
         }
@@ -929,8 +930,8 @@ template <typename F> hipError_t with_logm(int logM, F f) {
 }
 
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const T *R, void *G,
-                            void *scr, hipStream_t st) {
+hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half, const T *R,
+                            void *G, void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
@@ -939,12 +940,12 @@ hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int co
             hipError_t e = set_lds(k_theta_inv<T, LM, true>, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL((k_theta_inv<T, LM, true>), row_grid(ft, (ft.L + 1) / 2 * B), dim3(row_threads(ft.M)),
-                               lds, st, ft, s, B, Cn, coff, R, g, w);
+                               lds, st, ft, s, B, Cn, coff, flip, R, g, w);
         } else {
             hipError_t e = set_lds(k_theta_inv<T, LM, false>, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL((k_theta_inv<T, LM, false>), row_grid(ft, ft.L * B), dim3(row_threads(ft.M)), lds, st,
-                               ft, s, B, Cn, coff, R, g, w);
+                               ft, s, B, Cn, coff, flip, R, g, w);
         }
         return hipGetLastError();
     });
@@ -981,8 +982,8 @@ hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, int rs, const void *map
 }
 
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const void *Q, T *X,
-                            void *scr, hipStream_t st) {
+hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half,
+                            const void *Q, T *X, void *scr, hipStream_t st) {
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
@@ -992,12 +993,12 @@ hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int co
             hipError_t e = set_lds(k_theta_fwd<T, LM, true>, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL((k_theta_fwd<T, LM, true>), row_grid(ft, (ft.L + 1) / 2 * B), dim3(row_threads(ft.M)),
-                               lds, st, ft, s, B, Cn, coff, q, X, w);
+                               lds, st, ft, s, B, Cn, coff, flip, q, X, w);
         } else {
             hipError_t e = set_lds(k_theta_fwd<T, LM, false>, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL((k_theta_fwd<T, LM, false>), row_grid(ft, ft.L * B), dim3(row_threads(ft.M)), lds, st,
-                               ft, s, B, Cn, coff, q, X, w);
+                               ft, s, B, Cn, coff, flip, q, X, w);
         }
         return hipGetLastError();
     });
@@ -1091,8 +1092,8 @@ template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft) {
 }
 
 #define SHT_INST(T)                                                                                      \
-    template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, int, int, bool, const T *, void *, \
-                                            void *, hipStream_t);                                        \
+    template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, int, int, int, bool, const T *,  \
+                                            void *, void *, hipStream_t);                                \
     template hipError_t launch_phi_inv_real<T>(const FftTables<T> &, int, const void *, T *, void *, hipStream_t); \
     template hipError_t launch_phi_fwd_real<T>(const FftTables<T> &, int, const T *, void *, void *, hipStream_t); \
     template hipError_t launch_phi_inv<T>(const FftTables<T> &, int, int, const void *, void *, void *,    \
@@ -1100,8 +1101,8 @@ template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft) {
     template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, int, const void *, void *, void *,    \
                                           hipStream_t);                                                  \
     template hipError_t launch_theta_dft<T>(const FftTables<T> &, int, int, const void *, void *, hipStream_t); \
-    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, int, int, bool, const void *, T *, \
-                                            void *, hipStream_t);                                        \
+    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, int, int, int, bool, const void *, \
+                                            T *, void *, hipStream_t);                                   \
     template size_t split_scratch_bytes<T>(const FftTables<T> &);                                        \
     template hipError_t launch_transpose<T>(int, int, int, const void *, void *, hipStream_t);                \
     template hipError_t launch_fft_inplace<T>(const FftTables<T> &, typename CT<T>::type *, int, double, \

@@ -13,6 +13,10 @@
 // coefficient rows (contiguous in m) and the panels (contiguous in l) are
 // both accessed with unit stride.
 //
+// flip: the launch's maps (spin s) are contracted with the factors of spin
+// -s, d^l_{m',s}(pi/2) = (-1)^{l+m'} d^l_{m',-s}(pi/2) (Eq. (wignerd_sym6)):
+// their panels carry one more (-1)^l here, the theta stages the (-1)^{m'}.
+//
 // HALF (real spin-0 signals, f_{l,-m} = (-1)^m conj(f_lm), Section 3.3):
 // only q = 0, 1 are kept (c = q*B + b, 2B columns); the output side writes
 // the negative orders from the symmetry.
@@ -25,7 +29,7 @@ namespace {
 constexpr int TL = 32;  // tile edge
 
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, int coff,
+__global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, int coff, int flip,
                                                   const typename CT<T>::type *__restrict__ flm, T *__restrict__ P) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][l_local][m_local]
@@ -41,11 +45,12 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, 
         if (l < L && m <= l && l >= as) {
             const size_t base = (size_t)l * l + l;
             const C p = fb[base + m];
-            v0 = p.x;
-            v1 = p.y;
+            const T sl = (flip && (l & 1)) ? T(-1) : T(1);
+            v0 = p.x * sl;
+            v1 = p.y * sl;
             if (!HALF && m > 0) {
                 const C q = fb[base - m];
-                const T sg = (l & 1) ? T(-1) : T(1);
+                const T sg = ((l & 1) && !flip) ? T(-1) : T(1);
                 v2 = q.x * sg;
                 v3 = q.y * sg;
             }
@@ -70,8 +75,8 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, 
 //   f_{l, m}  = (-1)^s i^{m+s}              (R0 + i R1)
 //   f_{l,-m}  = (-1)^s i^{s-m} (-1)^l       (R2 + i R3)      (m > 0)
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, int Cn, int coff, const T *__restrict__ R,
-                                                   typename CT<T>::type *__restrict__ flm) {
+__global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, int Cn, int coff, int flip,
+                                                   const T *__restrict__ R, typename CT<T>::type *__restrict__ flm) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][m_local][l_local]
     const int l0 = blockIdx.x * TL, m0 = blockIdx.y * TL, b = blockIdx.z;
@@ -96,7 +101,8 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, int Cn,
         const int l = l0 + li, m = m0 + tx;
         if (l >= L || m > l) continue;
         const size_t base = (size_t)l * l + l;
-        C p{tile[0][tx][li] * sgn_s, tile[1][tx][li] * sgn_s};
+        const T sf = (flip && (l & 1)) ? -sgn_s : sgn_s;
+        C p{tile[0][tx][li] * sf, tile[1][tx][li] * sf};
         // multiply by i^{m+s}
         switch ((m + s) & 3) {
             case 0: break;
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, int Cn,
             // f_{l,-m} = (-1)^m conj(f_lm)
             fb[base - m] = (m & 1) ? C{-p.x, p.y} : C{p.x, -p.y};
         } else if (m > 0) {
-            const T sl = (l & 1) ? -sgn_s : sgn_s;
+            const T sl = ((l & 1) && !flip) ? -sgn_s : sgn_s;
             C q{tile[2][tx][li] * sl, tile[3][tx][li] * sl};
             switch ((s - m) & 3) {
                 case 0: break;
@@ -161,28 +167,29 @@ template hipError_t launch_spin_pair<double>(int, int, int, const void *, void *
 template hipError_t launch_spin_pair<float>(int, int, int, const void *, void *, hipStream_t);
 
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, bool half, const void *flm, T *P,
+hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, int flip, bool half, const void *flm, T *P,
                             hipStream_t st) {
     dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
     const typename CT<T>::type *f = (const typename CT<T>::type *)flm;
-    if (half) hipLaunchKernelGGL((k_layout_in<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, f, P);
-    else hipLaunchKernelGGL((k_layout_in<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, f, P);
+    if (half) hipLaunchKernelGGL((k_layout_in<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, f, P);
+    else hipLaunchKernelGGL((k_layout_in<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, f, P);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, bool half, const T *R, void *flm,
+hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, int flip, bool half, const T *R, void *flm,
                              hipStream_t st) {
     dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
     typename CT<T>::type *f = (typename CT<T>::type *)flm;
-    if (half) hipLaunchKernelGGL((k_layout_out<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, R, f);
-    else hipLaunchKernelGGL((k_layout_out<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, R, f);
+    if (half) hipLaunchKernelGGL((k_layout_out<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, R, f);
+    else hipLaunchKernelGGL((k_layout_out<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, R, f);
     return hipGetLastError();
 }
 
-template hipError_t launch_layout_in<double>(int, int, int, int, int, bool, const void *, double *, hipStream_t);
-template hipError_t launch_layout_in<float>(int, int, int, int, int, bool, const void *, float *, hipStream_t);
-template hipError_t launch_layout_out<double>(int, int, int, int, int, bool, const double *, void *, hipStream_t);
-template hipError_t launch_layout_out<float>(int, int, int, int, int, bool, const float *, void *, hipStream_t);
+template hipError_t launch_layout_in<double>(int, int, int, int, int, int, bool, const void *, double *, hipStream_t);
+template hipError_t launch_layout_in<float>(int, int, int, int, int, int, bool, const void *, float *, hipStream_t);
+template hipError_t launch_layout_out<double>(int, int, int, int, int, int, bool, const double *, void *,
+                                              hipStream_t);
+template hipError_t launch_layout_out<float>(int, int, int, int, int, int, bool, const float *, void *, hipStream_t);
 
 }  // namespace sht

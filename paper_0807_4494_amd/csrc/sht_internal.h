@@ -136,13 +136,15 @@ hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
 // layout.hip.  The panels have Cn columns per order; the B maps of one
-// launch (one spin) own columns coff + q*B + b.
+// launch (one spin) own columns coff + q*B + b.  flip: those maps are
+// contracted with the factors of spin -s (the layout stages then apply
+// (-1)^l, the theta stages (-1)^{m'}; Eq. (wignerd_sym6)).
 // half: real spin-0 signals, orders m >= 0 only (2 columns per map)
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, bool half, const void *flm, T *P,
+hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, int flip, bool half, const void *flm, T *P,
                             hipStream_t st);
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, bool half, const T *R, void *flm,
+hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, int flip, bool half, const T *R, void *flm,
                              hipStream_t st);
 
 // {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m}) for spin pairs f_{-s} = conj(f_s)
@@ -155,8 +157,8 @@ template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft);
 // The theta stages of B maps of one spin whose contraction columns are
 // coff + q*B + b of Cn; G / Q point at the first of those maps' rings.
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const T *R, void *G,
-                            void *scr, hipStream_t st);
+hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half, const T *R,
+                            void *G, void *scr, hipStream_t st);
 // rs: row stride of the rings G / Q (ring_len(L, false), or N for the
 // triangular forward's rows)
 template <typename T>
@@ -166,8 +168,8 @@ template <typename T>
 hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, int rs, const void *map, void *Q, void *scr,
                           hipStream_t st);
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, bool half, const void *Q, T *X,
-                            void *scr, hipStream_t st);
+hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half,
+                            const void *Q, T *X, void *scr, hipStream_t st);
 // real maps (spin 0): phi synthesis from orders m >= 0, phi analysis keeping m >= 0
 template <typename T>
 hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, void *scr, hipStream_t st);

@@ -69,6 +69,20 @@ class Group:
         return (self.L, tuple(self.segments))
 
 
+def pair_order(spins: List[int]) -> List[int]:
+    """Spins in order of first appearance, except that -s is moved right
+    after s (s != 0): the library then runs the two segments as one
+    contraction, with one Wigner generation for both (Eq. (wignerd_sym6))."""
+    out: List[int] = []
+    for s in spins:
+        if s in out:
+            continue
+        out.append(s)
+        if s != 0 and -s in spins:
+            out.append(-s)
+    return out
+
+
 class Scheduler:
     """FIFO admission with same-L grouping under a memory budget.
 
@@ -131,6 +145,7 @@ class Scheduler:
         for req in members:
             self.waiting.remove(req)
         self.used += need
+        spins = pair_order(spins)
         ordered = [r for s in spins for r in members if r.spin == s]
         segments = [(s, sum(r.batch for r in members if r.spin == s)) for s in spins]
         return Group(head.L, ordered, segments, batch, need)

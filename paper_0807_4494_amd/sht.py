@@ -302,8 +302,9 @@ def plan_tables(L: int, spin: int = 0, precision="fp32", enable: bool = True, de
 
 
 def tile_set(L: int, columns: int, precision="fp32", tile: int = 0) -> None:
-    """Pin the contraction's column tile (16, 32, 64; 0 = default) for
-    (L, columns = 4 x batch, precision) on the current device."""
+    """Pin the contraction's column tile (16, 32, 64, and 128 for fp32;
+    0 = default) for (L, columns = 4 x batch, precision) on the current
+    device."""
     N.check(N.load().sht_tile_set(L, columns, _prec(precision), tile), "sht_tile_set")
 
 

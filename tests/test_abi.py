@@ -119,6 +119,10 @@ def test_tile_and_tune_argument_checks_run_before_any_hip_call():
     assert lib.sht_tile_set(64, 4 * 64 + 1, 1, 32) == N.SHT_ERR_INVALID_ARG
     assert lib.sht_tile_set(64, 8, 7, 32) == N.SHT_ERR_UNSUPPORTED
     assert lib.sht_tile_set(64, 8, 1, 48) == N.SHT_ERR_INVALID_ARG
+    # the 128-column tile exists for FP32 only
+    assert lib.sht_tile_set(64, 8, N.SHT_FP64, 128) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_tile_set(64, 8, N.SHT_BF16X3, 128) == N.SHT_ERR_INVALID_ARG
+    assert lib.sht_tile_set(64, 8, N.SHT_FP32, 256) == N.SHT_ERR_INVALID_ARG
     fake = ctypes.c_void_p(1 << 20)
     assert lib.sht_tune(0, 0, 1, 1, fake, 1 << 40, None, None) == N.SHT_ERR_INVALID_ARG
     assert lib.sht_tune(64, 0, 1, 1, None, 1 << 40, None, None) == N.SHT_ERR_INVALID_ARG

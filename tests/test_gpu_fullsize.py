@@ -108,6 +108,38 @@ def test_round_trip_full_size(name, prec):
         assert err <= TOL[prec], (name, s, prec, err)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_paired_spins_in_one_call_full_size(prec):
+    """The benchmark's spins 0, 2, -2 (16 maps each, L = 1024) in one
+    multi-spin call, where -2 shares the contraction of 2 (FP32: one
+    128-column tile over the pair): sampled outputs against the stored oracle
+    values, as for the per-spin calls above."""
+    name = "L1024_s0pm2_b16"
+    sht, dev = _sht(), _dev()
+    wl, g = _workload(name), _golden(name)
+    L, B, spins = wl.L, wl.batch, list(wl.spins)
+    assert spins == [0, 2, -2]
+    print(f"[paired full size] {name} {prec}", flush=True)
+    flm = torch.cat([torch.from_numpy(wl.flm(s)) for s in spins]).to(dev, sht.io_dtype(prec))
+    fmap = sht.inverse_multi(flm, L, spins, [B] * 3, prec)
+    t = torch.from_numpy(g["pix_t"]).to(dev)
+    p = torch.from_numpy(g["pix_p"]).to(dev)
+    for k, s in enumerate(spins):
+        for i, b in enumerate(g["members"]):
+            got = fmap[k * B + int(b)][t, p].cpu().numpy().astype(np.complex128)
+            err = _rel(g[f"inv_s{s}"][i], got)
+            assert err <= TOL[prec], (s, int(b), prec, "inverse", err)
+    del fmap
+    maps = torch.from_numpy(_random_maps(name)).to(dev, sht.io_dtype(prec))
+    back = sht.forward_multi(torch.cat([maps] * 3), L, spins, [B] * 3, prec)
+    idx = torch.from_numpy(g["fwd_index"]).to(dev)
+    for k, s in enumerate(spins):
+        for i, b in enumerate(g["members"]):
+            got = back[k * B + int(b)][idx].cpu().numpy().astype(np.complex128)
+            err = _rel(g[f"fwd_s{s}"][i], got)
+            assert err <= TOL[prec], (s, int(b), prec, "forward", err)
+
+
 # ---- the largest band-limit the library accepts (SHT_L_MAX = 4096) ----
 # FFT rows of M = 16384 points: in LDS for FP32, as two M/2-point halves with
 # global scratch for FP64 (their buffer exceeds a CU's LDS).  The oracle takes

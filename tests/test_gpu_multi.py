@@ -1,7 +1,14 @@
 """Several spins at one band-limit in one call (sht_inverse_multi /
 sht_forward_multi): each map's result equals the single-spin call at its
-spin (bitwise: every output column is accumulated in the same order whatever
-its column block) and the oracle's transform within the precision's bar."""
+spin and the oracle's transform within the precision's bar.
+
+Bitwise, except for a segment of spin -s that directly follows one of spin
+s != 0: it shares that segment's contraction factors through
+d^l_{m',s}(pi/2) = (-1)^{l+m'} d^l_{m',-s}(pi/2) (Eq. (wignerd_sym6)), whose
+two sides the plan tabulates separately, so it agrees with its own
+single-spin call to rounding (relative l2 at most 1e-13 in FP64, 1e-6 in
+FP32).  Every other column is accumulated in the same order whatever its
+column block or tile."""
 
 import numpy as np
 import pytest
@@ -14,6 +21,7 @@ import sht_synth
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 2e-5}
+ROUNDING = {"fp64": 1e-13, "fp32": 1e-6, "bf16x3": 1e-6}
 
 
 def _sht():
@@ -28,7 +36,30 @@ SEGMENTS = [
     (33, [0, 1, -1, 2, -2, 3, -3, 4], [1, 1, 2, 1, 1, 1, 1, 1]),   # the most segments, tiny batches
     (128, [2, -2], [16, 16]),                                        # two full 64-column blocks
     (200, [-1], [5]),                                                 # one segment = the plain call
+    # a pair of 72 columns (FP32: the 128-column tile; L odd, element-wise X loads)
+    (257, [2, -2], [9, 9]),
+    # L % 4 == 0: the 128-column tile's LDS-direct X loads; unpaired spin 0 after the pair
+    (260, [-3, 3, 0], [12, 5, 4]),
 ]
+
+
+def _flipped(spins):
+    """Segments that share the previous segment's contraction (spin -s right
+    after a spin s != 0 that is not itself flipped)."""
+    out = [False] * len(spins)
+    k = 0
+    while k + 1 < len(spins):
+        if spins[k] != 0 and spins[k + 1] == -spins[k]:
+            out[k + 1] = True
+            k += 2
+        else:
+            k += 1
+    return out
+
+
+def _rel(a, b):
+    return float(torch.linalg.vector_norm((a - b).to(torch.complex128)) /
+                 torch.linalg.vector_norm(b.to(torch.complex128)))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
@@ -45,13 +76,17 @@ def test_multi_spin_call_equals_single_spin_calls(L, spins, batches, prec):
     back = sht.forward_multi(maps, L, spins, batches, prec)
     torch.cuda.synchronize()
     off = 0
-    for s, n in zip(spins, batches):
+    for s, n, flip in zip(spins, batches, _flipped(spins)):
         sl = slice(off, off + n)
         m1 = sht.inverse(x[sl], L, s, prec)
         f1 = sht.forward(maps[sl], L, s, prec)
         torch.cuda.synchronize()
-        assert torch.equal(maps[sl], m1), (s, "inverse")
-        assert torch.equal(back[sl], f1), (s, "forward")
+        if flip:
+            assert _rel(maps[sl], m1) <= ROUNDING[prec], (s, "inverse", _rel(maps[sl], m1))
+            assert _rel(back[sl], f1) <= ROUNDING[prec], (s, "forward", _rel(back[sl], f1))
+        else:
+            assert torch.equal(maps[sl], m1), (s, "inverse")
+            assert torch.equal(back[sl], f1), (s, "forward")
         ref = oracle.inverse_batch(flm[sl], L, s)
         assert oracle.rel_l2(ref, maps[sl].cpu().numpy()) < TOL[prec]
         assert oracle.rel_l2(flm[sl], back[sl].cpu().numpy()) < TOL[prec]

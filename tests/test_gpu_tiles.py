@@ -13,6 +13,8 @@ import sht_synth
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 5e-5}
+# the 128-column tile is FP32 only
+TILES = {"fp64": (16, 32, 64), "fp32": (16, 32, 64, 128), "bf16x3": (16, 32, 64)}
 
 
 def _sht():
@@ -25,7 +27,9 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("L,s,B", [(48, 0, 2), (64, 1, 6), (100, -2, 7), (70, 2, 17)])
+# L % 4 == 0 takes the 128-column tile's LDS-direct X loads, other L its
+# element-wise loads; 4 B = 68 and 132 columns fill both halves of a block
+@pytest.mark.parametrize("L,s,B", [(48, 0, 2), (64, 1, 6), (100, -2, 7), (70, 2, 17), (132, 3, 33)])
 def test_every_tile_gives_the_transform(L, s, B, prec):
     sht = _sht()
     print(f"[tiles] L={L} s={s} B={B} {prec}", flush=True)
@@ -35,7 +39,7 @@ def test_every_tile_gives_the_transform(L, s, B, prec):
     x = torch.from_numpy(flm).to(dev, sht.io_dtype(prec))
     outs = []
     try:
-        for tile in (16, 32, 64):
+        for tile in TILES[prec]:
             sht.tile_set(L, 4 * B, prec, tile)
             m = sht.inverse(x, L, s, prec)
             f = sht.forward(torch.from_numpy(ref).to(dev, sht.io_dtype(prec)), L, s, prec)
@@ -59,7 +63,7 @@ def test_real_path_tiles(prec):
     ref = oracle.forward_batch(raw.astype(np.complex128), L, 0)
     got = []
     try:
-        for tile in (16, 32, 64):
+        for tile in TILES[prec]:
             sht.tile_set(L, 2 * B, prec, tile)
             g = sht.forward_real(torch.from_numpy(raw).to(dev, sht.real_dtype(prec)), L, prec)
             torch.cuda.synchronize()
@@ -77,7 +81,7 @@ def test_autotuner_pick_keeps_the_results(prec, L, s, B):
     try:
         tile = sht.tune(L, s, B, prec)
         print(f"[tune] L={L} s={s} B={B} {prec}: tile {tile}", flush=True)
-        assert tile in (16, 32, 64)
+        assert tile in TILES[prec]
         flm = np.stack([sht_synth.gaussian_flm(L, s, 8700 + b) for b in range(B)])
         ref = oracle.inverse_batch(flm, L, s)
         m = sht.inverse(torch.from_numpy(flm).to(dev, sht.io_dtype(prec)), L, s, prec)

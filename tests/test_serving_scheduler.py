@@ -4,7 +4,8 @@ import dataclasses
 
 import pytest
 
-from paper_0807_4494_amd.serving import BATCH_MAX, SEG_MAX, Scheduler, Server, footprint_bytes, percentile
+from paper_0807_4494_amd.serving import (BATCH_MAX, SEG_MAX, Scheduler, Server, footprint_bytes, pair_order,
+                                         percentile)
 
 
 @dataclasses.dataclass
@@ -107,6 +108,19 @@ def test_groups_same_L_across_spins_in_segments():
     assert g.spin is None
     g2 = s.next_group()
     assert [r.rid for r in g2.requests] == [1] and g2.spin == 0
+
+
+def test_opposite_spins_are_adjacent_segments():
+    # -s right after s, so that the library shares one contraction between them
+    assert pair_order([1, 2, 0, -1, -2, 3]) == [1, -1, 2, -2, 0, 3]
+    assert pair_order([0, -2, 1, 2]) == [0, -2, 2, 1]
+    assert pair_order([0]) == [0]
+    s = Scheduler(1 << 40, ws)
+    for r in [Req(0, 64, 1, 2), Req(1, 64, 2, 1), Req(2, 64, -1, 3), Req(3, 64, 1, 1)]:
+        s.arrive(r)
+    g = s.next_group()
+    assert g.segments == [(1, 3), (-1, 3), (2, 1)]
+    assert [r.rid for r in g.requests] == [0, 3, 2, 1]
 
 
 def test_group_respects_segment_limit():
