@@ -58,10 +58,14 @@ SPECTRA = {"flat": "C_l = 1", "inv_lp1_sq": "C_l = 1/(l+1)^2", "inv_l_lp1": "C_l
 
 def contraction_flops(L: int, s: int, B: int) -> float:
     """Algorithmic flops of one contraction launch (one direction, B maps):
-    4 sum_{l=|s|}^{L-1} (2l+1)(l+1) per map -- real multiply-adds x 2 over the
-    non-zero triangle m' <= l, |m| <= l, m' >= 0 folded (the Delta product is
-    shared by the Re/Im columns and by +-m)."""
+    4 sum_{l=|s|}^{L-1} (2l+1) n_l per map -- real multiply-adds x 2 over the
+    non-zero terms, m' <= l, |m| <= l, m' >= 0 folded (the Delta product is
+    shared by the Re/Im columns and by +-m), with n_l = l + 1 orders m' per
+    degree, or floor(l/2) + 1 for spin 0, where Delta^l_{m',0}(pi/2) vanishes
+    for odd l + m' (the parity kernel skips those terms)."""
     a = abs(s)
+    if s == 0:
+        return 4.0 * B * sum((2 * l + 1) * (l // 2 + 1) for l in range(L))
     return 4.0 * B * sum((2 * l + 1) * (l + 1) for l in range(a, L))
 
 

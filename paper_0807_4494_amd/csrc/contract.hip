@@ -173,7 +173,7 @@ template <typename T> struct Args {
 // TAB: the producers copy the slab of M from the plan's cached table instead
 // of running the Wigner chains (the measured comparison of a precomputed-Delta
 // design with on-the-fly generation).
-template <int P, int MODE, int CTILE, bool TAB>
+template <int P, int MODE, int CTILE, bool TAB, bool PAR>
 __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>::T> a) {
     using T = typename Prec<P>::T;
     constexpr bool BF = P == kPBF;
@@ -205,6 +205,24 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
     const int m0 = mg * GM, j0 = jt * TJ, c0 = a.c0[cb], cend = a.cend[cb], asg = a.asg[cb];
     const T *wtab = a.wtab[cb], *mtab = a.mtab[cb];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // PAR: the parity kernel, launched on spin-0 blocks of FP32 data only.
+    // Delta^l_{m',0}(pi/2) = 0 for odd l + m' (K index and j of opposite
+    // parity).  The tile places its even j in the first TJ / 2 positions and
+    // its odd j after them (pj), so the j of a consumer wave share one parity;
+    // the K slabs of complete 16-blocks arrive with even K in positions 0-7
+    // and odd K in 8-15 (par16_pos; the producers emit in the same order), and
+    // the consumers skip the products of the other parity.  BF16x3 (one MFMA
+    // spans the slab's 16 K) keeps the K order of the FP32 panels but skips
+    // nothing.  FP64 data keeps the natural order, and the 128-column tile
+    // takes no spin-0 blocks.
+    static_assert(!PAR || P == kP32 || P == kPBF, "parity kernels");
+    constexpr bool par = PAR, pj = PAR && P == kP32;
+    // j of tile position p, and (producers, which keep consecutive j for
+    // contiguous table loads) the position of j0 + jl
+    auto jpos = [&](int p) { return pj ? 2 * (p % (TJ / 2)) + p / (TJ / 2) : p; };
+    auto jcol = [&](int jl) { return pj ? (jl & 1) * (TJ / 2) + (jl >> 1) : jl; };
+    // slab in parity blocks: a spin-0 block's slab inside [0, L)
+    auto pk_of = [&](int kbase) { return par && kbase + TK <= L; };
     const bool producer = tid >= NC;
 
     if (MODE == kForward) {
@@ -233,7 +251,7 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
         // ================= producers, table mode: copy M slabs =================
         const int ptid = tid - NC;
         const int jl = ptid % TJ, sub = ptid / TJ;
-        const int j = j0 + jl;
+        const int j = j0 + jl, jc = jcol(jl);
         T vc[NCH][TK], vn[NCH][TK];
         auto load_slab = [&](int chunk, T (&dst)[NCH][TK]) {
             const int kbase = kbase_of(chunk);
@@ -254,19 +272,24 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
             if constexpr (BF) {
                 unsigned short hi, lo;
                 bf16_split(v, hi, lo);
-                sm.Mh[buf][gi][kk >> 2][jl][kk & 3] = hi;
-                sm.Ml[buf][gi][kk >> 2][jl][kk & 3] = lo;
+                sm.Mh[buf][gi][kk >> 2][jc][kk & 3] = hi;
+                sm.Ml[buf][gi][kk >> 2][jc][kk & 3] = lo;
             } else if constexpr (KP) {
-                sm.M[buf][gi][kk >> 1][jl][kk & 1] = v;
+                sm.M[buf][gi][kk >> 1][jc][kk & 1] = v;
             } else {
-                sm.M[buf][gi][kk][jl] = v;
+                sm.M[buf][gi][kk][jc] = v;
             }
         };
-        auto store_slab = [&](int buf) {
+        auto store_slab = [&](int chunk, int buf) {
+            auto store = [&](auto pk_tag) {
+                constexpr bool PK = decltype(pk_tag)::value;
 #pragma unroll
-            for (int g = 0; g < NCH; ++g)
+                for (int g = 0; g < NCH; ++g)
 #pragma unroll
-                for (int kk = 0; kk < TK; ++kk) emit_t(buf, sub * NCH + g, kk, vc[g][kk]);
+                    for (int kk = 0; kk < TK; ++kk) emit_t(buf, sub * NCH + g, PK ? par16_pos(kk, TK) : kk, vc[g][kk]);
+            };
+            if (pk_of(kbase_of(chunk))) store(std::true_type{});
+            else store(std::false_type{});
         };
         auto advance = [&]() {
 #pragma unroll
@@ -278,13 +301,13 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
         load_slab(0, vc);
         __syncthreads();
         load_slab(1, vn);
-        store_slab(0);
+        store_slab(0, 0);
         __syncthreads();
         for (int chunk = 1; chunk <= nchunks; ++chunk) {
             if (chunk < nchunks) {
                 advance();
                 load_slab(chunk + 1, vn);
-                store_slab(chunk & 1);
+                store_slab(chunk, chunk & 1);
             }
             __syncthreads();
         }
@@ -298,7 +321,7 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
         const int ptid = tid - NC;
         // sub (the order rows of this thread) is uniform across a wave
         const int jl = ptid % TJ, sub = __builtin_amdgcn_readfirstlane(ptid / TJ);
-        const int j = j0 + jl;
+        const int j = j0 + jl, jc = jcol(jl);
         const bool jvalid = j < L;
         Chain ch[NCH];
         int l0[NCH];
@@ -382,28 +405,32 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
                 fbm[buf][fgi][fkk] = fnext.y;
             }
         };
-        // one entry of M, rounded to the MFMA precision, into LDS
-        // KP: the two entries of a K pair are written together as one 8-byte
-        // store when the second of them (in processing order, m' descending)
-        // is emitted; the first waits in `held`
-        T held[NCH];
-        auto emit = [&](int buf, int g, int kk, double dv, T W) {
+        // one entry of M, rounded to the MFMA precision, into LDS at slab
+        // position pos (the step kk, or par16_pos(kk) in parity blocks).
+        // KP: the two entries of a position pair are written together as one
+        // 8-byte store when the one in the even position is emitted (in
+        // processing order, m' descending, it comes last: one step after its
+        // partner, or two in parity blocks); the first waits in `held`, slot
+        // (pos >> 3) & 1 (a pair of odd steps and one of even steps may wait
+        // at once in parity blocks)
+        T held[NCH][2];
+        auto emit = [&](int buf, int g, int pos, double dv, T W) {
             const int gi = sub * NCH + g;
             if constexpr (BF) {
                 unsigned short hi, lo;
                 bf16_split((float)dv * W, hi, lo);
-                sm.Mh[buf][gi][kk >> 2][jl][kk & 3] = hi;
-                sm.Ml[buf][gi][kk >> 2][jl][kk & 3] = lo;
+                sm.Mh[buf][gi][pos >> 2][jc][pos & 3] = hi;
+                sm.Ml[buf][gi][pos >> 2][jc][pos & 3] = lo;
             } else if constexpr (KP) {
                 const T v = (T)dv * W;
-                if (kk & 1) {
-                    held[g] = v;
+                if (pos & 1) {
+                    held[g][(pos >> 3) & 1] = v;
                 } else {
                     typedef float f32x2 __attribute__((ext_vector_type(2)));
-                    *(f32x2 *)&sm.M[buf][gi][kk >> 1][jl][0] = f32x2{v, held[g]};
+                    *(f32x2 *)&sm.M[buf][gi][pos >> 1][jc][0] = f32x2{v, held[g][(pos >> 3) & 1]};
                 }
             } else {
-                sm.M[buf][gi][kk][jl] = (T)dv * W;
+                sm.M[buf][gi][pos][jc] = (T)dv * W;
             }
         };
         // keep |d| < 2^512 for chains still below the double range (checked once
@@ -419,8 +446,11 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
         // one slab.  INJ: some lane of the wave reaches a chain edge in it.
         // ES1: every chain of the wave is at scale level 0 (emission needs no
         // unscaling).
-        auto steps = [&](int chunk, int buf, auto inj_tag, auto es_tag) {
+        // PK: the slab is stored in parity blocks.  (Always inlined: a call
+        // would move the chain state it works on to scratch memory.)
+        auto steps = [&](int chunk, int buf, auto inj_tag, auto es_tag, auto pk_tag) __attribute__((always_inline)) {
             constexpr bool INJ = decltype(inj_tag)::value, ES1 = decltype(es_tag)::value;
+            constexpr bool PK = decltype(pk_tag)::value;
             const int kbase = kbase_of(chunk);
             // the step kk at which chain g reaches its edge (compared with the
             // unrolled kk, so no per-step constants are kept in registers)
@@ -455,7 +485,7 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
                     load_next(tj[kk % PD], wj[kk % PD]);
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        emit(buf, g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
+                        emit(buf, g, PK ? par16_pos(kk, TK) : kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
                     // step l -> l+1
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
@@ -474,7 +504,7 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
                     load_next(tj[kk % PD], wj[kk % PD]);
 #pragma unroll
                     for (int g = 0; g < NCH; ++g)
-                        emit(buf, g, kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
+                        emit(buf, g, PK ? par16_pos(kk, TK) : kk, ES1 ? ch[g].d : ch[g].d * ch[g].es, W);
                     // step m' -> m'-1
 #pragma unroll
                     for (int g = 0; g < NCH; ++g) {
@@ -487,7 +517,7 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
                 }
             }
         };
-        auto generate = [&](int chunk, int buf) {
+        auto generate = [&](int chunk, int buf) __attribute__((always_inline)) {
             const int kbase = kbase_of(chunk);
             fetch_factors(chunk + 1);
             // edges reached in this slab: inverse l+1 in (kbase, kbase+TK],
@@ -500,13 +530,17 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
                 lvl0 = lvl0 && ch[g].k == 0;
             }
             const bool inj = __any(mine), es1 = __all(lvl0);
-            if (inj) {
-                if (es1) steps(chunk, buf, std::true_type{}, std::true_type{});
-                else steps(chunk, buf, std::true_type{}, std::false_type{});
-            } else {
-                if (es1) steps(chunk, buf, std::false_type{}, std::true_type{});
-                else steps(chunk, buf, std::false_type{}, std::false_type{});
-            }
+            auto run = [&](auto pk_tag) __attribute__((always_inline)) {
+                if (inj) {
+                    if (es1) steps(chunk, buf, std::true_type{}, std::true_type{}, pk_tag);
+                    else steps(chunk, buf, std::true_type{}, std::false_type{}, pk_tag);
+                } else {
+                    if (es1) steps(chunk, buf, std::false_type{}, std::true_type{}, pk_tag);
+                    else steps(chunk, buf, std::false_type{}, std::false_type{}, pk_tag);
+                }
+            };
+            if (pk_of(kbase)) run(std::true_type{});
+            else run(std::false_type{});
 #pragma unroll
             for (int g = 0; g < NCH; ++g) renorm(ch[g]);
             store_factors(buf ^ 1);
@@ -546,13 +580,15 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
 
     auto mfma_slab = [&](int chunk, int buf) {
         const int kbase = kbase_of(chunk);
-        const int wj0 = j0 + jw * WJ;  // first j of this consumer wave
+        // this wave's j: positions jw WJ .. jw WJ + WJ - 1 of the tile, i.e.
+        // WJ consecutive j, or (parity placement) every other j from wj0
+        const int wj0 = j0 + jpos(jw * WJ), wj1 = wj0 + (pj ? 2 : 1) * (WJ - 1);
         bool active = c0 + cwo < cend;  // some column of this wave exists
         if (MODE == kInverse) {
             const int start = m0 > wj0 ? m0 : wj0;
             active = active && kbase + TK - 1 >= start && wj0 < L;
         } else {
-            active = active && kbase <= wj0 + WJ - 1 && wj0 < L;
+            active = active && kbase <= wj1 && wj0 < L;
         }
         if (!active) return;
         if constexpr (BF) {
@@ -594,75 +630,157 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
             // K slots in pairs: pair group (g, h) covers steps 2h and 2h + 1
             // of order g; slot q of step 2h + e takes k = 8h + 2q + e, so a
             // lane's two operands of a pair group are one 8-byte read from each
-            // slab.  Fragments double-buffered as below.
+            // slab.  Fragments double-buffered as below.  This lane's X base
+            // for pair group h is k = 8h + 2 (lane >> 4); in the swizzled rows
+            // its quad 2h + (lane >> 5) sits at slot (2h + (lane >> 5)) ^
+            // ((lane >> 2) & 3).
             typedef float f32x2 __attribute__((ext_vector_type(2)));
-            constexpr int NPG = GM * 2;
             f32x2 av[2][NCI], bv[2][NJI];
-            // this lane's X base for pair group h (k = 8h + 2 (lane >> 4) + e);
-            // in the swizzled rows its quad 2h + (lane >> 5) sits at slot
-            // (2h + (lane >> 5)) ^ ((lane >> 2) & 3)
-            const float *xlh[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = DX ? (2 * h + (lane >> 5)) ^ ((lane >> 2) & 3) : 2 * h + (lane >> 5);
-                xlh[h] = &sm.X[buf][0][cwo + (lane & 15)][4 * q + 2 * ((lane >> 4) & 1)];
-            }
-            const float *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)][0];
             constexpr int XR = Slabs<P, CTILE, KP>::XROW, MR = (TJ + 16) * 2;
-            auto ldfrag = [&](int idx, int slot) {
-                const int g = idx / 2, h = idx % 2;
+            // halves of the slab (parity kernel): pair group h of every order,
+            // in a loop that is not unrolled (one copy of the body)
+            auto halves = [&](int h0, int nhalf) __attribute__((always_inline)) {
+#pragma clang loop unroll(disable)
+                for (int hf = 0; hf < nhalf; ++hf) {
+                    const int h = h0 + hf;
+                    const int q = DX ? (2 * h + (lane >> 5)) ^ ((lane >> 2) & 3) : 2 * h + (lane >> 5);
+                    const float *xl = &sm.X[buf][0][cwo + (lane & 15)][4 * q + 2 * ((lane >> 4) & 1)];
+                    const float *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)][0] + 4 * h * MR;
+                    auto ldfrag = [&](int g, int slot) {
 #pragma unroll
-                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = *(const f32x2 *)&xlh[h][(g * CTILE + ci * 16) * XR];
+                        for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = *(const f32x2 *)&xl[(g * CTILE + ci * 16) * XR];
 #pragma unroll
-                for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = *(const f32x2 *)&ml[(g * (TK / 2) + 4 * h) * MR + ji * 32];
+                        for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = *(const f32x2 *)&ml[g * (TK / 2) * MR + ji * 32];
+                    };
+                    ldfrag(0, 0);
+#pragma unroll
+                    for (int g = 0; g < GM; ++g) {
+                        if (g + 1 < GM) ldfrag(g + 1, (g + 1) & 1);
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+#pragma unroll
+                            for (int ci = 0; ci < NCI; ++ci)
+#pragma unroll
+                                for (int ji = 0; ji < NJI; ++ji)
+                                    acc[g][ci][ji] = Mfma<T>::op(av[g & 1][ci][e], bv[g & 1][ji][e], acc[g][ci][ji]);
+                    }
+                }
             };
-            ldfrag(0, 0);
+            // the whole slab in one pass
+            auto whole = [&]() __attribute__((always_inline)) {
+                constexpr int NPG = GM * 2;
+                const float *xlh[2];
 #pragma unroll
-            for (int idx = 0; idx < NPG; ++idx) {
-                if (idx + 1 < NPG) ldfrag(idx + 1, (idx + 1) & 1);
-                const int g = idx / 2;
+                for (int h = 0; h < 2; ++h) {
+                    const int q = DX ? (2 * h + (lane >> 5)) ^ ((lane >> 2) & 3) : 2 * h + (lane >> 5);
+                    xlh[h] = &sm.X[buf][0][cwo + (lane & 15)][4 * q + 2 * ((lane >> 4) & 1)];
+                }
+                const float *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)][0];
+                auto ldfrag = [&](int idx, int slot) {
+                    const int g = idx / 2, h = idx % 2;
 #pragma unroll
-                for (int e = 0; e < 2; ++e)
+                    for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = *(const f32x2 *)&xlh[h][(g * CTILE + ci * 16) * XR];
+#pragma unroll
+                    for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = *(const f32x2 *)&ml[(g * (TK / 2) + 4 * h) * MR + ji * 32];
+                };
+                ldfrag(0, 0);
+#pragma unroll
+                for (int idx = 0; idx < NPG; ++idx) {
+                    if (idx + 1 < NPG) ldfrag(idx + 1, (idx + 1) & 1);
+                    const int g = idx / 2;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e)
+#pragma unroll
+                        for (int ci = 0; ci < NCI; ++ci)
+#pragma unroll
+                            for (int ji = 0; ji < NJI; ++ji)
+                                acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci][e], bv[idx & 1][ji][e], acc[g][ci][ji]);
+                }
+            };
+            // parity kernel: in a parity-block slab only the half of the
+            // wave's parity, else both halves
+            if constexpr (P == kP32 && PAR) {
+                const bool pk = pk_of(kbase);  // one call: one copy of the body
+                halves(pk ? (jw * WJ) / (TJ / 2) : 0, pk ? 1 : 2);
+            } else {
+                whole();
+            }
+        } else {
+            // operand fragments double-buffered: group idx+1 is read from LDS
+            // while the MFMAs of group idx run.  This lane's fragment bases in
+            // the slab (X: k quad q, at slot q ^ ((lane >> 2) & 3) in swizzled
+            // rows); every fragment is a constant offset from them.
+            T av[2][NCI], bv[2][NJI];
+            constexpr int XR = Slabs<P, CTILE, KP>::XROW, MR = TJ + 16;
+            // halves of the slab (parity kernel): k quads 2h and 2h + 1 of
+            // every order, in a loop that is not unrolled (one copy of the body)
+            auto halves = [&](int h0, int nhalf) __attribute__((always_inline)) {
+#pragma clang loop unroll(disable)
+                for (int hf = 0; hf < nhalf; ++hf) {
+                    const int kq0 = 2 * (h0 + hf);
+                    const T *xl[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int q = DX ? (kq0 + e) ^ ((lane >> 2) & 3) : kq0 + e;
+                        xl[e] = &sm.X[buf][0][cwo + (lane & 15)][4 * q + (lane >> 4)];
+                    }
+                    const T *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)] + 4 * kq0 * MR;
+                    constexpr int NG = GM * 2;
+                    auto ldfrag = [&](int idx, int slot) {
+                        const int g = idx / 2, e = idx % 2;
+#pragma unroll
+                        for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = xl[e][(g * CTILE + ci * 16) * XR];
+#pragma unroll
+                        for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = ml[(g * TK + e * 4) * MR + ji * 16];
+                    };
+                    ldfrag(0, 0);
+#pragma unroll
+                    for (int idx = 0; idx < NG; ++idx) {
+                        if (idx + 1 < NG) ldfrag(idx + 1, (idx + 1) & 1);
+                        const int g = idx / 2;
+#pragma unroll
+                        for (int ci = 0; ci < NCI; ++ci)
+#pragma unroll
+                            for (int ji = 0; ji < NJI; ++ji)
+                                acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci], bv[idx & 1][ji], acc[g][ci][ji]);
+                    }
+                }
+            };
+            // the whole slab in one pass
+            auto whole = [&]() __attribute__((always_inline)) {
+                constexpr int NKS = TK / 4, NGRP = GM * NKS;
+                const T *xlk[NKS];
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) {
+                    const int q = DX ? ks ^ ((lane >> 2) & 3) : ks;
+                    xlk[ks] = &sm.X[buf][0][cwo + (lane & 15)][4 * q + (lane >> 4)];
+                }
+                const T *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)];
+                auto ldfrag = [&](int idx, int slot) {
+                    const int g = idx / NKS, ks = idx % NKS;
+#pragma unroll
+                    for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = xlk[ks][(g * CTILE + ci * 16) * XR];
+#pragma unroll
+                    for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = ml[(g * TK + ks * 4) * MR + ji * 16];
+                };
+                ldfrag(0, 0);
+#pragma unroll
+                for (int idx = 0; idx < NGRP; ++idx) {
+                    if (idx + 1 < NGRP) ldfrag(idx + 1, (idx + 1) & 1);
+                    const int g = idx / NKS;
 #pragma unroll
                     for (int ci = 0; ci < NCI; ++ci)
 #pragma unroll
                         for (int ji = 0; ji < NJI; ++ji)
-                            acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci][e], bv[idx & 1][ji][e], acc[g][ci][ji]);
-            }
-        } else {
-            // operand fragments double-buffered: group idx+1 is read from LDS
-            // while the MFMAs of group idx run
-            constexpr int NKS = TK / 4, NGRP = GM * NKS;
-            T av[2][NCI], bv[2][NJI];
-            // this lane's fragment bases in the slab; every fragment is a
-            // constant offset from them
-            // this lane's X base for k quad ks (swizzled rows: slot
-            // ks ^ ((lane >> 2) & 3))
-            const T *xlk[NKS];
-#pragma unroll
-            for (int ks = 0; ks < NKS; ++ks) {
-                const int q = DX ? ks ^ ((lane >> 2) & 3) : ks;
-                xlk[ks] = &sm.X[buf][0][cwo + (lane & 15)][4 * q + (lane >> 4)];
-            }
-            const T *ml = &sm.M[buf][0][lane >> 4][jw * WJ + (lane & 15)];
-            constexpr int XR = Slabs<P, CTILE, KP>::XROW, MR = TJ + 16;
-            auto ldfrag = [&](int idx, int slot) {
-                const int g = idx / NKS, ks = idx % NKS;
-#pragma unroll
-                for (int ci = 0; ci < NCI; ++ci) av[slot][ci] = xlk[ks][(g * CTILE + ci * 16) * XR];
-#pragma unroll
-                for (int ji = 0; ji < NJI; ++ji) bv[slot][ji] = ml[(g * TK + ks * 4) * MR + ji * 16];
+                            acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci], bv[idx & 1][ji], acc[g][ci][ji]);
+                }
             };
-            ldfrag(0, 0);
-#pragma unroll
-            for (int idx = 0; idx < NGRP; ++idx) {
-                if (idx + 1 < NGRP) ldfrag(idx + 1, (idx + 1) & 1);
-                const int g = idx / NKS;
-#pragma unroll
-                for (int ci = 0; ci < NCI; ++ci)
-#pragma unroll
-                    for (int ji = 0; ji < NJI; ++ji)
-                        acc[g][ci][ji] = Mfma<T>::op(av[idx & 1][ci], bv[idx & 1][ji], acc[g][ci][ji]);
+            // parity kernel: as in the paired path above
+            if constexpr (P == kP32 && PAR) {
+                const bool pk = pk_of(kbase);  // one call: one copy of the body
+                halves(pk ? (jw * WJ) / (TJ / 2) : 0, pk ? 1 : 2);
+            } else {
+                whole();
             }
         }
     };
@@ -706,9 +824,11 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
             }
         };
         // otherwise element by element with the bounds of the panel rows
-        // (inverse: l >= m), through registers
+        // (inverse: l >= m, with l the degree a position holds), through
+        // registers
         auto load_masked = [&](int chunk, int buf) {
             const int kbase = kbase_of(chunk);
+            const bool pk = pk_of(kbase);
 #pragma unroll
             for (int i = 0; i < NSL; ++i) {
                 const int sl = (wv * NSL + i) * 64 + lane;
@@ -718,8 +838,8 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
                 T v[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int k = kbase + 4 * lq + e;
-                    const bool ok = row && k >= 0 && k < L && (MODE != kInverse || k >= m0 + g);
+                    const int k = kbase + 4 * lq + e, kt = kbase + (pk ? par16_idx(4 * lq + e) : 4 * lq + e);
+                    const bool ok = row && k >= 0 && k < L && (MODE != kInverse || kt >= m0 + g);
                     v[e] = ok ? src[k] : T(0);
                 }
                 *(float4 *)(&sm.X[buf][0][0][0] + sl * 4) = make_float4(v[0], v[1], v[2], v[3]);
@@ -825,7 +945,9 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
                 for (int i = 0; i < XPT; ++i) {
                     const int k = kbase + xkk[i];
                     bool ok = xok[i] && k >= 0 && k < L;
-                    if (MODE == kInverse) ok = ok && k >= m0 + xg[i];
+                    // the degree this position holds (parity blocks: par16_idx)
+                    const int kt = kbase + (pk_of(kbase) ? par16_idx(xkk[i]) : xkk[i]);
+                    if (MODE == kInverse) ok = ok && kt >= m0 + xg[i];
                     xr[i] = ok ? xbase[xoff[i] + kbase] : T(0);
                 }
             }
@@ -878,18 +1000,28 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int c = c0 + cwo + ci * 16 + Mfma<T>::row(lane, r);
-                    const int jj = j0 + jw * WJ + ji * 16 + (lane & 15);
+                    const int jj = j0 + jpos(jw * WJ + ji * 16 + (lane & 15));
                     if (c < cend && jj < L) yrow[c * L + jj] = acc[g][ci][ji][r];
                 }
     }
 }
 
+// par: the parity kernel (spin-0 blocks of FP32 data; 64-column-or-narrower
+// FP32 and BF16x3 tiles)
 template <int P, int MODE, int CTILE>
-hipError_t launch_one(Args<typename Prec<P>::T> a, int nsched, bool tab, hipStream_t st) {
+hipError_t launch_one(Args<typename Prec<P>::T> a, int nsched, bool tab, bool par, hipStream_t st) {
     if (nsched == 0 || a.ncb == 0) return hipSuccess;
     const dim3 grid(nsched, a.ncb);
-    if (tab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true>), grid, dim3(kThreads<P>), 0, st, a);
-    else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false>), grid, dim3(kThreads<P>), 0, st, a);
+    if constexpr (P == kP32 || P == kPBF) {
+        if (par) {
+            if (tab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true, true>), grid, dim3(kThreads<P>), 0, st, a);
+            else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false, true>), grid, dim3(kThreads<P>), 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    if (par) return hipErrorInvalidValue;
+    if (tab) hipLaunchKernelGGL((k_contract<P, MODE, CTILE, true, false>), grid, dim3(kThreads<P>), 0, st, a);
+    else hipLaunchKernelGGL((k_contract<P, MODE, CTILE, false, false>), grid, dim3(kThreads<P>), 0, st, a);
     return hipGetLastError();
 }
 
@@ -945,6 +1077,34 @@ std::map<std::tuple<int, int, int, int>, int> g_tiles;
 
 // (several spins: the cost is summed over their column ranges; a pinned tile
 // is looked up under the total column count)
+// Segments a launch takes: all, only those of spin 0, or only the others.
+enum { kAllSpins = 0, kSpinZero = 1, kSpinNonzero = 2 };
+bool seg_in(const ContractSeg &sg, int which) {
+    return which == kAllSpins || ((sg.sp->spin == 0) == (which == kSpinZero));
+}
+
+// the cost model's best tile up to tmax over the segments `which` selects
+int best_tile(int nseg, const ContractSeg *seg, int tmax, int which) {
+    int best = 16;
+    long best_cost = -1;
+    for (int t = 16; t <= tmax; t *= 2) {
+        const int gran = t > 64 ? 64 : t;
+        long cost = 0;
+        for (int k = 0; k < nseg; ++k) {
+            if (!seg_in(seg[k], which)) continue;
+            for (int c = 0; c < seg[k].ncol; c += t) {
+                const int n = seg[k].ncol - c < t ? seg[k].ncol - c : t;
+                cost += (n + gran - 1) / gran * gran + 24;
+            }
+        }
+        if (best_cost < 0 || cost < best_cost) {
+            best = t;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 int contract_tile(int L, int nseg, const ContractSeg *seg, int P) {
     int C = 0;
     for (int k = 0; k < nseg; ++k) C += seg[k].ncol;
@@ -955,28 +1115,13 @@ int contract_tile(int L, int nseg, const ContractSeg *seg, int P) {
         auto it = g_tiles.find(std::make_tuple(dev, L, C, P));
         if (it != g_tiles.end()) return it->second;
     }
-    int best = 16;
-    long best_cost = -1;
-    const int tmax = P == kP32 ? 128 : 64;
-    for (int t = 16; t <= tmax; t *= 2) {
-        const int gran = t > 64 ? 64 : t;
-        long cost = 0;
-        for (int k = 0; k < nseg; ++k)
-            for (int c = 0; c < seg[k].ncol; c += t) {
-                const int n = seg[k].ncol - c < t ? seg[k].ncol - c : t;
-                cost += (n + gran - 1) / gran * gran + 24;
-            }
-        if (best_cost < 0 || cost < best_cost) {
-            best = t;
-            best_cost = cost;
-        }
-    }
-    return best;
+    return best_tile(nseg, seg, P == kP32 ? 128 : 64, kAllSpins);
 }
 
 template <int P>
 hipError_t launch_tiled(int mode, int L, int nseg, const ContractSeg *seg, int ct, const typename Prec<P>::T *X,
-                        typename Prec<P>::T *Y, const EdgeTable &E, const RecTables &rt, hipStream_t st) {
+                        typename Prec<P>::T *Y, const EdgeTable &E, const RecTables &rt, hipStream_t st, int which,
+                        bool par) {
     using T = typename Prec<P>::T;
     Args<T> a;
     a.L = L;
@@ -996,6 +1141,10 @@ hipError_t launch_tiled(int mode, int L, int nseg, const ContractSeg *seg, int c
     bool tab = true;
     int nb = 0, c = 0;
     for (int k = 0; k < nseg; ++k) {
+        if (!seg_in(seg[k], which)) {  // another launch's columns
+            c += seg[k].ncol;
+            continue;
+        }
         const SpinPlan &sp = *seg[k].sp;
         const T *w, *mt;
         if constexpr (P == kP64) {
@@ -1019,17 +1168,17 @@ hipError_t launch_tiled(int mode, int L, int nseg, const ContractSeg *seg, int c
     }
     a.ncb = nb;
     if constexpr (P == kP32W) {
-        return mode == kInverse ? launch_one<P, kInverse, 128>(a, ns, tab, st)
-                                : launch_one<P, kForward, 128>(a, ns, tab, st);
+        return mode == kInverse ? launch_one<P, kInverse, 128>(a, ns, tab, par, st)
+                                : launch_one<P, kForward, 128>(a, ns, tab, par, st);
     } else {
         if (ct == 16)
-            return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, tab, st)
-                                    : launch_one<P, kForward, 16>(a, ns, tab, st);
+            return mode == kInverse ? launch_one<P, kInverse, 16>(a, ns, tab, par, st)
+                                    : launch_one<P, kForward, 16>(a, ns, tab, par, st);
         if (ct == 32)
-            return mode == kInverse ? launch_one<P, kInverse, 32>(a, ns, tab, st)
-                                    : launch_one<P, kForward, 32>(a, ns, tab, st);
-        return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, tab, st)
-                                : launch_one<P, kForward, 64>(a, ns, tab, st);
+            return mode == kInverse ? launch_one<P, kInverse, 32>(a, ns, tab, par, st)
+                                    : launch_one<P, kForward, 32>(a, ns, tab, par, st);
+        return mode == kInverse ? launch_one<P, kInverse, 64>(a, ns, tab, par, st)
+                                : launch_one<P, kForward, 64>(a, ns, tab, par, st);
     }
 }
 
@@ -1037,10 +1186,27 @@ template <int P>
 hipError_t launch_prec(int mode, int L, int nseg, const ContractSeg *seg, const typename Prec<P>::T *X,
                        typename Prec<P>::T *Y, const EdgeTable &E, const RecTables &rt, hipStream_t st) {
     const int ct = contract_tile(L, nseg, seg, P);
-    if constexpr (P == kP32) {
-        if (ct == 128) return launch_tiled<kP32W>(mode, L, nseg, seg, ct, X, Y, E, rt, st);
+    if constexpr (P == kP64) {
+        return launch_tiled<P>(mode, L, nseg, seg, ct, X, Y, E, rt, st, kAllSpins, false);
+    } else {
+        // FP32 data: the spin-0 segments (their panels in parity blocks) go to
+        // the parity kernel, on a tile of at most 64 columns; the others to
+        // the plain one, the 128-column tile when chosen (two launches on the
+        // stream when there are both)
+        bool zero = false, other = false;
+        for (int k = 0; k < nseg; ++k) (seg[k].sp->spin == 0 ? zero : other) = true;
+        hipError_t e = hipSuccess;
+        if (other) {
+            const int which = zero ? kSpinNonzero : kAllSpins;
+            if (P == kP32 && ct == 128) e = launch_tiled<kP32W>(mode, L, nseg, seg, ct, X, Y, E, rt, st, which, false);
+            else e = launch_tiled<P>(mode, L, nseg, seg, ct, X, Y, E, rt, st, which, false);
+        }
+        if (e == hipSuccess && zero) {
+            const int ct0 = ct > 64 ? best_tile(nseg, seg, 64, kSpinZero) : ct;
+            e = launch_tiled<P>(mode, L, nseg, seg, ct0, X, Y, E, rt, st, other ? kSpinZero : kAllSpins, true);
+        }
+        return e;
     }
-    return launch_tiled<P>(mode, L, nseg, seg, ct, X, Y, E, rt, st);
 }
 
 }  // namespace

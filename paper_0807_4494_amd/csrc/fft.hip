@@ -628,7 +628,9 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int
 // [-(L-1), L-1] gives both rows: X_{mu m'} = c_{m'} 2 pi (Y(m') + sigma Y(-m')).
 // Written as X[|mu|][c][m'] with c = q*B + b (q = 0,1 for mu >= 0, 2,3 for
 // mu < 0), times (-1)^{m'} for mu < 0 (the d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
-// symmetry; the (-1)^l part is applied on output).
+// symmetry; the (-1)^l part is applied on output).  Spin 0 in FP32: each
+// complete block of 16 orders m' of a row is stored even orders first
+// (par16_pos), the order the FP32 and BF16x3 spin-0 contractions read.
 // HALF (real spin-0 signals): only mu >= 0, rings of L orders, pairs
 // (2i, 2i+1), 2-column panels.
 template <typename T, int LOGM, bool HALF>
@@ -706,8 +708,9 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, i
             C x{(yp.x + sg * ym.x) * w, (yp.y + sg * ym.y) * w};
             if (k == h) x = cadd(x, top);
             const T sgn = ((neg ^ flip) && (k & 1)) ? T(-1) : T(1);
-            Xre[k] = x.x * sgn;
-            Xim[k] = x.y * sgn;
+            const int pk = (s == 0 && sizeof(T) == 4) ? par16_pos(k, L) : k;  // FP32 spin 0: parity blocks
+            Xre[pk] = x.x * sgn;
+            Xim[pk] = x.y * sgn;
         }
     };
     store(mua, oddA, Qa);

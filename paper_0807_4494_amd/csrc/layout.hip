@@ -17,6 +17,10 @@
 // -s, d^l_{m',s}(pi/2) = (-1)^{l+m'} d^l_{m',-s}(pi/2) (Eq. (wignerd_sym6)):
 // their panels carry one more (-1)^l here, the theta stages the (-1)^{m'}.
 //
+// Spin 0 (FP32 panels): each complete block of 16 degrees of a panel row is
+// stored even degrees first (par16_pos), the order the FP32 and BF16x3
+// spin-0 contractions read.
+//
 // HALF (real spin-0 signals, f_{l,-m} = (-1)^m conj(f_lm), Section 3.3):
 // only q = 0, 1 are kept (c = q*B + b, 2B columns); the output side writes
 // the negative orders from the symmetry.
@@ -66,7 +70,8 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, 
     for (int mi = ty; mi < TL; mi += 8) {
         const int m = m0 + mi, l = l0 + tx;
         if (m >= L || l >= L || l < m) continue;
-        for (int q = 0; q < NQ; ++q) P[((size_t)m * Cn + coff + (size_t)q * B + b) * L + l] = tile[q][tx][mi];
+        const int pl = (s == 0 && sizeof(T) == 4) ? par16_pos(l, L) : l;  // FP32 spin 0: parity blocks
+        for (int q = 0; q < NQ; ++q) P[((size_t)m * Cn + coff + (size_t)q * B + b) * L + pl] = tile[q][tx][mi];
     }
 }
 

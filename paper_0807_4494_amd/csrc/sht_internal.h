@@ -65,6 +65,19 @@ template <typename T> struct FftTables {
 // aligned 16-byte piece), L + (L & 1) for real maps (orders m >= 0).
 __host__ __device__ constexpr int ring_len(int L, bool half) { return half ? L + (L & 1) : 2 * L; }
 
+// Spin-0 panel order (FP32 data).  Delta^l_{m',0}(pi/2) vanishes for odd
+// l + m', so spin-0 contractions pair even degrees with even m' and odd with
+// odd.  The FP32 contraction inputs of spin 0 (degrees l of the inverse's
+// coefficient panels, orders m' of the forward's theta-stage output)
+// therefore hold each complete aligned block of 16 indices as its 8 even
+// entries followed by its 8 odd ones; an incomplete last block keeps the
+// natural order.
+__host__ __device__ constexpr int par16_pos(int k, int L) {
+    return (k | 15) < L ? (k & ~15) | ((k & 1) << 3) | ((k & 15) >> 1) : k;
+}
+// offset within a complete block: position p holds index 2 (p & 7) + (p >> 3)
+__host__ __device__ constexpr int par16_idx(int p) { return ((p & 7) << 1) | ((p >> 3) & 1); }
+
 // Rows whose M-point buffer exceeds the LDS (FP64 at M = 16384) run as two
 // halves with a global scratch slot of M complex values per workgroup; a
 // launch uses at most kSplitSlots workgroups.

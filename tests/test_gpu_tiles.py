@@ -28,8 +28,11 @@ def rel(a, b):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 # L % 4 == 0 takes the 128-column tile's LDS-direct X loads, other L its
-# element-wise loads; 4 B = 68 and 132 columns fill both halves of a block
-@pytest.mark.parametrize("L,s,B", [(48, 0, 2), (64, 1, 6), (100, -2, 7), (70, 2, 17), (132, 3, 33)])
+# element-wise loads; 4 B = 68 and 132 columns fill both halves of a block.
+# Spin 0 runs the parity kernel (complete 16-blocks in parity order, an
+# incomplete last block at L = 143; a pinned 128 tile falls back to 64).
+@pytest.mark.parametrize("L,s,B", [(48, 0, 2), (64, 1, 6), (100, -2, 7), (70, 2, 17), (132, 3, 33),
+                                   (143, 0, 17)])
 def test_every_tile_gives_the_transform(L, s, B, prec):
     sht = _sht()
     print(f"[tiles] L={L} s={s} B={B} {prec}", flush=True)
