@@ -397,8 +397,9 @@ def tile_autotune(prec: str, shapes) -> dict:
         back = torch.empty_like(x)
         ws = torch.empty(sht.workspace_bytes(L, s, B, prec), dtype=torch.uint8, device=dev)
         times = {}
+        tiles = (16, 32, 64, 128) if prec == "fp32" else (16, 32, 64)
         try:
-            for tile in (16, 32, 64):
+            for tile in tiles:
                 sht.tile_set(L, 4 * B, prec, tile)
                 for _ in range(2):
                     sht.inverse(x, L, s, prec, out=m, workspace=ws)
@@ -416,7 +417,13 @@ def tile_autotune(prec: str, shapes) -> dict:
         finally:
             sht.tile_set(L, 4 * B, prec, 0)
         C = 4 * B
-        default = min((16, 32, 64), key=lambda t: (-(-C // t) * (t + 24), t))
+
+        def cost(t):
+            # the library's model: each column block's columns rounded up to t
+            # (to 64 in the 128-column tile) plus 24 for its Wigner generation
+            g = min(t, 64)
+            return sum(-(-min(t, C - c) // g) * g + 24 for c in range(0, C, t))
+        default = min(tiles, key=lambda t: (cost(t), t))
         out[f"L{L}_s{s}_b{B}"] = {"ms_per_pair_by_tile": times, "default_tile": default,
                                   "tuned_tile": pick, "best_tile": min(times, key=times.get)}
     return out
