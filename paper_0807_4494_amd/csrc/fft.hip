@@ -471,10 +471,12 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N)
 // sigma, so one length-N transform of their sum Z gives both:
 //   g_mu(theta_t) = (Z(theta_t) + sigma_mu Z(theta_{N-1-t})) / 2.
 // Block (b, i) takes mu = 2i - (L-1) and mu + 1 (the last block of a map
-// takes mu = L-1 alone).  Output: columns mu + L - 1 and mu + L of the rings
-// G[b][t][.] that the phi stage reads (one 16-byte or 32-byte piece per t).
+// takes mu = L-1 alone).  Output: columns 2i and 2i + 1 (mu + L - 1 and
+// mu + L) of every ring t, stored pair-major, G[b][i][t][2]: the block's
+// output is one contiguous run of L 16-byte pieces (strided stores cost far
+// more here than strided loads; the phi stage gathers the pairs of a ring).
 // HALF (real spin-0 signals): only mu >= 0, from the 2-column panels, pairs
-// (2i, 2i+1), rings of L orders.
+// (2i, 2i+1), rings of L orders, ring-major G[b][t][.].
 template <typename T, int LOGM, bool HALF>
 __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B, int Cn, int coff,
                                                            int flip, const T *__restrict__ R,
@@ -539,11 +541,13 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     // columns mu and mu+1 of the rings G[b][t][.] (ring_len: even, and mu
     // starts at an even column, so a pair is one aligned 16-byte piece)
     const int rl = ring_len(L, HALF);
-    C *Ga = G + (size_t)b * L * rl + (HALF ? mua : mua + h);
+    // ring-major (HALF): piece t at Ga + t rl; pair-major: at Ga + 2t
+    C *Ga = G + (size_t)b * L * rl + (HALF ? mua : (size_t)pair * rl);
+    const size_t ts = HALF ? (size_t)rl : 2;
     const T sa = ra.odd ? T(-0.5) : T(0.5);
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const C z = buf[pad(t)], zr = buf[pad(N - 1 - t)];
-        C *g = Ga + (size_t)t * rl;
+        C *g = Ga + (size_t)t * ts;
         const C ga{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
         if (two) store_pair(g, ga, C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y});
         else g[0] = ga;
@@ -551,7 +555,9 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     });
 }
 
-// Inverse phi stage.  Row (b, t): f(theta_t, phi_p) = sum_mu g_mu(theta_t) e^{i mu phi_p}.
+// Inverse phi stage.  Row (b, t): f(theta_t, phi_p) = sum_mu g_mu(theta_t) e^{i mu phi_p},
+// g_mu(theta_t) from the theta stage's pair-major rings: column n of ring t of
+// map b at G[b][n / 2][t][n % 2] (rs = 2L values per pair, L rings per map).
 template <typename T, int LOGM>
 __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int rows, int rs,
                                                          const typename CT<T>::type *__restrict__ G,
@@ -562,12 +568,25 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int N = ft.N;
     for_items<split_rows<T, LOGM>()>(rows, [&](int item) {
-    const size_t row = split_rows<T, LOGM>() ? (size_t)item : (size_t)blockIdx.x;
-    const C *in = G + row * rs;
+    // rows in XCD-grouped order: neighbouring rings share the lines of the
+    // pair-major layout, and this keeps them in one XCD's L2
+    const size_t row = (size_t)item;
+    const int L = ft.L;
+    const C *in = G + (row / L) * L * rs + 2 * (row % L);
     C *out = map + row * N;
     const C *cha = ft.cha, *chb = ft.chb;
+    // the ring's pairs gathered into LDS, one 16-byte piece per load (the
+    // FFT's first pass reads them before it overwrites the buffer)
+    C *sr = buf;
+    for (int q = threadIdx.x; q < L; q += blockDim.x) {
+        C a, c;
+        load_pair(in + (size_t)q * rs, a, c);
+        sr[2 * q] = a;
+        sr[2 * q + 1] = c;
+    }
+    __syncthreads();
     auto ld = [&](int n) -> C {
-        const C x = cmul(ldc(in, n, N), ldc(cha, n, N));
+        const C x = cmul(sr[n < N ? n : N - 1], ldc(cha, n, N));
         return n < N ? x : C{T(0), T(0)};
     };
     auto pre = [&](int p) { return ldc(chb, p, N); };
