@@ -41,10 +41,12 @@
  *
  * Semantics: every transform call only enqueues work on `stream` (a
  * hipStream_t; NULL = the legacy default stream) and returns.  The first call
- * for a new (L, spin, precision) builds its plan, which allocates device
- * memory and enqueues the plan kernels on the same stream.  Results are
- * deterministic for a given (L, spin, batch, precision).  Calls may be made
- * from several host threads; the plan cache is internally locked.
+ * for a new (L, spin) on a device builds its plan: it allocates device memory,
+ * runs the plan kernels on a stream of the library's own (one per device,
+ * default priority) and waits for them, but not for the work already queued
+ * on `stream`.  Results are deterministic for a given (L, spin, batch,
+ * precision).  Calls may be made from several host threads: plans are built
+ * one at a time, and calls whose plans are resident do not wait for a build.
  *
  * Errors: 0 on success, a negative SHT_ERR_* code otherwise.  All argument
  * checks run before any HIP call; a failed check enqueues nothing.  No C++
@@ -235,9 +237,10 @@ int sht_forward_lstsq(int L, int spin, int batch, int sampling, int precision,
  * (the same size serves both directions).  0 if the arguments are invalid. */
 size_t sht_workspace_bytes(int L, int spin, int batch, int sampling, int precision);
 
-/* Build (or find) the plan for (L, spin, precision) on the current device,
- * enqueueing its kernels on `stream`.  Optional: transforms build plans on
- * first use.  Returns SHT_OK or an error code. */
+/* Build (or find) the plan for (L, spin, precision) on the current device
+ * (the plan kernels run on the library's own stream and are waited for;
+ * `stream` is not used).  Optional: transforms build plans on first use.
+ * Returns SHT_OK or an error code. */
 int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream);
 
 /*
@@ -269,8 +272,8 @@ int sht_plan_tables(int L, int spin, int precision, int enable, void *stream);
  * The graph binds these device buffers: they stay owned by the caller, must
  * outlive the graph, and a launch overwrites map, flm_out and the workspace.
  * Launches of one graph, or of graphs sharing buffers, that overlap on
- * different streams race.  Creation builds the plan (synchronising `stream`)
- * and records without executing anything; *out receives the handle (NULL on
+ * different streams race.  Creation builds the plan if needed (as a first
+ * transform call does) and records without executing anything; *out receives the handle (NULL on
  * error).  Errors as for sht_inverse; SHT_ERR_INVALID_ARG for a NULL out or
  * an unknown handle, or a launch on another device than the creation's.
  * sht_release_all destroys every live graph.

@@ -36,6 +36,14 @@ std::map<int, DeviceState> g_devices;
 std::map<std::tuple<int, int>, Plan *> g_plans;              // (device, L)
 std::map<std::tuple<int, int, int>, SpinPlan *> g_spin;      // (device, L, spin)
 
+// Plans are built one at a time (g_build_mu), on a stream of the library's
+// own per device, with g_mu held only to look them up and to publish them: a
+// first-use build waits for its own kernels, not for the caller's queued
+// work, and transforms whose plans exist do not wait for it.  Lock order:
+// g_build_mu before g_mu.
+std::mutex g_build_mu;
+std::map<int, hipStream_t> g_build_streams;
+
 // ---- captured transforms ----
 }  // namespace
 struct sht_graph_s {
@@ -136,8 +144,11 @@ int check_args(int L, int spin, int batch, int sampling, int precision) {
 }
 
 int get_device_state(int dev, hipStream_t st, DeviceState **out) {
-    auto it = g_devices.find(dev);
-    if (it != g_devices.end()) { *out = &it->second; return SHT_OK; }
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_devices.find(dev);
+        if (it != g_devices.end()) { *out = &it->second; return SHT_OK; }
+    }
     DeviceState ds;
     ds.E.lmax = SHT_L_MAX;
     const size_t n = (size_t)SHT_L_MAX * (SHT_L_MAX + 1) / 2;
@@ -145,6 +156,7 @@ int get_device_state(int dev, hipStream_t st, DeviceState **out) {
     if (hipMalloc(&ds.E.expo, n * sizeof(int)) != hipSuccess) { (void)hipFree(ds.E.mant); return SHT_ERR_OOM; }
     SHT_HIP(launch_edge_table(ds.E, st), "edge table");
     SHT_HIP(hipStreamSynchronize(st), "edge table sync");
+    std::lock_guard<std::mutex> lock(g_mu);
     auto res = g_devices.emplace(dev, ds);
     *out = &res.first->second;
     return SHT_OK;
@@ -177,8 +189,11 @@ template <typename T> int alloc_fft(FftTables<T> &ft, int L) {
 
 int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     auto key = std::make_tuple(dev, L);
-    auto it = g_plans.find(key);
-    if (it != g_plans.end()) { *out = it->second; return SHT_OK; }
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) { *out = it->second; return SHT_OK; }
+    }
     Plan *p = new Plan();
     p->device = dev;
     p->L = L;
@@ -208,6 +223,7 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
     SHT_HIP(prepare_row_kernels<double>(p->f64), "row kernel attributes f64");
     SHT_HIP(prepare_row_kernels<float>(p->f32), "row kernel attributes f32");
     SHT_HIP(hipStreamSynchronize(st), "plan sync");
+    std::lock_guard<std::mutex> lock(g_mu);
     g_plans[key] = p;
     *out = p;
     return SHT_OK;
@@ -216,8 +232,11 @@ int get_plan(int dev, int L, hipStream_t st, Plan **out) {
 int get_spin_plan(int dev, int L, int spin, const DeviceState *ds, const Plan *plan, hipStream_t st,
                   SpinPlan **out) {
     auto key = std::make_tuple(dev, L, spin);
-    auto it = g_spin.find(key);
-    if (it != g_spin.end()) { *out = it->second; return SHT_OK; }
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_spin.find(key);
+        if (it != g_spin.end()) { *out = it->second; return SHT_OK; }
+    }
     SpinPlan *sp = new SpinPlan();
     sp->device = dev;
     sp->L = L;
@@ -235,20 +254,52 @@ int get_spin_plan(int dev, int L, int spin, const DeviceState *ds, const Plan *p
     sp->wf32 = (float *)((double *)blk + 2 * n) + n + pad;
     SHT_HIP(launch_spin_tables(ds->E, plan->rec, *sp, st), "spin tables");
     SHT_HIP(hipStreamSynchronize(st), "spin plan sync");
+    std::lock_guard<std::mutex> lock(g_mu);
     g_spin[key] = sp;
     *out = sp;
     return SHT_OK;
 }
 
-int prepare(int L, int spin, hipStream_t st, DeviceState **ds, Plan **plan, SpinPlan **sp) {
+// the resident plans of (dev, L, spin), if all exist (g_mu held)
+bool find_ready(int dev, int L, int spin, DeviceState **ds, Plan **plan, SpinPlan **sp) {
+    auto d = g_devices.find(dev);
+    auto p = g_plans.find(std::make_tuple(dev, L));
+    auto q = g_spin.find(std::make_tuple(dev, L, spin));
+    if (d == g_devices.end() || p == g_plans.end() || q == g_spin.end()) return false;
+    *ds = &d->second;
+    *plan = p->second;
+    *sp = q->second;
+    return true;
+}
+
+// the library's build stream of the device (g_build_mu held)
+int build_stream(int dev, hipStream_t *out) {
+    auto it = g_build_streams.find(dev);
+    if (it == g_build_streams.end()) {
+        hipStream_t s = nullptr;
+        SHT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "plan build stream");
+        it = g_build_streams.emplace(dev, s).first;
+    }
+    *out = it->second;
+    return SHT_OK;
+}
+
+int prepare(int L, int spin, DeviceState **ds, Plan **plan, SpinPlan **sp) {
     int dev = 0;
     SHT_HIP(hipGetDevice(&dev), "hipGetDevice");
-    std::lock_guard<std::mutex> lock(g_mu);
-    int rc = get_device_state(dev, st, ds);
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        if (find_ready(dev, L, spin, ds, plan, sp)) return SHT_OK;
+    }
+    std::lock_guard<std::mutex> build(g_build_mu);
+    hipStream_t bs = nullptr;
+    int rc = build_stream(dev, &bs);
     if (rc != SHT_OK) return rc;
-    rc = get_plan(dev, L, st, plan);
+    rc = get_device_state(dev, bs, ds);
     if (rc != SHT_OK) return rc;
-    return get_spin_plan(dev, L, spin, *ds, *plan, st, sp);
+    rc = get_plan(dev, L, bs, plan);
+    if (rc != SHT_OK) return rc;
+    return get_spin_plan(dev, L, spin, *ds, *plan, bs, sp);
 }
 
 bool misaligned(const void *p, size_t a) { return ((uintptr_t)p) % a != 0; }
@@ -437,7 +488,7 @@ int transform_segs(bool inverse, bool real, int L, int nseg, const int *spins, c
     Seg seg[kMaxSegs];
     for (int k = 0; k < nseg; ++k) {
         SpinPlan *sp;
-        rc = prepare(L, spins[k], st, &ds, &plan, &sp);
+        rc = prepare(L, spins[k], &ds, &plan, &sp);
         if (rc != SHT_OK) return rc;
         seg[k] = Seg{spins[k], batches[k], sp, 0};
     }
@@ -490,14 +541,7 @@ int scratch_on(int dev, void **out) {
 // nothing is built here.
 int find_plans(int dev, int L, int spin, DeviceState **ds, Plan **plan, SpinPlan **sp) {
     std::lock_guard<std::mutex> lock(g_mu);
-    auto d = g_devices.find(dev);
-    auto p = g_plans.find(std::make_tuple(dev, L));
-    auto q = g_spin.find(std::make_tuple(dev, L, spin));
-    if (d == g_devices.end() || p == g_plans.end() || q == g_spin.end()) return SHT_ERR_NOT_READY;
-    *ds = &d->second;
-    *plan = p->second;
-    *sp = q->second;
-    return SHT_OK;
+    return find_ready(dev, L, spin, ds, plan, sp) ? SHT_OK : SHT_ERR_NOT_READY;
 }
 
 }  // namespace
@@ -581,7 +625,7 @@ int sht_forward_triangular(int L, int spin, int batch, int sampling, int precisi
     DeviceState *ds;
     Plan *plan;
     SpinPlan *sp;
-    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    rc = prepare(L, spin, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     size_t ra, rb;
     regions(L, batch, precision, ra, rb);
@@ -607,7 +651,7 @@ int sht_forward_lstsq(int L, int spin, int batch, int sampling, int precision, c
     DeviceState *ds;
     Plan *plan;
     SpinPlan *sp;
-    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    rc = prepare(L, spin, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     size_t ra, rb;
     regions(L, batch, precision, ra, rb);
@@ -642,7 +686,7 @@ int sht_plan_tables(int L, int spin, int precision, int enable, void *stream) {
     DeviceState *ds;
     Plan *plan;
     SpinPlan *sp;
-    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    rc = prepare(L, spin, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     std::lock_guard<std::mutex> lock(g_mu);
     const bool f64 = precision == SHT_FP64;
@@ -673,7 +717,7 @@ int sht_plan_warmup(int L, int spin, int sampling, int precision, void *stream) 
     DeviceState *ds;
     Plan *plan;
     SpinPlan *sp;
-    return prepare(L, spin, (hipStream_t)stream, &ds, &plan, &sp);
+    return prepare(L, spin, &ds, &plan, &sp);
 }
 
 size_t sht_error_workspace_bytes(void) { return error_workspace_bytes(); }
@@ -714,7 +758,7 @@ int sht_tune(int L, int spin, int batch, int precision, void *workspace, size_t 
     DeviceState *ds;
     Plan *plan;
     SpinPlan *sp;
-    rc = prepare(L, spin, st, &ds, &plan, &sp);
+    rc = prepare(L, spin, &ds, &plan, &sp);
     if (rc != SHT_OK) return rc;
     const int C = 4 * batch;
     const bool f64 = precision == SHT_FP64, bf = precision == SHT_BF16X3;
@@ -877,6 +921,7 @@ int sht_release_all(void) {
         }
         g_graphs.clear();
     }
+    std::lock_guard<std::mutex> build(g_build_mu);  // no build runs meanwhile
     std::lock_guard<std::mutex> lock(g_mu);
     int rc = SHT_OK;
     int cur = 0;
@@ -911,6 +956,11 @@ int sht_release_all(void) {
         if (hipFree(kv.second.E.expo) != hipSuccess) rc = SHT_ERR_HIP;
     }
     g_devices.clear();
+    for (auto &kv : g_build_streams) {
+        (void)hipSetDevice(kv.first);
+        if (hipStreamDestroy(kv.second) != hipSuccess) rc = SHT_ERR_HIP;
+    }
+    g_build_streams.clear();
     (void)hipSetDevice(cur);
     return rc;
 }
