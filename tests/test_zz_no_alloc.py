@@ -31,8 +31,9 @@ def test_noalloc_inverse_equals_inverse_on_two_calls(prec):
     from paper_0807_4494_amd import _native as N
     dev = torch.device("cuda", 0)
     dt = sht.io_dtype(prec)
-    # second call smaller than the first (fewer maps, lower band-limit)
-    for k, (L, s, B) in enumerate([(160, 2, 5), (48, -1, 2)]):
+    # each call smaller than the one before (fewer maps, lower band-limit);
+    # the last is spin 0 (parity-ordered panels and the parity kernel in FP32)
+    for k, (L, s, B) in enumerate([(160, 2, 5), (96, -1, 2), (64, 0, 1)]):
         print(f"[noalloc] call {k}: L={L} s={s} B={B} {prec}", flush=True)
         flm = np.stack([sht_synth.gaussian_flm(L, s, 7100 + 17 * k + b) for b in range(B)])
         x = torch.from_numpy(flm).to(dev, dt)
