@@ -24,7 +24,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("prec,L,s,B", [("fp32", 48, 1, 3), ("fp64", 33, -2, 2), ("bf16x3", 64, 0, 4),
-                                        ("fp32", 96, 2, 4)])
+                                        ("fp32", 96, 2, 4), ("fp32", 80, 0, 3)])
 def test_graph_replays_equal_eager(prec, L, s, B):
     sht = _sht()
     print(f"[graph] L={L} s={s} B={B} {prec}", flush=True)
