@@ -201,6 +201,7 @@ __global__ __launch_bounds__(kThreads<P>) void k_contract(Args<typename Prec<P>:
     // schedule, longest K loop first, so the short ones fill the tail; the
     // column block is blockIdx.y.
     const int code = a.sched[blockIdx.x];
+    if (code < 0) return;  // padding of the schedule
     const int mg = code >> 8, jt = code & 255, cb = (int)blockIdx.y;
     const int m0 = mg * GM, j0 = jt * TJ, c0 = a.c0[cb], cend = a.cend[cb], asg = a.asg[cb];
     const T *wtab = a.wtab[cb], *mtab = a.mtab[cb];
@@ -1247,8 +1248,20 @@ int build_contract_schedules(int L, RecTables &rt) {
                 }
             std::stable_sort(items.begin(), items.end(),
                              [](const std::pair<int, int> &x, const std::pair<int, int> &y) { return x.first > y.first; });
-            std::vector<int> codes(items.size());
-            for (size_t i = 0; i < items.size(); ++i) codes[i] = items[i].second;
+            // Workgroups go to the 8 XCDs round-robin (x mod 8).  Order group
+            // mg goes to XCD mg mod 8 with all its j tiles, which read the
+            // same panel rows, so those rows are fetched into one L2; each
+            // XCD's list stays longest first.  Interleaved entry 8i + k is
+            // the i-th of XCD k's list, padded with -1 (no work) to a
+            // multiple of 8, which keeps x mod 8 the XCD in every column block.
+            std::vector<int> per[8];
+            for (const auto &it : items) per[(it.second >> 8) & 7].push_back(it.second);
+            size_t n = 0;
+            for (int k = 0; k < 8; ++k) n = per[k].size() > n ? per[k].size() : n;
+            std::vector<int> codes(8 * n, -1);
+            for (size_t i = 0; i < n; ++i)
+                for (int k = 0; k < 8; ++k)
+                    if (i < per[k].size()) codes[8 * i + k] = per[k][i];
             if (hipMalloc(&rt.sched[mode][cls], codes.size() * sizeof(int)) != hipSuccess) return -1;
             if (hipMemcpy(rt.sched[mode][cls], codes.data(), codes.size() * sizeof(int), hipMemcpyHostToDevice) !=
                 hipSuccess)
