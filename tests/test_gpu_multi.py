@@ -40,6 +40,11 @@ SEGMENTS = [
     (257, [2, -2], [9, 9]),
     # L % 4 == 0: the 128-column tile's LDS-direct X loads; unpaired spin 0 after the pair
     (260, [-3, 3, 0], [12, 5, 4]),
+    # pairing rule: two (1, -1) pairs in a row; s, s, -s pairs the second s;
+    # two spin-0 segments (the parity kernel over both, no pairing)
+    (64, [1, -1, 1, -1], [2, 3, 1, 2]),
+    (48, [2, 2, -2], [1, 2, 3]),
+    (80, [0, 1, 0], [2, 1, 3]),
 ]
 
 
