@@ -368,6 +368,18 @@ hipError_t contract(int mode, bool bf16x3, int L, int nq, int nseg, const Seg *s
     return launch_contract<T>(mode, L, nseg, cs, X, Y, ds->E, rec, st);
 }
 
+// The layout kernels' segment table: the maps of segment k follow those of
+// the segments before it, in the caller's buffers and in the panel columns.
+LayoutSegs layout_segs(int nq, int nseg, const Seg *seg) {
+    LayoutSegs sg{};
+    sg.n = nseg;
+    for (int k = 0; k < nseg; ++k) {
+        sg.seg[k] = LayoutSeg{seg[k].spin, seg[k].B, sg.batch, nq * sg.batch, seg[k].flip};
+        sg.batch += seg[k].B;
+    }
+    return sg;
+}
+
 // real: spin-0 real maps; only the orders m >= 0 are carried (2 columns per
 // map, L theta rows), and the phi stages read / write real rings.
 // The layout and theta stages run per segment (their spin enters the
@@ -387,15 +399,9 @@ int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     const int nq = real ? 2 : 4, Cn = nq * batch;
     const size_t cb = 2 * sizeof(T);                           // bytes per complex
     const size_t ring = (size_t)L * ring_len(L, real);         // ring entries per map (theta stage output)
-    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
-        const void *f = (const unsigned char *)flm + (size_t)off * L * L * cb;
-        SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st,
-                       [&] {
-                           return launch_layout_in<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, f, P,
-                                                      st);
-                       }),
-                "layout_in");
-    }
+    const LayoutSegs lsg = layout_segs(nq, nseg, seg);
+    SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st, [&] { return launch_layout_in<T>(L, lsg, Cn, real, flm, P, st); }),
+            "layout_in");
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
                    [&] { return contract<T>(kInverse, bf16x3, L, nq, nseg, seg, P, R, ds, rec, st); }),
             "contract inverse");
@@ -453,15 +459,9 @@ int run_forward(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
                    [&] { return contract<T>(kForward, bf16x3, L, nq, nseg, seg, X, R, ds, rec, st); }),
             "contract forward");
-    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
-        void *f = (unsigned char *)flm + (size_t)off * L * L * cb;
-        SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st,
-                       [&] {
-                           return launch_layout_out<T>(L, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, R, f,
-                                                       st);
-                       }),
-                "layout_out");
-    }
+    const LayoutSegs lsg = layout_segs(nq, nseg, seg);
+    SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st, [&] { return launch_layout_out<T>(L, lsg, Cn, real, R, flm, st); }),
+            "layout_out");
     return SHT_OK;
 }
 

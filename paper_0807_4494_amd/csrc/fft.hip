@@ -223,11 +223,13 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
     constexpr int NP = (nb + nt - 1) / nt;               // butterflies per thread
     constexpr int logNs = LOGNS;
     constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
-    // w^{r k}, r < R, is contiguous in the table; for radix 16 only w^{k},
-    // w^{2k}, w^{4k}, w^{8k} are loaded and the rest formed as products of
-    // at most four table values (the loads, not the multiplies, limit these
-    // passes)
-    constexpr int NW = LOGNS == 0 ? 1 : R == 16 ? 4 : R;
+    // w^{r k} sits at ptw[r Ns + k], so a wave's threads (consecutive k)
+    // read one contiguous run per r.  For radix 16 only w^{k}, w^{2k},
+    // w^{4k}, w^{8k} are loaded and the rest formed as products of at most
+    // four table values (loading all fifteen was slower, in FP32 too)
+    constexpr bool ALLW = R != 16;
+    constexpr int Ns = 1 << LOGNS;
+    constexpr int NW = LOGNS == 0 ? 1 : ALLW ? R : 4;
     static_assert(!HIN || LOGNS == 0, "zero upper half only on the first pass");
     static_assert(!HOUT || LOGNS + LOGR == LOGM, "half output only on the last pass");
     C v[NP][R];
@@ -247,15 +249,15 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
                 for (int r = 0; r < RIN; ++r) v[q][r] = ld(j + r * nb);
             }
             if constexpr (LOGNS > 0) {
-                const C *wk = ptw + k * R;
-                if constexpr (R == 16) {
-                    w[q][0] = wk[1];
-                    w[q][1] = wk[2];
-                    w[q][2] = wk[4];
-                    w[q][3] = wk[8];
+                const C *wk = ptw + k;
+                if constexpr (!ALLW) {
+                    w[q][0] = wk[1 * Ns];
+                    w[q][1] = wk[2 * Ns];
+                    w[q][2] = wk[4 * Ns];
+                    w[q][3] = wk[8 * Ns];
                 } else {
 #pragma unroll
-                    for (int r = 1; r < R; ++r) w[q][r] = wk[r];
+                    for (int r = 1; r < R; ++r) w[q][r] = wk[r * Ns];
                 }
             }
 #pragma unroll
@@ -269,7 +271,7 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
         if (j < nb) {
             const int k = j & ((1 << logNs) - 1);
             if constexpr (LOGNS > 0) {
-                if constexpr (R == 16) {
+                if constexpr (!ALLW) {
                     C t[16];
                     t[1] = w[q][0];
                     t[2] = w[q][1];

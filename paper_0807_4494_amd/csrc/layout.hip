@@ -11,9 +11,13 @@
 //
 // Both kernels transpose 32 x 32 (l, m) tiles through LDS so that the
 // coefficient rows (contiguous in m) and the panels (contiguous in l) are
-// both accessed with unit stride.
+// both accessed with unit stride.  One launch covers every map of a call:
+// workgroup i takes map i / T and tile i mod T of the T tiles that meet the
+// triangle m <= l.  Each thread issues all its global loads before the first
+// use (indices clamped to a valid entry, the values selected afterwards), so
+// that a workgroup has its whole tile in flight at once.
 //
-// flip: the launch's maps (spin s) are contracted with the factors of spin
+// flip: the segment's maps (spin s) are contracted with the factors of spin
 // -s, d^l_{m',s}(pi/2) = (-1)^{l+m'} d^l_{m',-s}(pi/2) (Eq. (wignerd_sym6)):
 // their panels carry one more (-1)^l here, the theta stages the (-1)^{m'}.
 //
@@ -30,48 +34,76 @@ namespace sht {
 
 namespace {
 
-constexpr int TL = 32;  // tile edge
+constexpr int TL = 32;       // tile edge
+constexpr int NR = TL / 8;   // tile rows per thread (256 threads, 32 per row)
+
+__host__ __device__ constexpr int tri_count(int nt) { return nt * (nt + 1) / 2; }
+
+// Tile t of the lower triangle of 32 x 32 tiles, row by row: (lt, mt), mt <= lt.
+__device__ __forceinline__ void tri_tile(int t, int &lt, int &mt) {
+    int r = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+    while (tri_count(r + 1) <= t) ++r;
+    while (tri_count(r) > t) --r;
+    lt = r;
+    mt = t - tri_count(r);
+}
+
+// The segment holding map bg (workgroup-uniform).
+__device__ __forceinline__ LayoutSeg find_seg(const LayoutSegs &sg, int bg) {
+    int k = 0;
+    while (k + 1 < sg.n && bg >= sg.seg[k + 1].b0) ++k;
+    return sg.seg[k];
+}
 
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, int coff, int flip,
+__global__ __launch_bounds__(256) void k_layout_in(int L, int ntri, LayoutSegs sg, int Cn,
                                                   const typename CT<T>::type *__restrict__ flm, T *__restrict__ P) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][l_local][m_local]
-    const int l0 = blockIdx.x * TL, m0 = blockIdx.y * TL, b = blockIdx.z;
-    if (l0 + TL - 1 < m0) return;  // tile entirely above the diagonal (l < m)
-    const int as = s < 0 ? -s : s;
-    const C *fb = flm + (size_t)b * L * L;
+    const int bg = (int)blockIdx.x / ntri;
+    int lt, mt;
+    tri_tile((int)blockIdx.x - bg * ntri, lt, mt);
+    const int l0 = lt * TL, m0 = mt * TL;
+    const LayoutSeg g = find_seg(sg, bg);
+    const int s = g.s, as = s < 0 ? -s : s, b = bg - g.b0, flip = g.flip;
+    const C *fb = flm + (size_t)bg * L * L;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // read: x runs over m (contiguous in flm)
-    for (int li = ty; li < TL; li += 8) {
-        const int l = l0 + li, m = m0 + tx;
-        T v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-        if (l < L && m <= l && l >= as) {
-            const size_t base = (size_t)l * l + l;
-            const C p = fb[base + m];
-            const T sl = (flip && (l & 1)) ? T(-1) : T(1);
-            v0 = p.x * sl;
-            v1 = p.y * sl;
-            if (!HALF && m > 0) {
-                const C q = fb[base - m];
-                const T sg = ((l & 1) && !flip) ? T(-1) : T(1);
-                v2 = q.x * sg;
-                v3 = q.y * sg;
-            }
+    C vp[NR], vn[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int l = l0 + ty + 8 * i, m = m0 + tx;
+        const bool ok = l < L && m <= l && l >= as;
+        const size_t base = ok ? (size_t)l * l + l : 0;
+        const int mm = ok ? m : 0;
+        vp[i] = fb[base + mm];
+        if (!HALF) vn[i] = fb[base - mm];
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int li = ty + 8 * i, l = l0 + li, m = m0 + tx;
+        const bool ok = l < L && m <= l && l >= as;
+        const T sl = (flip && (l & 1)) ? T(-1) : T(1);
+        tile[0][li][tx] = ok ? vp[i].x * sl : T(0);
+        tile[1][li][tx] = ok ? vp[i].y * sl : T(0);
+        if (!HALF) {
+            const bool okn = ok && m > 0;
+            const T sn = ((l & 1) && !flip) ? T(-1) : T(1);
+            tile[2][li][tx] = okn ? vn[i].x * sn : T(0);
+            tile[3][li][tx] = okn ? vn[i].y * sn : T(0);
         }
-        tile[0][li][tx] = v0;
-        tile[1][li][tx] = v1;
-        tile[2][li][tx] = v2;
-        tile[3][li][tx] = v3;
     }
     __syncthreads();
     // write: x runs over l (contiguous in the panel)
     constexpr int NQ = HALF ? 2 : 4;
-    for (int mi = ty; mi < TL; mi += 8) {
-        const int m = m0 + mi, l = l0 + tx;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int mi = ty + 8 * i, m = m0 + mi, l = l0 + tx;
         if (m >= L || l >= L || l < m) continue;
         const int pl = (s == 0 && sizeof(T) == 4) ? par16_pos(l, L) : l;  // FP32 spin 0: parity blocks
-        for (int q = 0; q < NQ; ++q) P[((size_t)m * Cn + coff + (size_t)q * B + b) * L + pl] = tile[q][tx][mi];
+        T *row = P + ((size_t)m * Cn + g.coff + b) * L + pl;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) row[(size_t)q * g.B * L] = tile[q][tx][mi];
     }
 }
 
@@ -80,30 +112,43 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int s, int B, int Cn, 
 //   f_{l, m}  = (-1)^s i^{m+s}              (R0 + i R1)
 //   f_{l,-m}  = (-1)^s i^{s-m} (-1)^l       (R2 + i R3)      (m > 0)
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_out(int L, int s, int B, int Cn, int coff, int flip,
-                                                   const T *__restrict__ R, typename CT<T>::type *__restrict__ flm) {
+__global__ __launch_bounds__(256) void k_layout_out(int L, int ntri, LayoutSegs sg, int Cn, const T *__restrict__ R,
+                                                   typename CT<T>::type *__restrict__ flm) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][m_local][l_local]
-    const int l0 = blockIdx.x * TL, m0 = blockIdx.y * TL, b = blockIdx.z;
-    if (l0 + TL - 1 < m0) return;
-    const int as = s < 0 ? -s : s;
+    const int bg = (int)blockIdx.x / ntri;
+    int lt, mt;
+    tri_tile((int)blockIdx.x - bg * ntri, lt, mt);
+    const int l0 = lt * TL, m0 = mt * TL;
+    const LayoutSeg g = find_seg(sg, bg);
+    const int s = g.s, as = s < 0 ? -s : s, b = bg - g.b0, flip = g.flip;
     constexpr int NQ = HALF ? 2 : 4;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // read: x runs over l
-    for (int mi = ty; mi < TL; mi += 8) {
-        const int m = m0 + mi, l = l0 + tx;
-        T v[4] = {0, 0, 0, 0};
-        if (m < L && l < L && l >= m && l >= as) {
-            for (int q = 0; q < NQ; ++q) v[q] = R[((size_t)m * Cn + coff + (size_t)q * B + b) * L + l];
-        }
-        for (int q = 0; q < 4; ++q) tile[q][mi][tx] = v[q];
+    T v[NR][NQ];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int m = m0 + ty + 8 * i, l = l0 + tx;
+        const bool ok = m < L && l < L && l >= m && l >= as;
+        const size_t at = ok ? ((size_t)m * Cn + g.coff + b) * L + l : 0;
+        const size_t qs = ok ? (size_t)g.B * L : 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[i][q] = R[at + q * qs];
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int mi = ty + 8 * i, m = m0 + mi, l = l0 + tx;
+        const bool ok = m < L && l < L && l >= m && l >= as;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tile[q][mi][tx] = (ok && q < NQ) ? v[i][q < NQ ? q : 0] : T(0);
     }
     __syncthreads();
-    C *fb = flm + (size_t)b * L * L;
+    C *fb = flm + (size_t)bg * L * L;
     const T sgn_s = (s & 1) ? T(-1) : T(1);
     // write: x runs over m
-    for (int li = ty; li < TL; li += 8) {
-        const int l = l0 + li, m = m0 + tx;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int li = ty + 8 * i, l = l0 + li, m = m0 + tx;
         if (l >= L || m > l) continue;
         const size_t base = (size_t)l * l + l;
         const T sf = (flip && (l & 1)) ? -sgn_s : sgn_s;
@@ -171,30 +216,42 @@ hipError_t launch_spin_pair(int L, int s, int B, const void *in, void *out, hipS
 template hipError_t launch_spin_pair<double>(int, int, int, const void *, void *, hipStream_t);
 template hipError_t launch_spin_pair<float>(int, int, int, const void *, void *, hipStream_t);
 
+// Workgroups of a layout launch: T tiles per map, every map of the call.
+static bool layout_grid(int L, const LayoutSegs &sg, int &ntri, unsigned &nblk) {
+    const int nt = (L + TL - 1) / TL;
+    ntri = tri_count(nt);
+    const long long n = (long long)ntri * sg.batch;
+    if (sg.n < 1 || sg.n > SHT_MULTI_SEG_MAX || n < 1 || n > 0x7fffffffLL) return false;
+    nblk = (unsigned)n;
+    return true;
+}
+
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, int flip, bool half, const void *flm, T *P,
-                            hipStream_t st) {
-    dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
+hipError_t launch_layout_in(int L, const LayoutSegs &sg, int Cn, bool half, const void *flm, T *P, hipStream_t st) {
+    int ntri;
+    unsigned nblk;
+    if (!layout_grid(L, sg, ntri, nblk)) return hipErrorInvalidValue;
     const typename CT<T>::type *f = (const typename CT<T>::type *)flm;
-    if (half) hipLaunchKernelGGL((k_layout_in<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, f, P);
-    else hipLaunchKernelGGL((k_layout_in<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, f, P);
+    if (half) hipLaunchKernelGGL((k_layout_in<T, true>), dim3(nblk), dim3(256), 0, st, L, ntri, sg, Cn, f, P);
+    else hipLaunchKernelGGL((k_layout_in<T, false>), dim3(nblk), dim3(256), 0, st, L, ntri, sg, Cn, f, P);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, int flip, bool half, const T *R, void *flm,
-                             hipStream_t st) {
-    dim3 grid((L + TL - 1) / TL, (L + TL - 1) / TL, B);
+hipError_t launch_layout_out(int L, const LayoutSegs &sg, int Cn, bool half, const T *R, void *flm, hipStream_t st) {
+    int ntri;
+    unsigned nblk;
+    if (!layout_grid(L, sg, ntri, nblk)) return hipErrorInvalidValue;
     typename CT<T>::type *f = (typename CT<T>::type *)flm;
-    if (half) hipLaunchKernelGGL((k_layout_out<T, true>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, R, f);
-    else hipLaunchKernelGGL((k_layout_out<T, false>), grid, dim3(256), 0, st, L, s, B, Cn, coff, flip, R, f);
+    if (half) hipLaunchKernelGGL((k_layout_out<T, true>), dim3(nblk), dim3(256), 0, st, L, ntri, sg, Cn, R, f);
+    else hipLaunchKernelGGL((k_layout_out<T, false>), dim3(nblk), dim3(256), 0, st, L, ntri, sg, Cn, R, f);
     return hipGetLastError();
 }
 
-template hipError_t launch_layout_in<double>(int, int, int, int, int, int, bool, const void *, double *, hipStream_t);
-template hipError_t launch_layout_in<float>(int, int, int, int, int, int, bool, const void *, float *, hipStream_t);
-template hipError_t launch_layout_out<double>(int, int, int, int, int, int, bool, const double *, void *,
+template hipError_t launch_layout_in<double>(int, const LayoutSegs &, int, bool, const void *, double *, hipStream_t);
+template hipError_t launch_layout_in<float>(int, const LayoutSegs &, int, bool, const void *, float *, hipStream_t);
+template hipError_t launch_layout_out<double>(int, const LayoutSegs &, int, bool, const double *, void *,
                                               hipStream_t);
-template hipError_t launch_layout_out<float>(int, int, int, int, int, int, bool, const float *, void *, hipStream_t);
+template hipError_t launch_layout_out<float>(int, const LayoutSegs &, int, bool, const float *, void *, hipStream_t);
 
 }  // namespace sht

@@ -197,12 +197,12 @@ __global__ void k_fill_chirps(cplx64 *cha, cplx64 *chb, int N, int L) {
     chb[n] = cplx64{c, s};
 }
 
-// Twiddles of Stockham pass p: ptw[off + k R + r] = e^{-2 pi i r k / (Ns R)}.
+// Twiddles of Stockham pass p: ptw[off + r Ns + k] = e^{-2 pi i r k / (Ns R)}.
 __global__ void k_fill_pass_tw(cplx64 *ptw, int off, int logNs, int logR) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = 1 << (logNs + logR);
     if (i >= n) return;
-    const int k = i >> logR, r = i & ((1 << logR) - 1);
+    const int r = i >> logNs, k = i & ((1 << logNs) - 1);
     const long long num = ((long long)r * k) % n;
     double s, c;
     sincospi(-2.0 * (double)num / (double)n, &s, &c);

@@ -148,17 +148,23 @@ hipError_t launch_spin_tables(const EdgeTable &E, const RecTables &rt, SpinPlan 
 hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
-// layout.hip.  The panels have Cn columns per order; the B maps of one
-// launch (one spin) own columns coff + q*B + b.  flip: those maps are
-// contracted with the factors of spin -s (the layout stages then apply
-// (-1)^l, the theta stages (-1)^{m'}; Eq. (wignerd_sym6)).
+// layout.hip.  The panels have Cn columns per order.  One launch covers the
+// maps of every spin segment of a call: segment k holds the caller's maps
+// [b0, b0 + B) of spin s, which own columns coff + q*B + (b - b0).  flip:
+// those maps are contracted with the factors of spin -s (the layout stages
+// then apply (-1)^l, the theta stages (-1)^{m'}; Eq. (wignerd_sym6)).
 // half: real spin-0 signals, orders m >= 0 only (2 columns per map)
+struct LayoutSeg {
+    int s, B, b0, coff, flip;
+};
+struct LayoutSegs {
+    int n, batch;
+    LayoutSeg seg[SHT_MULTI_SEG_MAX];
+};
 template <typename T>
-hipError_t launch_layout_in(int L, int s, int B, int Cn, int coff, int flip, bool half, const void *flm, T *P,
-                            hipStream_t st);
+hipError_t launch_layout_in(int L, const LayoutSegs &sg, int Cn, bool half, const void *flm, T *P, hipStream_t st);
 template <typename T>
-hipError_t launch_layout_out(int L, int s, int B, int Cn, int coff, int flip, bool half, const T *R, void *flm,
-                             hipStream_t st);
+hipError_t launch_layout_out(int L, const LayoutSegs &sg, int Cn, bool half, const T *R, void *flm, hipStream_t st);
 
 // {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m}) for spin pairs f_{-s} = conj(f_s)
 template <typename T>
@@ -249,7 +255,8 @@ inline int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
 // Stockham pass structure of an M = 2^logM point FFT: pass 0 has radix
 // 2^(logM mod 4) when that is non-zero, every other pass radix 16.  Pass p
 // (p >= 1) keeps its twiddles w^{r k}, k < Ns_p, r < R_p, at
-// ptw[fft_pass_offset(logM, p) + k R_p + r].
+// ptw[fft_pass_offset(logM, p) + r Ns_p + k] (consecutive k adjacent: the
+// threads of a wave, which hold consecutive k, read one contiguous run).
 __host__ __device__ constexpr int fft_pass_lr(int logM, int p) { return (p == 0 && (logM & 3)) ? (logM & 3) : 4; }
 __host__ __device__ constexpr int fft_npass(int logM) { return (logM + 3) / 4; }
 __host__ __device__ constexpr int fft_pass_logns(int logM, int p) {
