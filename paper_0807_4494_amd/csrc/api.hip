@@ -368,13 +368,14 @@ hipError_t contract(int mode, bool bf16x3, int L, int nq, int nseg, const Seg *s
     return launch_contract<T>(mode, L, nseg, cs, X, Y, ds->E, rec, st);
 }
 
-// The layout kernels' segment table: the maps of segment k follow those of
-// the segments before it, in the caller's buffers and in the panel columns.
-LayoutSegs layout_segs(int nq, int nseg, const Seg *seg) {
-    LayoutSegs sg{};
+// The segment table of the layout and theta kernels: the maps of segment k
+// follow those of the segments before it, in the caller's buffers, the rings
+// and the panel columns.
+SpinSegs spin_segs(int nq, int nseg, const Seg *seg) {
+    SpinSegs sg{};
     sg.n = nseg;
     for (int k = 0; k < nseg; ++k) {
-        sg.seg[k] = LayoutSeg{seg[k].spin, seg[k].B, sg.batch, nq * sg.batch, seg[k].flip};
+        sg.seg[k] = SpinSeg{seg[k].spin, seg[k].B, sg.batch, nq * sg.batch, seg[k].flip};
         sg.batch += seg[k].B;
     }
     return sg;
@@ -382,9 +383,9 @@ LayoutSegs layout_segs(int nq, int nseg, const Seg *seg) {
 
 // real: spin-0 real maps; only the orders m >= 0 are carried (2 columns per
 // map, L theta rows), and the phi stages read / write real rings.
-// The layout and theta stages run per segment (their spin enters the
-// phases and the parity extension), the contraction and the phi stages once
-// over all maps.
+// Every stage runs once over all maps: the layout and theta kernels look up
+// each map's segment (its spin enters the phases and the parity extension),
+// the contraction takes one column range per segment or spin pair.
 template <typename T>
 int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const FftTables<T> &ft,
                 const RecTables &rec, const DeviceState *ds, const void *flm, void *map, void *ws, hipStream_t st) {
@@ -397,9 +398,7 @@ int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     T *R = (T *)(w + ra);     // region B: contraction output
     void *scr = w + ra + rb;  // split-row scratch (L > 2048, FP64)
     const int nq = real ? 2 : 4, Cn = nq * batch;
-    const size_t cb = 2 * sizeof(T);                           // bytes per complex
-    const size_t ring = (size_t)L * ring_len(L, real);         // ring entries per map (theta stage output)
-    const LayoutSegs lsg = layout_segs(nq, nseg, seg);
+    const SpinSegs lsg = spin_segs(nq, nseg, seg);
     SHT_HIP(traced(SHT_STAGE_LAYOUT_IN, st, [&] { return launch_layout_in<T>(L, lsg, Cn, real, flm, P, st); }),
             "layout_in");
     SHT_HIP(traced(SHT_STAGE_CONTRACT_INV, st,
@@ -407,15 +406,9 @@ int run_inverse(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
             "contract inverse");
     // theta stage writes g_mu(theta_t) straight into the rings over mu that
     // the phi stage reads (region A; the panels are no longer needed)
-    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
-        void *g = (unsigned char *)P + (size_t)off * ring * cb;
-        SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
-                       [&] {
-                           return launch_theta_inv<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, R, g,
-                                                      scr, st);
-                       }),
-                "theta inverse");
-    }
+    SHT_HIP(traced(SHT_STAGE_THETA_INV, st,
+                   [&] { return launch_theta_inv<T>(ft, lsg, Cn, real, R, P, scr, st); }),
+            "theta inverse");
     SHT_HIP(traced(SHT_STAGE_PHI_INV, st,
                    [&] {
                        return real ? launch_phi_inv_real<T>(ft, batch, (const void *)P, (T *)map, scr, st)
@@ -437,8 +430,6 @@ int run_forward(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
     T *X = (T *)w;                // region A: weighted theta coefficients
     void *scr = w + ra + rb;      // split-row scratch (L > 2048, FP64)
     const int nq = real ? 2 : 4, Cn = nq * batch;
-    const size_t cb = 2 * sizeof(T);
-    const size_t ring = (size_t)L * ring_len(L, real);
     SHT_HIP(traced(SHT_STAGE_PHI_FWD, st,
                    [&] {
                        return real ? launch_phi_fwd_real<T>(ft, batch, (const T *)map, Q, scr, st)
@@ -446,20 +437,14 @@ int run_forward(int L, int nseg, const Seg *seg, bool bf16x3, bool real, const F
                    }),
             "phi forward");
     // the theta stage reads its two orders as columns of the rings in place
-    for (int k = 0, off = 0; k < nseg; off += seg[k].B, ++k) {
-        const void *q = (const unsigned char *)Q + (size_t)off * ring * cb;
-        SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
-                       [&] {
-                           return launch_theta_fwd<T>(ft, seg[k].spin, seg[k].B, Cn, nq * off, seg[k].flip, real, q, X,
-                                                      scr, st);
-                       }),
-                "theta forward");
-    }
+    const SpinSegs lsg = spin_segs(nq, nseg, seg);
+    SHT_HIP(traced(SHT_STAGE_THETA_FWD, st,
+                   [&] { return launch_theta_fwd<T>(ft, lsg, Cn, real, Q, X, scr, st); }),
+            "theta forward");
     T *R = (T *)(w + ra);
     SHT_HIP(traced(SHT_STAGE_CONTRACT_FWD, st,
                    [&] { return contract<T>(kForward, bf16x3, L, nq, nseg, seg, X, R, ds, rec, st); }),
             "contract forward");
-    const LayoutSegs lsg = layout_segs(nq, nseg, seg);
     SHT_HIP(traced(SHT_STAGE_LAYOUT_OUT, st, [&] { return launch_layout_out<T>(L, lsg, Cn, real, R, flm, st); }),
             "layout_out");
     return SHT_OK;

@@ -480,8 +480,8 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N)
 // HALF (real spin-0 signals): only mu >= 0, from the 2-column panels, pairs
 // (2i, 2i+1), rings of L orders, ring-major G[b][t][.].
 template <typename T, int LOGM, bool HALF>
-__global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, int s, int B, int Cn, int coff,
-                                                           int flip, const T *__restrict__ R,
+__global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, SpinSegs sg, int Cn,
+                                                           const T *__restrict__ R,
                                                            typename CT<T>::type *__restrict__ G,
                                                            typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
@@ -489,19 +489,19 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
     const int npair = HALF ? (L + 1) / 2 : L;
-    for_items<split_rows<T, LOGM>()>(npair * B, [&](int item) {
-    const int pair = item % npair, b = item / npair;
-    const T sgn_s = (s & 1) ? T(-1) : T(1);
+    for_items<split_rows<T, LOGM>()>(npair * sg.batch, [&](int item) {
+    const int pair = item % npair, bg = item / npair;
+    const SpinSeg sgm = find_seg(sg, bg);
+    const int s = sgm.s, B = sgm.B, coff = sgm.coff, flip = sgm.flip, b = bg - sgm.b0;
     struct Row {
         const T *re, *im;
-        int phase, neg, odd;
+        int neg, odd;
     };
     auto row_of = [&](int mu) {
         const int m = mu < 0 ? -mu : mu, neg = mu < 0;
         Row r;
         r.re = R + ((size_t)m * Cn + coff + (size_t)(2 * neg) * B + b) * L;
         r.im = r.re + (size_t)B * L;
-        r.phase = -(mu + s);  // i^{-(mu+s)}
         r.neg = neg;
         r.odd = parity((long long)mu + s);
         return r;
@@ -519,10 +519,12 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     stage_row(sr + 2 * L, rb.re, L);
     stage_row(sr + 3 * L, rb.im, L);
     __syncthreads();
+    // The row factors (-1)^s i^{-(mu+s)} are left out of the transformed
+    // sum: the factor of mu + 1 is the factor of mu times -i, so the sum
+    // carries F_a + (-i) F_b and the factor of mu multiplies the outputs.
     auto coef = [&](const Row &r, const T *s2, int n) -> C {
         const int mp = n - h, amp = mp < 0 ? -mp : mp;
-        C F{s2[amp] * sgn_s, s2[L + amp] * sgn_s};
-        F = rot_ipow(F, r.phase);
+        const C F{s2[amp], s2[L + amp]};
         // (-1)^{m'} for mu < 0 and for factors of spin -s; sigma for m' < 0
         const int neg = ((r.neg ^ flip) && (amp & 1)) ^ (mp < 0 && r.odd);
         return neg ? C{-F.x, -F.y} : F;
@@ -530,8 +532,8 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
         const int nc = n < N ? n : N - 1;
-        const C Fa = coef(ra, sr, nc), Fb = coef(rb, sr + 2 * L, nc), c = cha[nc];
-        const C x = cmul(two ? cadd(Fa, Fb) : Fa, c);
+        const C Fa = coef(ra, sr, nc), c = cha[nc];
+        const C x = cmul(two ? cadd(Fa, mul_mi(coef(rb, sr + 2 * L, nc))) : Fa, c);
         return n < N ? x : C{T(0), T(0)};
     };
     // Z(theta_t), t < N, lands in LDS
@@ -544,14 +546,17 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, i
     // starts at an even column, so a pair is one aligned 16-byte piece)
     const int rl = ring_len(L, HALF);
     // ring-major (HALF): piece t at Ga + t rl; pair-major: at Ga + 2t
-    C *Ga = G + (size_t)b * L * rl + (HALF ? mua : (size_t)pair * rl);
+    C *Ga = G + (size_t)bg * L * rl + (HALF ? mua : (size_t)pair * rl);
     const size_t ts = HALF ? (size_t)rl : 2;
-    const T sa = ra.odd ? T(-0.5) : T(0.5);
+    // halves, with the row factor (-1)^s i^{-(mua+s)} of both rows
+    const T hf = (s & 1) ? T(-0.5) : T(0.5);
+    const T sa = ra.odd ? -hf : hf;
+    const int ph = -(mua + s);
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
         const C z = buf[pad(t)], zr = buf[pad(N - 1 - t)];
         C *g = Ga + (size_t)t * ts;
-        const C ga{T(0.5) * z.x + sa * zr.x, T(0.5) * z.y + sa * zr.y};
-        if (two) store_pair(g, ga, C{T(0.5) * z.x - sa * zr.x, T(0.5) * z.y - sa * zr.y});
+        const C ga = rot_ipow(C{hf * z.x + sa * zr.x, hf * z.y + sa * zr.y}, ph);
+        if (two) store_pair(g, ga, rot_ipow(C{hf * z.x - sa * zr.x, hf * z.y - sa * zr.y}, ph));
         else g[0] = ga;
     }
     });
@@ -655,23 +660,25 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int
 // HALF (real spin-0 signals): only mu >= 0, rings of L orders, pairs
 // (2i, 2i+1), 2-column panels.
 template <typename T, int LOGM, bool HALF>
-__global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, int s, int B, int Cn, int coff,
-                                                           int flip, const typename CT<T>::type *__restrict__ Q,
+__global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, SpinSegs sg, int Cn,
+                                                           const typename CT<T>::type *__restrict__ Q,
                                                            T *__restrict__ X, typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *buf = reinterpret_cast<C *>(smem_raw);
     const int L = ft.L, N = ft.N, h = L - 1;
     const int npair = HALF ? (L + 1) / 2 : L;
-    for_items<split_rows<T, LOGM>()>(npair * B, [&](int item) {
-    const int pair = item % npair, b = item / npair;
+    for_items<split_rows<T, LOGM>()>(npair * sg.batch, [&](int item) {
+    const int pair = item % npair, bg = item / npair;
+    const SpinSeg sgm = find_seg(sg, bg);
+    const int s = sgm.s, B = sgm.B, coff = sgm.coff, flip = sgm.flip, b = bg - sgm.b0;
     const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
     const int oddA = parity((long long)mua + s);
     // columns mu and mu+1 of the rings Q[b][t][.] (ring_len, even; mu at an
     // even column), t < L
     const int rl = ring_len(L, HALF);
-    const C *Qa = Q + (size_t)b * L * rl + (HALF ? mua : mua + h);
+    const C *Qa = Q + (size_t)bg * L * rl + (HALF ? mua : mua + h);
     const C *Qb = two ? Qa + 1 : Qa;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
@@ -953,9 +960,19 @@ template <typename F> hipError_t with_logm(int logM, F f) {
     }
 }
 
+// Rows of a theta launch over every map of a call (order pairs per map
+// times maps), or 0 when the table is malformed or the count overflows.
+static long long theta_rows(int L, bool half, const SpinSegs &sg) {
+    if (sg.n < 1 || sg.n > SHT_MULTI_SEG_MAX || sg.batch < 1) return 0;
+    const long long n = (long long)(half ? (L + 1) / 2 : L) * sg.batch;
+    return n <= 0x7fffffffLL ? n : 0;
+}
+
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half, const T *R,
-                            void *G, void *scr, hipStream_t st) {
+hipError_t launch_theta_inv(const FftTables<T> &ft, const SpinSegs &sg, int Cn, bool half, const T *R, void *G,
+                            void *scr, hipStream_t st) {
+    const long long rows = theta_rows(ft.L, half, sg);
+    if (rows == 0) return hipErrorInvalidValue;
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
@@ -963,13 +980,13 @@ hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int co
         if (half) {
             hipError_t e = set_lds(k_theta_inv<T, LM, true>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_inv<T, LM, true>), row_grid(ft, (ft.L + 1) / 2 * B), dim3(row_threads(ft.M)),
-                               lds, st, ft, s, B, Cn, coff, flip, R, g, w);
+            hipLaunchKernelGGL((k_theta_inv<T, LM, true>), row_grid(ft, (int)rows), dim3(row_threads(ft.M)), lds, st,
+                               ft, sg, Cn, R, g, w);
         } else {
             hipError_t e = set_lds(k_theta_inv<T, LM, false>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_inv<T, LM, false>), row_grid(ft, ft.L * B), dim3(row_threads(ft.M)), lds, st,
-                               ft, s, B, Cn, coff, flip, R, g, w);
+            hipLaunchKernelGGL((k_theta_inv<T, LM, false>), row_grid(ft, (int)rows), dim3(row_threads(ft.M)), lds, st,
+                               ft, sg, Cn, R, g, w);
         }
         return hipGetLastError();
     });
@@ -1006,8 +1023,10 @@ hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, int rs, const void *map
 }
 
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half,
-                            const void *Q, T *X, void *scr, hipStream_t st) {
+hipError_t launch_theta_fwd(const FftTables<T> &ft, const SpinSegs &sg, int Cn, bool half, const void *Q, T *X,
+                            void *scr, hipStream_t st) {
+    const long long rows = theta_rows(ft.L, half, sg);
+    if (rows == 0) return hipErrorInvalidValue;
     return with_logm(ft.logM, [&](auto lm) {
         constexpr int LM = decltype(lm)::value;
         const size_t lds = lds_bytes(ft);
@@ -1016,13 +1035,13 @@ hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int co
         if (half) {
             hipError_t e = set_lds(k_theta_fwd<T, LM, true>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_fwd<T, LM, true>), row_grid(ft, (ft.L + 1) / 2 * B), dim3(row_threads(ft.M)),
-                               lds, st, ft, s, B, Cn, coff, flip, q, X, w);
+            hipLaunchKernelGGL((k_theta_fwd<T, LM, true>), row_grid(ft, (int)rows), dim3(row_threads(ft.M)), lds, st,
+                               ft, sg, Cn, q, X, w);
         } else {
             hipError_t e = set_lds(k_theta_fwd<T, LM, false>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_theta_fwd<T, LM, false>), row_grid(ft, ft.L * B), dim3(row_threads(ft.M)), lds, st,
-                               ft, s, B, Cn, coff, flip, q, X, w);
+            hipLaunchKernelGGL((k_theta_fwd<T, LM, false>), row_grid(ft, (int)rows), dim3(row_threads(ft.M)), lds, st,
+                               ft, sg, Cn, q, X, w);
         }
         return hipGetLastError();
     });
@@ -1116,7 +1135,7 @@ template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft) {
 }
 
 #define SHT_INST(T)                                                                                      \
-    template hipError_t launch_theta_inv<T>(const FftTables<T> &, int, int, int, int, int, bool, const T *,  \
+    template hipError_t launch_theta_inv<T>(const FftTables<T> &, const SpinSegs &, int, bool, const T *,     \
                                             void *, void *, hipStream_t);                                \
     template hipError_t launch_phi_inv_real<T>(const FftTables<T> &, int, const void *, T *, void *, hipStream_t); \
     template hipError_t launch_phi_fwd_real<T>(const FftTables<T> &, int, const T *, void *, void *, hipStream_t); \
@@ -1125,7 +1144,7 @@ template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft) {
     template hipError_t launch_phi_fwd<T>(const FftTables<T> &, int, int, const void *, void *, void *,    \
                                           hipStream_t);                                                  \
     template hipError_t launch_theta_dft<T>(const FftTables<T> &, int, int, const void *, void *, hipStream_t); \
-    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, int, int, int, int, int, bool, const void *, \
+    template hipError_t launch_theta_fwd<T>(const FftTables<T> &, const SpinSegs &, int, bool, const void *,  \
                                             T *, void *, hipStream_t);                                   \
     template size_t split_scratch_bytes<T>(const FftTables<T> &);                                        \
     template hipError_t launch_transpose<T>(int, int, int, const void *, void *, hipStream_t);                \

@@ -48,15 +48,8 @@ __device__ __forceinline__ void tri_tile(int t, int &lt, int &mt) {
     mt = t - tri_count(r);
 }
 
-// The segment holding map bg (workgroup-uniform).
-__device__ __forceinline__ LayoutSeg find_seg(const LayoutSegs &sg, int bg) {
-    int k = 0;
-    while (k + 1 < sg.n && bg >= sg.seg[k + 1].b0) ++k;
-    return sg.seg[k];
-}
-
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_in(int L, int ntri, LayoutSegs sg, int Cn,
+__global__ __launch_bounds__(256) void k_layout_in(int L, int ntri, SpinSegs sg, int Cn,
                                                   const typename CT<T>::type *__restrict__ flm, T *__restrict__ P) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][l_local][m_local]
@@ -64,7 +57,7 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int ntri, LayoutSegs s
     int lt, mt;
     tri_tile((int)blockIdx.x - bg * ntri, lt, mt);
     const int l0 = lt * TL, m0 = mt * TL;
-    const LayoutSeg g = find_seg(sg, bg);
+    const SpinSeg g = find_seg(sg, bg);
     const int s = g.s, as = s < 0 ? -s : s, b = bg - g.b0, flip = g.flip;
     const C *fb = flm + (size_t)bg * L * L;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -112,7 +105,7 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int ntri, LayoutSegs s
 //   f_{l, m}  = (-1)^s i^{m+s}              (R0 + i R1)
 //   f_{l,-m}  = (-1)^s i^{s-m} (-1)^l       (R2 + i R3)      (m > 0)
 template <typename T, bool HALF>
-__global__ __launch_bounds__(256) void k_layout_out(int L, int ntri, LayoutSegs sg, int Cn, const T *__restrict__ R,
+__global__ __launch_bounds__(256) void k_layout_out(int L, int ntri, SpinSegs sg, int Cn, const T *__restrict__ R,
                                                    typename CT<T>::type *__restrict__ flm) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][m_local][l_local]
@@ -120,7 +113,7 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int ntri, LayoutSegs 
     int lt, mt;
     tri_tile((int)blockIdx.x - bg * ntri, lt, mt);
     const int l0 = lt * TL, m0 = mt * TL;
-    const LayoutSeg g = find_seg(sg, bg);
+    const SpinSeg g = find_seg(sg, bg);
     const int s = g.s, as = s < 0 ? -s : s, b = bg - g.b0, flip = g.flip;
     constexpr int NQ = HALF ? 2 : 4;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -217,7 +210,7 @@ template hipError_t launch_spin_pair<double>(int, int, int, const void *, void *
 template hipError_t launch_spin_pair<float>(int, int, int, const void *, void *, hipStream_t);
 
 // Workgroups of a layout launch: T tiles per map, every map of the call.
-static bool layout_grid(int L, const LayoutSegs &sg, int &ntri, unsigned &nblk) {
+static bool layout_grid(int L, const SpinSegs &sg, int &ntri, unsigned &nblk) {
     const int nt = (L + TL - 1) / TL;
     ntri = tri_count(nt);
     const long long n = (long long)ntri * sg.batch;
@@ -227,7 +220,7 @@ static bool layout_grid(int L, const LayoutSegs &sg, int &ntri, unsigned &nblk) 
 }
 
 template <typename T>
-hipError_t launch_layout_in(int L, const LayoutSegs &sg, int Cn, bool half, const void *flm, T *P, hipStream_t st) {
+hipError_t launch_layout_in(int L, const SpinSegs &sg, int Cn, bool half, const void *flm, T *P, hipStream_t st) {
     int ntri;
     unsigned nblk;
     if (!layout_grid(L, sg, ntri, nblk)) return hipErrorInvalidValue;
@@ -238,7 +231,7 @@ hipError_t launch_layout_in(int L, const LayoutSegs &sg, int Cn, bool half, cons
 }
 
 template <typename T>
-hipError_t launch_layout_out(int L, const LayoutSegs &sg, int Cn, bool half, const T *R, void *flm, hipStream_t st) {
+hipError_t launch_layout_out(int L, const SpinSegs &sg, int Cn, bool half, const T *R, void *flm, hipStream_t st) {
     int ntri;
     unsigned nblk;
     if (!layout_grid(L, sg, ntri, nblk)) return hipErrorInvalidValue;
@@ -248,10 +241,10 @@ hipError_t launch_layout_out(int L, const LayoutSegs &sg, int Cn, bool half, con
     return hipGetLastError();
 }
 
-template hipError_t launch_layout_in<double>(int, const LayoutSegs &, int, bool, const void *, double *, hipStream_t);
-template hipError_t launch_layout_in<float>(int, const LayoutSegs &, int, bool, const void *, float *, hipStream_t);
-template hipError_t launch_layout_out<double>(int, const LayoutSegs &, int, bool, const double *, void *,
+template hipError_t launch_layout_in<double>(int, const SpinSegs &, int, bool, const void *, double *, hipStream_t);
+template hipError_t launch_layout_in<float>(int, const SpinSegs &, int, bool, const void *, float *, hipStream_t);
+template hipError_t launch_layout_out<double>(int, const SpinSegs &, int, bool, const double *, void *,
                                               hipStream_t);
-template hipError_t launch_layout_out<float>(int, const LayoutSegs &, int, bool, const float *, void *, hipStream_t);
+template hipError_t launch_layout_out<float>(int, const SpinSegs &, int, bool, const float *, void *, hipStream_t);
 
 }  // namespace sht

@@ -148,23 +148,32 @@ hipError_t launch_spin_tables(const EdgeTable &E, const RecTables &rt, SpinPlan 
 hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
-// layout.hip.  The panels have Cn columns per order.  One launch covers the
-// maps of every spin segment of a call: segment k holds the caller's maps
-// [b0, b0 + B) of spin s, which own columns coff + q*B + (b - b0).  flip:
-// those maps are contracted with the factors of spin -s (the layout stages
-// then apply (-1)^l, the theta stages (-1)^{m'}; Eq. (wignerd_sym6)).
-// half: real spin-0 signals, orders m >= 0 only (2 columns per map)
-struct LayoutSeg {
+// The spin segments of one call, as the layout and theta kernels see them:
+// segment k holds the caller's maps [b0, b0 + B) of spin s (their rings and
+// coefficient arrays follow those of the segments before), and those maps
+// own the panel columns coff + q*B + (b - b0) of Cn.  flip: the segment's
+// maps are contracted with the factors of spin -s (the layout stages then
+// apply (-1)^l, the theta stages (-1)^{m'}; Eq. (wignerd_sym6)).
+struct SpinSeg {
     int s, B, b0, coff, flip;
 };
-struct LayoutSegs {
+struct SpinSegs {
     int n, batch;
-    LayoutSeg seg[SHT_MULTI_SEG_MAX];
+    SpinSeg seg[SHT_MULTI_SEG_MAX];
 };
+// The segment holding map bg (uniform over a workgroup).
+__device__ __forceinline__ SpinSeg find_seg(const SpinSegs &sg, int bg) {
+    int k = 0;
+    while (k + 1 < sg.n && bg >= sg.seg[k + 1].b0) ++k;
+    return sg.seg[k];
+}
+
+// layout.hip: one launch over every map of a call.  half: real spin-0
+// signals, orders m >= 0 only (2 columns per map)
 template <typename T>
-hipError_t launch_layout_in(int L, const LayoutSegs &sg, int Cn, bool half, const void *flm, T *P, hipStream_t st);
+hipError_t launch_layout_in(int L, const SpinSegs &sg, int Cn, bool half, const void *flm, T *P, hipStream_t st);
 template <typename T>
-hipError_t launch_layout_out(int L, const LayoutSegs &sg, int Cn, bool half, const T *R, void *flm, hipStream_t st);
+hipError_t launch_layout_out(int L, const SpinSegs &sg, int Cn, bool half, const T *R, void *flm, hipStream_t st);
 
 // {}_{-s}f_{lm} = (-1)^{s+m} conj({}_s f_{l,-m}) for spin pairs f_{-s} = conj(f_s)
 template <typename T>
@@ -173,11 +182,11 @@ hipError_t launch_spin_pair(int L, int s, int B, const void *in, void *out, hipS
 // fft.hip: row transforms.  scr: split-row scratch of split_scratch_bytes(ft)
 // bytes (unused, may be NULL, when that is 0)
 template <typename T> size_t split_scratch_bytes(const FftTables<T> &ft);
-// The theta stages of B maps of one spin whose contraction columns are
-// coff + q*B + b of Cn; G / Q point at the first of those maps' rings.
+// The theta stages of every map of a call (one launch); G / Q point at the
+// first map's rings.
 template <typename T>
-hipError_t launch_theta_inv(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half, const T *R,
-                            void *G, void *scr, hipStream_t st);
+hipError_t launch_theta_inv(const FftTables<T> &ft, const SpinSegs &sg, int Cn, bool half, const T *R, void *G,
+                            void *scr, hipStream_t st);
 // rs: row stride of the rings G / Q (ring_len(L, false), or N for the
 // triangular forward's rows)
 template <typename T>
@@ -187,8 +196,8 @@ template <typename T>
 hipError_t launch_phi_fwd(const FftTables<T> &ft, int B, int rs, const void *map, void *Q, void *scr,
                           hipStream_t st);
 template <typename T>
-hipError_t launch_theta_fwd(const FftTables<T> &ft, int s, int B, int Cn, int coff, int flip, bool half,
-                            const void *Q, T *X, void *scr, hipStream_t st);
+hipError_t launch_theta_fwd(const FftTables<T> &ft, const SpinSegs &sg, int Cn, bool half, const void *Q, T *X,
+                            void *scr, hipStream_t st);
 // real maps (spin 0): phi synthesis from orders m >= 0, phi analysis keeping m >= 0
 template <typename T>
 hipError_t launch_phi_inv_real(const FftTables<T> &ft, int B, const void *G, T *map, void *scr, hipStream_t st);
