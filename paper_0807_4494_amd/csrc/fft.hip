@@ -682,29 +682,31 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, S
     const C *Qb = two ? Qa + 1 : Qa;
     const C *cha = ft.cha, *chb = ft.chb;
     const T invN = T(1) / T(N);
-    // the two columns staged in LDS, one aligned 16-byte piece per ring
-    // (each ring read once; the extension reads them back mirrored)
-    C *sa = buf, *sb = buf + L;
+    // the two columns staged in LDS by parity, one aligned 16-byte piece per
+    // ring (each ring read once; the extension reads them back mirrored):
+    // se the even row, so the odd one, whose theta = pi sample (t = L-1) is
+    // left out of the extension and stored as zero; a missing second row
+    // (the last block of a map) is zero
+    C *se = buf, *so = buf + L;
+    const C zero{T(0), T(0)};
     for (int t = threadIdx.x; t < L; t += blockDim.x) {
-        C xa, xb;
+        C xa, xb = zero;
         if (two) load_pair(Qa + (size_t)t * rl, xa, xb);
-        else xa = xb = Qa[(size_t)t * rl];
-        sa[t] = xa;
-        sb[t] = xb;
+        else xa = Qa[(size_t)t * rl];
+        const C xo = oddA ? xa : xb;
+        se[t] = oddA ? xb : xa;
+        so[t] = t == h ? zero : xo;
     }
     __syncthreads();
-    // extension of one row at n < N; the theta = pi sample (t = L-1) of an
-    // odd row is left out
-    auto ext = [&](const C *Qr, int odd, int n) -> C {
-        const C x = Qr[n < L ? n : 2 * L - 2 - n];
-        if (odd && n == h) return C{T(0), T(0)};
-        return (odd && n >= L) ? C{-x.x, -x.y} : x;
-    };
+    // the extended sum at n < N: even + odd below L, even - odd mirrored
     auto ld = [&](int n) -> C {
         const int nc = n < N ? n : N - 1;
-        const C xa = ext(sa, oddA, nc), xb = ext(sb, !oddA, nc), c = chb[nc];
-        const C x = cmulc(two ? cadd(xa, xb) : xa, c);
-        return n < N ? x : C{T(0), T(0)};
+        const bool lo = nc < L;
+        const int i = lo ? nc : 2 * L - 2 - nc;
+        const C xe = se[i], xo = so[i], c = chb[nc];
+        const T sg = lo ? T(1) : T(-1);
+        const C x = cmulc(C{xe.x + sg * xo.x, xe.y + sg * xo.y}, c);
+        return n < N ? x : zero;
     };
     // the theta DFT lands in LDS (zero from N to M/2) as the input of the correlation
     auto pre = [&](int k) { return ldc(cha, k, N); };
