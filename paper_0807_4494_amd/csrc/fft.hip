@@ -422,20 +422,6 @@ template <bool SPLIT, typename F> __device__ __forceinline__ void for_items(int 
     }
 }
 
-// dst[i] = src[i] for i < n, with 16-byte loads and stores when n allows
-// (src and dst 16-byte aligned then: rows of n values from aligned bases).
-template <typename T> __device__ __forceinline__ void stage_row(T *dst, const T *src, int n) {
-    constexpr int V = 16 / (int)sizeof(T);
-    if (n % V == 0) {
-        typedef T vec __attribute__((ext_vector_type(V)));
-        const vec *s = reinterpret_cast<const vec *>(src);
-        vec *d = reinterpret_cast<vec *>(dst);
-        for (int i = threadIdx.x; i < n / V; i += blockDim.x) d[i] = s[i];
-    } else {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-    }
-}
-
 // The two adjacent complex values g[0], g[1] as one aligned piece (16 bytes
 // for complex float; two 16-byte stores for complex double).
 __device__ __forceinline__ void store_pair(cplx32 *g, cplx32 a, cplx32 b) {
@@ -509,32 +495,51 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, S
     const int mua = HALF ? 2 * pair : 2 * pair - h;
     const bool two = mua < h;
     const Row ra = row_of(mua), rb = row_of(two ? mua + 1 : mua);
-    // the four contraction rows (re, im of both orders, m' = 0..L-1) staged
-    // in LDS with 16-byte loads, each read once; the fill of m' < 0 below
-    // reads them back mirrored (the FFT's first pass only overwrites the
-    // buffer after its loads)
-    T *sr = reinterpret_cast<T *>(buf);
-    stage_row(sr, ra.re, L);
-    stage_row(sr + L, ra.im, L);
-    stage_row(sr + 2 * L, rb.re, L);
-    stage_row(sr + 3 * L, rb.im, L);
-    __syncthreads();
     // The row factors (-1)^s i^{-(mu+s)} are left out of the transformed
     // sum: the factor of mu + 1 is the factor of mu times -i, so the sum
     // carries F_a + (-i) F_b and the factor of mu multiplies the outputs.
-    auto coef = [&](const Row &r, const T *s2, int n) -> C {
-        const int mp = n - h, amp = mp < 0 ? -mp : mp;
-        const C F{s2[amp], s2[L + amp]};
-        // (-1)^{m'} for mu < 0 and for factors of spin -s; sigma for m' < 0
-        const int neg = ((r.neg ^ flip) && (amp & 1)) ^ (mp < 0 && r.odd);
-        return neg ? C{-F.x, -F.y} : F;
-    };
+    // Both contraction rows (m' = 0..L-1) are staged in LDS as complex
+    // values, each read once (16-byte loads where the row length allows),
+    // with (-1)^{m'} applied for mu < 0 and for factors of spin -s, and row b
+    // times -i; a missing second row is zero.  The fill of m' < 0 reads them
+    // back mirrored (the FFT's first pass only overwrites the buffer after
+    // its loads).
+    C *Fa = buf, *Fb = buf + L;
+    const C zero{T(0), T(0)};
+    {
+        constexpr int V = 16 / (int)sizeof(T);
+        typedef T vec __attribute__((ext_vector_type(V)));
+        const bool alta = ra.neg ^ flip, altb = rb.neg ^ flip;
+        auto put = [&](int m, T are, T aim, T bre, T bim) {
+            const T ga = (alta && (m & 1)) ? T(-1) : T(1), gb = (altb && (m & 1)) ? T(-1) : T(1);
+            Fa[m] = C{ga * are, ga * aim};
+            Fb[m] = two ? C{gb * bim, -gb * bre} : zero;  // (-i) (bre + i bim)
+        };
+        if (L % V == 0) {
+            for (int i = threadIdx.x; i < L / V; i += blockDim.x) {
+                const vec are = reinterpret_cast<const vec *>(ra.re)[i], aim = reinterpret_cast<const vec *>(ra.im)[i];
+                const vec bre = reinterpret_cast<const vec *>(rb.re)[i], bim = reinterpret_cast<const vec *>(rb.im)[i];
+#pragma unroll
+                for (int e = 0; e < V; ++e) put(i * V + e, are[e], aim[e], bre[e], bim[e]);
+            }
+        } else {
+            for (int m = threadIdx.x; m < L; m += blockDim.x) put(m, ra.re[m], ra.im[m], rb.re[m], rb.im[m]);
+        }
+    }
+    __syncthreads();
+    // sigma of the two rows for m' < 0: they have opposite parity, so the
+    // mirrored half carries sigma_a (F_a - (-i) F_b)
+    const T siga = ra.odd ? T(-1) : T(1);
     const C *cha = ft.cha, *chb = ft.chb;
     auto ld = [&](int n) -> C {
         const int nc = n < N ? n : N - 1;
-        const C Fa = coef(ra, sr, nc), c = cha[nc];
-        const C x = cmul(two ? cadd(Fa, mul_mi(coef(rb, sr + 2 * L, nc))) : Fa, c);
-        return n < N ? x : C{T(0), T(0)};
+        const int mp = nc - h;
+        const bool lo = mp >= 0;
+        const int amp = lo ? mp : -mp;
+        const C u = Fa[amp], v = Fb[amp], c = cha[nc];
+        const T sv = lo ? T(1) : T(-1), su = lo ? T(1) : siga;
+        const C x = cmul(C{su * (u.x + sv * v.x), su * (u.y + sv * v.y)}, c);
+        return n < N ? x : zero;
     };
     // Z(theta_t), t < N, lands in LDS
     auto pre = [&](int t) { return ldc(chb, t, N); };
