@@ -39,6 +39,20 @@ template <typename T, int LOGM> __host__ __device__ constexpr bool split_rows() 
     return rows_split(1 << LOGM, 2 * (int)sizeof(T));
 }
 
+// Waves per SIMD that a row kernel's LDS buffer admits (workgroups per CU of
+// 160 KB, row_threads(M) / 64 waves each), between 2 and 4: the kernels are
+// compiled to that occupancy (at most 512 / waves registers per lane), so
+// the compiler does not trade it for registers.
+template <typename T, int LOGM> constexpr int row_waves() {
+    constexpr int M = 1 << LOGM;
+    constexpr int m = split_rows<T, LOGM>() ? M / 2 : M;
+    constexpr int lds = (m + m / 16) * 2 * (int)sizeof(T);
+    constexpr int w = (160 * 1024 / lds) * (row_threads(M) / 64) / 4;
+    return w < 2 ? 2 : w > 4 ? 4 : w;
+}
+#define SHT_ROW_KERNEL(T, LOGM) \
+    __global__ __launch_bounds__(kMaxRowThreads) __attribute__((amdgpu_waves_per_eu(row_waves<T, LOGM>())))
+
 // Workgroups are dealt to the 8 XCDs round-robin; this maps workgroup i to
 // the work item it takes so that each XCD runs one contiguous range of items
 // in order (the tail n mod 8 keeps its own index).  Neighbouring items share
@@ -221,6 +235,12 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
     constexpr int nb = M >> LOGR;
     constexpr int nt = row_threads(M);                  // threads per row
     constexpr int NP = (nb + nt - 1) / nt;               // butterflies per thread
+    // every row kernel runs with row_threads(M) threads (M/2-point halves
+    // of split rows too: both counts are kMaxRowThreads there), so with one
+    // butterfly per thread and nt of them the butterfly exists and its
+    // compute phase needs no guard (the load phase keeps it: without it the
+    // compiler hoists loads across passes until the kernel spills)
+    constexpr bool FULL = nb == nt;
     constexpr int logNs = LOGNS;
     constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
     // w^{r k} sits at ptw[r Ns + k], so a wave's threads (consecutive k)
@@ -268,7 +288,7 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         const int j = threadIdx.x + q * nt;
-        if (j < nb) {
+        if (FULL || j < nb) {
             const int k = j & ((1 << logNs) - 1);
             if constexpr (LOGNS > 0) {
                 if constexpr (!ALLW) {
@@ -466,7 +486,7 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N)
 // HALF (real spin-0 signals): only mu >= 0, from the 2-column panels, pairs
 // (2i, 2i+1), rings of L orders, ring-major G[b][t][.].
 template <typename T, int LOGM, bool HALF>
-__global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, SpinSegs sg, int Cn,
+SHT_ROW_KERNEL(T, LOGM) void k_theta_inv(FftTables<T> ft, SpinSegs sg, int Cn,
                                                            const T *__restrict__ R,
                                                            typename CT<T>::type *__restrict__ G,
                                                            typename CT<T>::type *scr) {
@@ -571,7 +591,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_inv(FftTables<T> ft, S
 // g_mu(theta_t) from the theta stage's pair-major rings: column n of ring t of
 // map b at G[b][n / 2][t][n % 2] (rs = 2L values per pair, L rings per map).
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int rows, int rs,
+SHT_ROW_KERNEL(T, LOGM) void k_phi_inv(FftTables<T> ft, int rows, int rs,
                                                          const typename CT<T>::type *__restrict__ G,
                                                          typename CT<T>::type *__restrict__ map,
                                                          typename CT<T>::type *scr) {
@@ -611,7 +631,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv(FftTables<T> ft, int
 
 // Forward phi stage.  Row (b, t): Q_mu(t) = N^-1 sum_p f(theta_t, phi_p) e^{-i mu phi_p}.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int rows, int rs,
+SHT_ROW_KERNEL(T, LOGM) void k_phi_fwd(FftTables<T> ft, int rows, int rs,
                                                          const typename CT<T>::type *__restrict__ map,
                                                          typename CT<T>::type *__restrict__ Q,
                                                          typename CT<T>::type *scr) {
@@ -665,7 +685,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd(FftTables<T> ft, int
 // HALF (real spin-0 signals): only mu >= 0, rings of L orders, pairs
 // (2i, 2i+1), 2-column panels.
 template <typename T, int LOGM, bool HALF>
-__global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, SpinSegs sg, int Cn,
+SHT_ROW_KERNEL(T, LOGM) void k_theta_fwd(FftTables<T> ft, SpinSegs sg, int Cn,
                                                            const typename CT<T>::type *__restrict__ Q,
                                                            T *__restrict__ X, typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
@@ -759,7 +779,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_theta_fwd(FftTables<T> ft, S
 // spectrum g_r + i g_{r+1} gives ring r in the real part and ring r+1 in the
 // imaginary part of one synthesis.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft, int rows,
+SHT_ROW_KERNEL(T, LOGM) void k_phi_inv_real(FftTables<T> ft, int rows,
                                                               const typename CT<T>::type *__restrict__ G,
                                                               T *__restrict__ map, typename CT<T>::type *scr) {
     using C = typename CT<T>::type;
@@ -803,7 +823,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_inv_real(FftTables<T> ft
 //   Q_r(m) = (Z_m + conj(Z_{-m})) / 2,  Q_{r+1}(m) = (Z_m - conj(Z_{-m})) / (2i),
 // with Q(m) = N^-1 sum_p x(phi_p) e^{-i m phi_p}.  Output Q[r][m], m < L.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft, int rows,
+SHT_ROW_KERNEL(T, LOGM) void k_phi_fwd_real(FftTables<T> ft, int rows,
                                                               const T *__restrict__ map,
                                                               typename CT<T>::type *__restrict__ Q,
                                                               typename CT<T>::type *scr) {
@@ -848,7 +868,7 @@ __global__ __launch_bounds__(kMaxRowThreads) void k_phi_fwd_real(FftTables<T> ft
 // is) and F_{mu m'} = N^-1 sum_t Q~_mu(t) e^{-i m' theta_t} for m' in [0, L),
 // written to F[b][mu + L - 1][m'].
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_theta_dft(FftTables<T> ft, int s,
+SHT_ROW_KERNEL(T, LOGM) void k_theta_dft(FftTables<T> ft, int s,
                                                            const typename CT<T>::type *__restrict__ Q,
                                                            typename CT<T>::type *__restrict__ F) {
     using C = typename CT<T>::type;
@@ -902,7 +922,7 @@ __global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const typ
 
 // Plan helper: forward DFT (natural order) of `rows` sequences of length M, in place, scaled.
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kMaxRowThreads) void k_fft_rows(FftTables<T> ft, typename CT<T>::type *data,
+SHT_ROW_KERNEL(T, LOGM) void k_fft_rows(FftTables<T> ft, typename CT<T>::type *data,
                                                           T scale) {
     using C = typename CT<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
