@@ -53,15 +53,6 @@ template <typename T, int LOGM> constexpr int row_waves() {
 #define SHT_ROW_KERNEL(T, LOGM) \
     __global__ __launch_bounds__(kMaxRowThreads) __attribute__((amdgpu_waves_per_eu(row_waves<T, LOGM>())))
 
-// Workgroups are dealt to the 8 XCDs round-robin; this maps workgroup i to
-// the work item it takes so that each XCD runs one contiguous range of items
-// in order (the tail n mod 8 keeps its own index).  Neighbouring items share
-// cache lines of the strided rows the theta stages read or write, and then
-// meet in one L2.
-__device__ __forceinline__ int xcd_item(int i, int n) {
-    const int per = n >> 3;
-    return i < (per << 3) ? (i & 7) * per + (i >> 3) : i;
-}
 
 // LDS slot of point i: one pad slot after every 16 points, so that the
 // stride-16 accesses of the Stockham passes spread over the banks.

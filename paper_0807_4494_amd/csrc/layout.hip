@@ -12,8 +12,10 @@
 // Both kernels transpose 32 x 32 (l, m) tiles through LDS so that the
 // coefficient rows (contiguous in m) and the panels (contiguous in l) are
 // both accessed with unit stride.  One launch covers every map of a call:
-// workgroup i takes map i / T and tile i mod T of the T tiles that meet the
-// triangle m <= l.  Each thread issues all its global loads before the first
+// work item i takes map i / T and tile i mod T of the T tiles that meet the
+// triangle m <= l, and each XCD runs a contiguous range of items, so that
+// the tiles that share the cache lines of a coefficient row (the rows start
+// at l^2 + l, not on a line) meet in one L2.  Each thread issues all its global loads before the first
 // use (indices clamped to a valid entry, the values selected afterwards), so
 // that a workgroup has its whole tile in flight at once.
 //
@@ -53,9 +55,9 @@ __global__ __launch_bounds__(256) void k_layout_in(int L, int ntri, SpinSegs sg,
                                                   const typename CT<T>::type *__restrict__ flm, T *__restrict__ P) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][l_local][m_local]
-    const int bg = (int)blockIdx.x / ntri;
+    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x), bg = item / ntri;
     int lt, mt;
-    tri_tile((int)blockIdx.x - bg * ntri, lt, mt);
+    tri_tile(item - bg * ntri, lt, mt);
     const int l0 = lt * TL, m0 = mt * TL;
     const SpinSeg g = find_seg(sg, bg);
     const int s = g.s, as = s < 0 ? -s : s, b = bg - g.b0, flip = g.flip;
@@ -109,9 +111,9 @@ __global__ __launch_bounds__(256) void k_layout_out(int L, int ntri, SpinSegs sg
                                                    typename CT<T>::type *__restrict__ flm) {
     using C = typename CT<T>::type;
     __shared__ T tile[4][TL][TL + 1];  // [q][m_local][l_local]
-    const int bg = (int)blockIdx.x / ntri;
+    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x), bg = item / ntri;
     int lt, mt;
-    tri_tile((int)blockIdx.x - bg * ntri, lt, mt);
+    tri_tile(item - bg * ntri, lt, mt);
     const int l0 = lt * TL, m0 = mt * TL;
     const SpinSeg g = find_seg(sg, bg);
     const int s = g.s, as = s < 0 ? -s : s, b = bg - g.b0, flip = g.flip;

@@ -148,6 +148,17 @@ hipError_t launch_spin_tables(const EdgeTable &E, const RecTables &rt, SpinPlan 
 hipError_t launch_rec_tables(int L, RecTables &rt, hipStream_t st);
 template <typename T> hipError_t launch_fft_tables(FftTables<T> &ft, FftTables<double> *src, hipStream_t st);
 
+// Workgroups are dealt to the 8 XCDs round-robin; this maps workgroup i to
+// the work item it takes so that each XCD runs one contiguous range of items
+// in order (the tail n mod 8 keeps its own index).  Neighbouring items share
+// cache lines (the strided rows the theta stages read or write, the rows of
+// unaligned coefficient blocks in the layout stages), and then meet in one
+// L2.
+__device__ __forceinline__ int xcd_item(int i, int n) {
+    const int per = n >> 3;
+    return i < (per << 3) ? (i & 7) * per + (i >> 3) : i;
+}
+
 // The spin segments of one call, as the layout and theta kernels see them:
 // segment k holds the caller's maps [b0, b0 + B) of spin s (their rings and
 // coefficient arrays follow those of the segments before), and those maps
