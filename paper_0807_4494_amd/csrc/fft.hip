@@ -217,6 +217,21 @@ template <typename C> struct IsLds<LdsLd<C>> : std::true_type {};
 template <typename C> struct IsLds<LdsSt<C>> : std::true_type {};
 template <int c> constexpr int padc = c + (c >> 4);
 
+// The twiddles w^{rk}, r = 1..15, of a radix-16 butterfly from the four
+// table values w^k, w^{2k}, w^{4k}, w^{8k} (t[0] is not set).
+template <typename C> __device__ __forceinline__ void radix16_twiddles(const C *w4, C *t) {
+    t[1] = w4[0];
+    t[2] = w4[1];
+    t[4] = w4[2];
+    t[8] = w4[3];
+    t[3] = cmul(t[1], t[2]);
+    t[5] = cmul(t[1], t[4]);
+    t[6] = cmul(t[2], t[4]);
+    t[7] = cmul(t[3], t[4]);
+#pragma unroll
+    for (int r = 9; r < 16; ++r) t[r] = cmul(t[r - 8], t[8]);
+}
+
 template <int R, int LOGM, int LOGNS, typename T, bool HIN, bool HOUT, typename Ld, typename Pre, typename St>
 __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, Ld ld, Pre pre, St st) {
     using C = typename CT<T>::type;
@@ -284,16 +299,7 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
             if constexpr (LOGNS > 0) {
                 if constexpr (!ALLW) {
                     C t[16];
-                    t[1] = w[q][0];
-                    t[2] = w[q][1];
-                    t[4] = w[q][2];
-                    t[8] = w[q][3];
-                    t[3] = cmul(t[1], t[2]);
-                    t[5] = cmul(t[1], t[4]);
-                    t[6] = cmul(t[2], t[4]);
-                    t[7] = cmul(t[3], t[4]);
-#pragma unroll
-                    for (int r = 9; r < 16; ++r) t[r] = cmul(t[r - 8], t[8]);
+                    radix16_twiddles(w[q], t);
 #pragma unroll
                     for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], t[r]);
                 } else {
@@ -319,8 +325,10 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
 // hands output k to st(k, X_k, pre(k)); intermediate passes live in buf
 // (LDS).  The first pass has radix 2^(LOGM mod 4) when LOGM is not a
 // multiple of 4, all others radix 16.  HIN: ld(n) is zero for n >= M/2 and is
-// not called there.  HOUT: st is called for k < M/2 only.
-template <int LOGM, int P, int LOGNS, typename T, bool HIN, bool HOUT, typename Ld, typename Pre, typename St>
+// not called there.  HOUT: st is called for k < M/2 only.  PSTOP: the last
+// pass run (earlier than the transform's last, it leaves its output in buf).
+template <int LOGM, int P, int LOGNS, typename T, bool HIN, bool HOUT, int PSTOP = fft_npass(LOGM) - 1,
+          typename Ld, typename Pre, typename St>
 __device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const typename CT<T>::type *ptw, Ld ld,
                                            Pre pre, St st) {
     using C = typename CT<T>::type;
@@ -336,7 +344,52 @@ __device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const type
     else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, ld, NoPre{}, sbuf);
     else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, lbuf, pre, st);
     else stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, lbuf, NoPre{}, sbuf);
-    if constexpr (!LAST) fft_passes<LOGM, P + 1, LOGNS + LR, T, HIN, HOUT>(buf, ptw, ld, pre, st);
+    if constexpr (P < PSTOP) fft_passes<LOGM, P + 1, LOGNS + LR, T, HIN, HOUT, PSTOP>(buf, ptw, ld, pre, st);
+}
+
+// Whether a convolution at M = 2^LOGM runs its spectrum product in registers
+// (spectrum_pass): M a power of 16 with one butterfly per thread and pass.
+template <int LOGM> constexpr bool fused_spectrum() {
+    return LOGM % 4 == 0 && LOGM >= 8 && (1 << (LOGM - 4)) == row_threads(1 << LOGM);
+}
+
+// The forward transform's last radix-16 pass, the product with the spectrum
+// H and the inverse transform's first pass, in registers.  With M = 16^n
+// points and nb = M/16 threads, thread j ends the forward transform holding
+// its outputs k = j + r nb (r < 16) and starts the inverse holding its inputs
+// n = j + r nb: the same points, so the product needs no round trip through
+// LDS.  The inverse is taken as conj(FFT(conj(.))), as in convolve.
+template <int LOGM, typename T>
+__device__ __forceinline__ void spectrum_pass(typename CT<T>::type *buf, const typename CT<T>::type *ptw,
+                                              const typename CT<T>::type *H) {
+    using C = typename CT<T>::type;
+    static_assert(fused_spectrum<LOGM>(), "M = 16^n, one butterfly per thread");
+    constexpr int nb = 1 << (LOGM - 4);  // = Ns of the forward's last pass
+    const int j = threadIdx.x;
+    const C *tp = ptw + fft_pass_offset(LOGM, fft_npass(LOGM) - 1) + j;
+    C v[16], h[16], w[4];
+    {
+        const C *p = buf + pad(j);
+        static_for<16>([&](auto rr) { v[rr.value] = p[padc<rr.value * nb>]; });
+    }
+    w[0] = tp[1 * nb];
+    w[1] = tp[2 * nb];
+    w[2] = tp[4 * nb];
+    w[3] = tp[8 * nb];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) h[r] = H[j + r * nb];
+    __syncthreads();
+    C t[16];
+    radix16_twiddles(w, t);
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], t[r]);
+    dft_r<16, C, T>(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = conj(cmul(v[r], h[r]));
+    dft_r<16, C, T>(v);
+    C *q = buf + pad(16 * j);
+    static_for<16>([&](auto rr) { q[padc<rr.value>] = v[rr.value]; });
+    __syncthreads();
 }
 
 template <int LOGM, typename T, typename Ld, typename St>
@@ -356,12 +409,20 @@ __device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typena
                                          const typename CT<T>::type *tw, Ld ld, Pre pre, St st) {
     using C = typename CT<T>::type;
     using A = decltype(pre(0));
-    fft_passes<LOGM, 0, 0, T, true, false>(
-        buf, tw, ld, [H](int k) { return H[k]; },
-        [buf](int k, C x, C hk) { buf[pad(k)] = conj(cmul(x, hk)); });
-    fft_passes<LOGM, 0, 0, T, false, true>(
-        buf, tw, LdsLd<C>{buf}, pre,
-        [&st](int k, C x, A a) { st(k, conj(x), a); });
+    if constexpr (fused_spectrum<LOGM>()) {
+        constexpr int NPASS = fft_npass(LOGM);
+        fft_passes<LOGM, 0, 0, T, true, false, NPASS - 2>(buf, tw, ld, NoPre{}, LdsSt<C>{buf});
+        spectrum_pass<LOGM, T>(buf, tw, H);
+        fft_passes<LOGM, 1, 4, T, false, true>(buf, tw, LdsLd<C>{buf}, pre,
+                                               [&st](int k, C x, A a) { st(k, conj(x), a); });
+    } else {
+        fft_passes<LOGM, 0, 0, T, true, false>(
+            buf, tw, ld, [H](int k) { return H[k]; },
+            [buf](int k, C x, C hk) { buf[pad(k)] = conj(cmul(x, hk)); });
+        fft_passes<LOGM, 0, 0, T, false, true>(
+            buf, tw, LdsLd<C>{buf}, pre,
+            [&st](int k, C x, A a) { st(k, conj(x), a); });
+    }
 }
 
 // The same convolution for rows whose M-point buffer does not fit in LDS,
