@@ -35,6 +35,17 @@ __host__ __device__ constexpr int row_threads(int M) {
 
 // Rows whose M-point buffer (with its pad slots) exceeds the LDS of a CU
 // (FP64 at M = 16384) run as two M/2-point halves (convolve_split below).
+//
+// Rows held whole also keep the twiddles of their transform's second pass in
+// LDS, after the padded buffer: that pass has Ns = 2^(LOGM mod 4) (16 when 4
+// divides LOGM) and every thread's k = j mod Ns is one of those few values,
+// so the whole table (16 Ns entries) is small; the convolutions copy it in
+// and the pass reads all fifteen w^{rk} instead of forming eleven of them.
+__host__ __device__ constexpr int ltw_entries(int logM, bool split) {
+    return split || logM < 8 ? 0 : 16 << fft_pass_lr(logM, 0);
+}
+// LDS slots of an M-point buffer with its pad slots (pad(i) = i + i/16)
+__host__ __device__ constexpr int padded_points(int logM) { return (1 << logM) + (1 << logM) / 16; }
 template <typename T, int LOGM> __host__ __device__ constexpr bool split_rows() {
     return rows_split(1 << LOGM, 2 * (int)sizeof(T));
 }
@@ -46,7 +57,7 @@ template <typename T, int LOGM> __host__ __device__ constexpr bool split_rows() 
 template <typename T, int LOGM> constexpr int row_waves() {
     constexpr int M = 1 << LOGM;
     constexpr int m = split_rows<T, LOGM>() ? M / 2 : M;
-    constexpr int lds = (m + m / 16) * 2 * (int)sizeof(T);
+    constexpr int lds = (m + m / 16 + ltw_entries(LOGM, split_rows<T, LOGM>())) * 2 * (int)sizeof(T);
     constexpr int w = (160 * 1024 / lds) * (row_threads(M) / 64) / 4;
     return w < 2 ? 2 : w > 4 ? 4 : w;
 }
@@ -232,7 +243,8 @@ template <typename C> __device__ __forceinline__ void radix16_twiddles(const C *
     for (int r = 9; r < 16; ++r) t[r] = cmul(t[r - 8], t[8]);
 }
 
-template <int R, int LOGM, int LOGNS, typename T, bool HIN, bool HOUT, typename Ld, typename Pre, typename St>
+template <int R, int LOGM, int LOGNS, typename T, bool HIN, bool HOUT, bool LW, typename Ld, typename Pre,
+          typename St>
 __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, Ld ld, Pre pre, St st) {
     using C = typename CT<T>::type;
     using A = decltype(pre(0));
@@ -250,10 +262,11 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
     constexpr int logNs = LOGNS;
     constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
     // w^{r k} sits at ptw[r Ns + k], so a wave's threads (consecutive k)
-    // read one contiguous run per r.  For radix 16 only w^{k}, w^{2k},
-    // w^{4k}, w^{8k} are loaded and the rest formed as products of at most
-    // four table values (loading all fifteen was slower, in FP32 too)
-    constexpr bool ALLW = R != 16;
+    // read one contiguous run per r.  For radix 16 from global memory only
+    // w^{k}, w^{2k}, w^{4k}, w^{8k} are loaded and the rest formed as products
+    // of at most four table values (loading all fifteen was slower, in FP32
+    // too); from the LDS copy (LW) all fifteen are read.
+    constexpr bool ALLW = R != 16 || LW;
     constexpr int Ns = 1 << LOGNS;
     constexpr int NW = LOGNS == 0 ? 1 : ALLW ? R : 4;
     static_assert(!HIN || LOGNS == 0, "zero upper half only on the first pass");
@@ -328,7 +341,7 @@ __device__ __forceinline__ void stockham_pass(const typename CT<T>::type *ptw, L
 // not called there.  HOUT: st is called for k < M/2 only.  PSTOP: the last
 // pass run (earlier than the transform's last, it leaves its output in buf).
 template <int LOGM, int P, int LOGNS, typename T, bool HIN, bool HOUT, int PSTOP = fft_npass(LOGM) - 1,
-          typename Ld, typename Pre, typename St>
+          bool LTW = false, typename Ld, typename Pre, typename St>
 __device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const typename CT<T>::type *ptw, Ld ld,
                                            Pre pre, St st) {
     using C = typename CT<T>::type;
@@ -337,14 +350,26 @@ __device__ __forceinline__ void fft_passes(typename CT<T>::type *buf, const type
     constexpr int RR = 1 << LR;
     constexpr bool FIRST = P == 0, LAST = P == NPASS - 1;
     constexpr bool PIN = HIN && FIRST, POUT = HOUT && LAST;
-    const C *tp = ptw + fft_pass_offset(LOGM, P);
+    // LTW: the second pass's twiddles from their copy in LDS (ltw_load)
+    constexpr bool LW = LTW && P == 1;
+    const C *tp = LW ? buf + padded_points(LOGM) : ptw + fft_pass_offset(LOGM, P);
     const LdsLd<C> lbuf{buf};
     const LdsSt<C> sbuf{buf};
-    if constexpr (FIRST && LAST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, ld, pre, st);
-    else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, ld, NoPre{}, sbuf);
-    else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, lbuf, pre, st);
-    else stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT>(tp, lbuf, NoPre{}, sbuf);
-    if constexpr (P < PSTOP) fft_passes<LOGM, P + 1, LOGNS + LR, T, HIN, HOUT, PSTOP>(buf, ptw, ld, pre, st);
+    if constexpr (FIRST && LAST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT, LW>(tp, ld, pre, st);
+    else if constexpr (FIRST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT, LW>(tp, ld, NoPre{}, sbuf);
+    else if constexpr (LAST) stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT, LW>(tp, lbuf, pre, st);
+    else stockham_pass<RR, LOGM, LOGNS, T, PIN, POUT, LW>(tp, lbuf, NoPre{}, sbuf);
+    if constexpr (P < PSTOP) fft_passes<LOGM, P + 1, LOGNS + LR, T, HIN, HOUT, PSTOP, LTW>(buf, ptw, ld, pre, st);
+}
+
+// Copies the second pass's twiddles into LDS after the padded M-point
+// buffer (rows held whole; ltw_entries).  Ordered before the second pass's
+// reads by the barriers of the first pass.
+template <int LOGM, typename T>
+__device__ __forceinline__ void ltw_load(typename CT<T>::type *buf, const typename CT<T>::type *ptw) {
+    typename CT<T>::type *dst = buf + padded_points(LOGM);
+    const typename CT<T>::type *src = ptw + fft_pass_offset(LOGM, 1);
+    for (int i = threadIdx.x; i < ltw_entries(LOGM, false); i += blockDim.x) dst[i] = src[i];
 }
 
 // Whether a convolution at M = 2^LOGM runs its spectrum product in registers
@@ -409,17 +434,19 @@ __device__ __forceinline__ void convolve(typename CT<T>::type *buf, const typena
                                          const typename CT<T>::type *tw, Ld ld, Pre pre, St st) {
     using C = typename CT<T>::type;
     using A = decltype(pre(0));
+    constexpr int NPASS = fft_npass(LOGM);
+    constexpr bool LTW = ltw_entries(LOGM, split_rows<T, LOGM>()) > 0;
+    if constexpr (LTW) ltw_load<LOGM, T>(buf, tw);
     if constexpr (fused_spectrum<LOGM>()) {
-        constexpr int NPASS = fft_npass(LOGM);
-        fft_passes<LOGM, 0, 0, T, true, false, NPASS - 2>(buf, tw, ld, NoPre{}, LdsSt<C>{buf});
+        fft_passes<LOGM, 0, 0, T, true, false, NPASS - 2, LTW>(buf, tw, ld, NoPre{}, LdsSt<C>{buf});
         spectrum_pass<LOGM, T>(buf, tw, H);
-        fft_passes<LOGM, 1, 4, T, false, true>(buf, tw, LdsLd<C>{buf}, pre,
-                                               [&st](int k, C x, A a) { st(k, conj(x), a); });
+        fft_passes<LOGM, 1, 4, T, false, true, NPASS - 1, LTW>(buf, tw, LdsLd<C>{buf}, pre,
+                                                                [&st](int k, C x, A a) { st(k, conj(x), a); });
     } else {
-        fft_passes<LOGM, 0, 0, T, true, false>(
+        fft_passes<LOGM, 0, 0, T, true, false, NPASS - 1, LTW>(
             buf, tw, ld, [H](int k) { return H[k]; },
             [buf](int k, C x, C hk) { buf[pad(k)] = conj(cmul(x, hk)); });
-        fft_passes<LOGM, 0, 0, T, false, true>(
+        fft_passes<LOGM, 0, 0, T, false, true, NPASS - 1, LTW>(
             buf, tw, LdsLd<C>{buf}, pre,
             [&st](int k, C x, A a) { st(k, conj(x), a); });
     }
@@ -989,8 +1016,9 @@ template <typename T> bool split_host(const FftTables<T> &ft) { return rows_spli
 // LDS of a row kernel: the M-point buffer with one pad slot per 16 points
 // (half of it for split rows).
 template <typename T> size_t lds_bytes(const FftTables<T> &ft) {
-    const size_t m = split_host(ft) ? (size_t)ft.M / 2 : (size_t)ft.M;
-    return (m + m / 16) * sizeof(typename CT<T>::type);
+    const bool split = split_host(ft);
+    const size_t m = split ? (size_t)ft.M / 2 : (size_t)ft.M;
+    return (m + m / 16 + (size_t)ltw_entries(ft.logM, split)) * sizeof(typename CT<T>::type);
 }
 
 // Launch shape of a row kernel over n items: one workgroup per item, or for
