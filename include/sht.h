@@ -115,9 +115,12 @@ int sht_forward(int L, int spin, int batch, int sampling, int precision,
  * same-L group): nseg segments, segment k holding batches[k] maps of spin
  * spins[k], stored one after another in flm and map (segment 0's maps first;
  * layouts per map as for sht_inverse / sht_forward).  The result of each map
- * is that of sht_inverse / sht_forward at its spin; the O(L^3) contraction of
- * every segment runs in one launch (its column blocks carry their segment's
- * spin factors) and the phi stages in one launch over all maps.
+ * is that of sht_inverse / sht_forward at its spin.  The layout, theta and
+ * phi stages run one launch each over all maps (the layout and theta kernels
+ * look up each map's segment); the O(L^3) contraction runs one launch per
+ * kernel it needs, its column blocks carrying their segment's spin factors
+ * (on the FP32 path the spin-0 segments take the kernel that skips the
+ * products Delta^l_{m',0}(pi/2) = 0 of odd l + m', the others one launch).
  *
  * Spin pairs.  A segment of spin -s that directly follows one of spin s != 0
  * (not itself so paired) shares that segment's contraction: at theta = pi/2,
