@@ -549,8 +549,9 @@ template <typename V> __device__ __forceinline__ V ldc(const V *p, int n, int N)
 
 // Inverse theta stage, two rows per block.  Row (b, mu): the Fourier
 // coefficients F_{mu m'}, m' >= 0, from the contraction output R[|mu|][c][m']
-// (c = q*B + b with q = 0,1 the real/imag part for mu >= 0 and q = 2,3 for
-// mu < 0), times (-1)^s i^{-(mu+s)} (and (-1)^{m'} for mu < 0); m' < 0 filled
+// (c = coff + q*B + b for map b of its spin segment, q = 0,1 the real/imag
+// part for mu >= 0 and q = 2,3 for mu < 0), times (-1)^s i^{-(mu+s)} (and
+// (-1)^{m'} for mu < 0); m' < 0 filled
 // with F_{mu,-m'} = sigma F_{mu m'}, sigma = (-1)^{mu+s} (Eq. (Ffourier_sym));
 // then g_mu(theta_t) = sum_{m'} F_{mu m'} e^{i m' theta_t}, t < L.
 // That symmetry makes g_mu even (sigma = 1) or odd (sigma = -1) under

@@ -1,7 +1,7 @@
 // Layout kernels between the caller's coefficient array flm[b][l*l + l + m]
 // and the order-major panels the contraction streams, [m >= 0][c][l] with
-// Cn columns per order, of which this launch's maps (one spin) own
-// c = coff + q*B + b:
+// Cn columns per order, of which map b of a segment of B maps (one spin,
+// columns from coff on) owns c = coff + q*B + b:
 //   q = 0, 1   Re, Im of f_{l, m}
 //   q = 2, 3   Re, Im of (-1)^l f_{l, -m}   (m > 0; zero for m = 0)
 // The (-1)^l factor realises d^l_{m',-m} = (-1)^{l+m'} d^l_{m'm}
