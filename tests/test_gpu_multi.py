@@ -96,3 +96,32 @@ def test_multi_spin_call_equals_single_spin_calls(L, spins, batches, prec):
         assert oracle.rel_l2(ref, maps[sl].cpu().numpy()) < TOL[prec]
         assert oracle.rel_l2(flm[sl], back[sl].cpu().numpy()) < TOL[prec]
         off += n
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_every_stage_is_one_traced_step_per_call(prec):
+    """A multi-spin call runs each of its eight stages once over all its
+    maps (the layout and theta kernels look up each map's segment), however
+    many segments it has; the trace counts one entry per stage and call."""
+    sht = _sht()
+    dev = torch.device("cuda", 0)
+    L, spins, batches = 72, [0, 2, -2, 1, 3], [2, 1, 1, 2, 1]
+    B = sum(batches)
+    x = torch.from_numpy(np.stack([sht_synth.gaussian_flm(L, s, 600 + 17 * k + b)
+                                   for k, s in enumerate(spins) for b in range(batches[k])]))
+    x = x.to(dev, sht.io_dtype(prec))
+    sht.inverse_multi(x, L, spins, batches, prec)   # plans built outside the traced calls
+    torch.cuda.synchronize()
+    sht.trace_enable(True)
+    try:
+        sht.trace_read()
+        fmap = sht.inverse_multi(x, L, spins, batches, prec)
+        back = sht.forward_multi(fmap, L, spins, batches, prec)
+        torch.cuda.synchronize()
+        counts = {name: n for name, (_, n) in sht.trace_read().items()}
+    finally:
+        sht.trace_enable(False)
+    assert set(counts.values()) == {1}, counts
+    err = float(torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x))
+    assert err <= TOL[prec], err
+    assert B == back.shape[0]
