@@ -125,3 +125,31 @@ def test_every_stage_is_one_traced_step_per_call(prec):
     err = float(torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x))
     assert err <= TOL[prec], err
     assert B == back.shape[0]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_paired_spins_at_L2048(prec):
+    """The spin pair (2, -2) at the largest configured band-limit: the paired
+    call (FP32: one 128-column tile for both spins, FFT rows of 8192 points)
+    agrees with the single-spin calls to rounding, and its round trip returns
+    the coefficients.  The rounding bar is the file's (set for L <= 260)
+    scaled by sqrt(L / 256): the contraction sums L terms, whose rounding
+    errors add like a random walk."""
+    sht = _sht()
+    dev = torch.device("cuda", 0)
+    L, spins, batches = 2048, [2, -2], [4, 4]
+    print(f"[multi] L={L} spins={spins} batches={batches} {prec}", flush=True)
+    x = torch.from_numpy(np.stack([sht_synth.gaussian_flm(L, s, 700 + 11 * k + b, "inv_lp1_sq")
+                                   for k, s in enumerate(spins) for b in range(batches[k])]))
+    x = x.to(dev, sht.io_dtype(prec))
+    maps = sht.inverse_multi(x, L, spins, batches, prec)
+    back = sht.forward_multi(maps, L, spins, batches, prec)
+    bar = ROUNDING[prec] * (L / 256) ** 0.5
+    for k, s in enumerate(spins):
+        sl = slice(4 * k, 4 * k + 4)
+        m1 = sht.inverse(x[sl], L, s, prec)
+        f1 = sht.forward(maps[sl], L, s, prec)
+        assert _rel(maps[sl], m1) <= bar, (s, "inverse", _rel(maps[sl], m1))
+        assert _rel(back[sl], f1) <= bar, (s, "forward", _rel(back[sl], f1))
+    err = float(torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x))
+    assert err <= TOL[prec], err
