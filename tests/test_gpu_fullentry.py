@@ -1,4 +1,5 @@
-"""GPU parity over every output entry at L = 512 and at L = 1024.
+"""GPU parity over every output entry at L = 512 and at L = 1024 (and at an
+odd L of the same 4096-point FFT range, L = 777).
 
 The sampled full-size tests compare a few hundred pixels and a few orders;
 here every entry of chosen maps is compared with the oracle, which takes about
@@ -186,3 +187,28 @@ def test_forward_every_entry_benchmark_call(s, prec):
     err = _rel(ref, got)
     print(f"[full entries] rel l2 {err:.3e}", flush=True)
     assert err <= TOL[prec], (s, prec, err)
+
+
+# ---- odd L in the 4096-point FFT range (the last theta block of a map holds one row) ----
+
+L_ODD, S_ODD = 777, -3
+
+
+@functools.lru_cache(maxsize=1)
+def _odd_inputs():
+    flm = sht_synth.gaussian_flm(L_ODD, S_ODD, SEED_MID + 500)
+    fmap = sht_synth.random_complex_map(L_ODD, SEED_MID + 501)
+    return flm, fmap, oracle.inverse(flm, L_ODD, S_ODD), oracle.forward(fmap, L_ODD, S_ODD)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_every_entry_odd_L(prec):
+    sht, dev = _sht(), _dev()
+    print(f"[full entries] L={L_ODD} s={S_ODD} {prec}", flush=True)
+    flm, fmap, ref_map, ref_flm = _odd_inputs()
+    got_map = sht.inverse(torch.from_numpy(flm[None]).to(dev, sht.io_dtype(prec)), L_ODD, S_ODD, prec)
+    got_flm = sht.forward(torch.from_numpy(fmap[None]).to(dev, sht.io_dtype(prec)), L_ODD, S_ODD, prec)
+    err_i = _rel(ref_map, got_map[0].cpu().numpy().astype(np.complex128))
+    err_f = _rel(ref_flm, got_flm[0].cpu().numpy().astype(np.complex128))
+    assert err_i <= TOL[prec], err_i
+    assert err_f <= TOL[prec], err_f
