@@ -150,15 +150,17 @@ L_MAX = 4096
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_low_degree_content_at_the_largest_band_limit(prec):
-    """A map with harmonics of degree <= 6 only, synthesised at L = 4096:
-    sampled pixels equal the direct sum of Eq. (ssh_wigner) harmonics (Wigner
-    sum in 40-digit arithmetic), and the forward returns the coefficients."""
+@pytest.mark.parametrize("L", [1537, L_MAX])
+def test_low_degree_content_at_large_band_limits(L, prec):
+    """A map with harmonics of degree <= 6 only, synthesised at L = 4096 and
+    at an odd L of the 8192-point FFT range: sampled pixels equal the direct
+    sum of Eq. (ssh_wigner) harmonics (Wigner sum in 40-digit arithmetic),
+    and the forward returns the coefficients."""
     from closed_forms import sylm_wigner
     sht = _sht()
     dev = _dev()
-    L, s, lmax = L_MAX, 2, 6
-    print(f"[L=4096 low degree] s={s} {prec}", flush=True)
+    s, lmax = 2, 6
+    print(f"[L={L} low degree] s={s} {prec}", flush=True)
     rng = np.random.Generator(np.random.PCG64(sht_synth.SEED_BASE + 9400))
     flm = np.zeros(L * L, complex)
     terms = [(l, m) for l in range(abs(s), lmax + 1) for m in range(-l, l + 1)]
