@@ -44,7 +44,8 @@ def rel(ref, got):
 
 
 CASES = [(1, 0, 1), (2, 0, 1), (2, 1, 2), (3, -2, 1), (5, 1, 3), (8, 0, 2), (8, -3, 1), (16, 2, 1),
-         (32, 0, 1), (33, -1, 2), (64, 2, 1), (100, -2, 3), (129, 0, 1), (256, 2, 1), (257, -1, 2),
+         (32, 0, 1), (33, -1, 2), (64, 2, 1), (100, -2, 3), (101, 3, 2), (129, 0, 1), (256, 2, 1),
+         (257, -1, 2),
          # whole column tiles (4B = 16, 64, and 64 + a partial tile): the
          # contraction's full-slab load path
          (96, 1, 4), (160, -2, 16), (200, 0, 20)]
